@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Throughput of the 4PCF hot path on one MI355X.
+
+Workload: 4PCF, lmax = 5, 10 linear radial bins over [20, 160] Mpc/h, on a
+synthetic data-minus-randoms catalog -- 200,000 Neyman-Scott clustered points
+plus 600,000 uniform randoms weighted -N_D/N_R -- in a periodic 1000 Mpc/h box:
+800,000 primaries, ~13,700 neighbours each.
+
+One step = the whole hot path on device-resident inputs: cell-grid build (with
+the D-R weighting) + harmonic-coefficient gather + coupling + FP64 sum over
+primaries + contraction to zeta, ending with zeta on the host.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "4PCF primaries/s (ℓmax=5, 10 bins) vs plain FP64 path; p50/p99 job latency"
+PEAK_ALU_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, non-packed VALU (FP32 or FP64)
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def gather_flops_per_pair(L):
+    """Algorithmic flops of one accepted pair in the gather (counted from the method):
+    separation + r^2 in FP64 (8), unit vector (r^2, rsqrt, 3 mul: 9), (x+iy)^m for
+    m = 2..L (6 per complex product), Legendre recurrence (3 per entry with l >= m+2,
+    plus z*w), accumulation of w Y (1 per m = 0 entry, 4 per complex entry)."""
+    f = 8 + 9 + 6 * max(L - 1, 0) + 1
+    f += 3 * sum(max(L - m - 1, 0) for m in range(L + 1))
+    f += (L + 1) + 4 * sum(L - m + 1 for m in range(1, L + 1))
+    return f
+
+
+def cpu_baseline(cfg, target_s):
+    """The FP64 oracle on the host cores, over a seeded sample of primaries (all
+    800k points stay secondaries)."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    w = oracle.dmr_weights(cfg["w"][:cfg["n_data"]], cfg["w"][cfg["n_data"]:])
+    n = len(w)
+    rng = np.random.default_rng(99)
+    cores = os.cpu_count() or 1
+    probe = rng.choice(n, 8 * cores, replace=False)
+    t0 = time.perf_counter()
+    oracle.zeta(cfg["pos"], w, 4, 5, cfg["edges"], box=cfg["box"], primaries=probe, nthreads=cores)
+    dt = time.perf_counter() - t0
+    k = int(min(20000, max(len(probe), target_s * len(probe) / max(dt, 1e-3))))
+    sample = rng.choice(n, k, replace=False)
+    log("cpu baseline: oracle over %d sampled primaries on %d threads" % (k, cores))
+    t0 = time.perf_counter()
+    oracle.zeta(cfg["pos"], w, 4, 5, cfg["edges"], box=cfg["box"], primaries=sample, nthreads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": k / dt, "unit": "primaries/s", "cores": cores, "kind": "oracle",
+            "sample": "%d seeded primaries of the 800k-point catalog, all 800k points as "
+                      "secondaries, FP64 C oracle (full M sum), %.1f s" % (k, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(primaries would shard across GPUs with one FP64 all-reduce of zeta).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2105_08722_amd import encore, synth
+
+    log("generating the synthetic catalog")
+    cfg = synth.config(2)
+    n = len(cfg["w"])
+    N, L, edges = 4, 5, cfg["edges"]
+    dev = torch.device("cuda:0")
+    tp = torch.from_numpy(cfg["pos"]).to(dev)
+    tw = torch.from_numpy(cfg["w"]).to(dev)
+    torch.cuda.synchronize()
+    ctx = encore.Context(0)
+
+    def step(prec):
+        g = encore.build_grid_device(ctx, tp, tw, r_max=edges[-1], box=cfg["box"], n_data=cfg["n_data"])
+        z = encore.npcf(ctx, g, N, L, edges, precision=prec)
+        g.free()
+        return z, ctx.last_timings()
+
+    for i in range(args.warmup):
+        step(args.precision)
+        log("warmup %d/%d done" % (i + 1, args.warmup))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gather_ms = couple_ms = 0.0
+    pairs = 0
+    z = None
+    for i in range(args.steps):
+        z, tm = step(args.precision)
+        gather_ms += tm["gather_ms"]
+        couple_ms += tm["couple_ms"]
+        pairs = tm["pairs"]
+        log("step %d/%d: %.1f ms (gather %.1f, couple %.1f)" % (i + 1, args.steps, tm["total_ms"],
+                                                               tm["gather_ms"], tm["couple_ms"]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = n / (ms / 1e3)
+    g_ms = gather_ms / args.steps
+    c_ms = couple_ms / args.steps
+    flops = gather_flops_per_pair(L) * pairs
+    achieved = flops / (g_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None,
+                "kernel": "k_gather<float,5,5> (harmonic-coefficient gather)",
+                "launch_ms": g_ms, "pairs_per_launch": pairs,
+                "flops_per_pair": gather_flops_per_pair(L)}
+
+    extra = {}
+    if not args.no_fp64 and args.precision != "fp64":
+        log("plain FP64 path, one step")
+        step("fp64")
+        t2 = time.perf_counter()
+        z64, tm64 = step("fp64")
+        t3 = time.perf_counter()
+        num = np.linalg.norm(z - z64, axis=1)
+        den = np.linalg.norm(z64, axis=1)
+        keep = den > 0
+        extra["fp64_path"] = {"value": n / (t3 - t2), "unit": "primaries/s", "ms_per_step": (t3 - t2) * 1e3,
+                              "gather_ms": tm64["gather_ms"], "couple_ms": tm64["couple_ms"]}
+        extra["speedup_vs_fp64_path"] = extra["fp64_path"]["ms_per_step"] / ms
+        extra["accuracy_vs_fp64_path"] = {"max_e_lambda": float(np.max(num[keep] / den[keep])),
+                                          "median_e_lambda": float(np.median(num[keep] / den[keep]))}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, args.cpu_seconds)
+    ctx.close()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "primaries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "4PCF lmax=5, 10 bins [20,160] Mpc/h, Neyman-Scott 200k data + "
+                               "600k uniform randoms (D-R), periodic 1000 Mpc/h box",
+                   "N": N, "lmax": L, "nbins": 10, "primaries": n, "precision": args.precision,
+                   "gather_ms": g_ms, "couple_ms": c_ms, "pairs": pairs},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * encore.h -- C ABI of the MI355X (gfx950) N-point correlation function hot path.
+ *
+ * The library computes the multiplets of the discrete isotropic NPCF estimator of
+ * Philcox, Slepian, Hou, Warner, Cahn & Eisenstein (2021), Section 3.2.1 (eq.
+ * NPCF-mult-discrete-binned-estimator with the harmonic coefficients of eq.
+ * binned-discrete-alm), for N = 3..6:
+ *
+ *   Z^B_L = sum_i w_i sum_M E(L) C^L_M prod_{k=1}^{N-1} a~^{b_k}_{l_k m_k}(i),
+ *   a~^b_lm(i) = sum_{j != i} w_j Y_lm((r_j - s_i)^) Theta^b(|r_j - s_i|),
+ *
+ * with L a multiplet (Section 2.1), B = (b_1 < ... < b_{N-1}) distinct radial bins
+ * (Section 3.2.1), C^L_M the coupling of eq. basis-coupling.  By default Z is raw
+ * (no 1/V, no 1/v_b); ENCORE_NORMALIZE divides by V prod_k v_{b_k}.
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns an int status: ENCORE_OK (0) or a negative code.  No
+ *    C++ exception crosses the ABI.  encore_last_error() returns a message for the
+ *    last failure on the calling thread.
+ *  - The caller owns every buffer it passes (host or device); the library owns
+ *    the handles it returns (free them with the matching destroy/free call).
+ *  - Outputs are written only on success.
+ *  - Positions are FP64, row-major [n][3]; weights FP64 [n].
+ *  - A radial bin b holds pairs with edges[b]^2 <= r^2 < edges[b+1]^2, r^2 formed
+ *    in FP64 as (dx*dx + dy*dy) + dz*dz; edges[0] > 0 excludes the self pair.
+ *  - Periodic boxes use the minimum image; they need 0 <= x < box and
+ *    edges[nbins] <= box/2 on every axis.
+ *  - Output layout: multiplet-major, zeta[l_index * n_bin_tuples + b_index].
+ *    Multiplets are ordered lexicographically over (l1, l2, (l12), l3, (l123), l4,
+ *    l5) with the last entry fastest; bin tuples lexicographically with the last
+ *    bin fastest.  Parity-even multiplets report Re Z, parity-odd ones Im Z
+ *    (Section 3.1: even multiplets are real, odd ones imaginary).
+ */
+#ifndef ENCORE_H
+#define ENCORE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define ENCORE_OK            0
+#define ENCORE_EINVAL       -1   /* bad argument (message says which) */
+#define ENCORE_ESIZE        -2   /* output buffer too small (message gives the size) */
+#define ENCORE_ENOMEM       -3   /* device or host allocation failed */
+#define ENCORE_EDEVICE      -4   /* HIP runtime error */
+#define ENCORE_EUNSUPPORTED -5   /* combination not built */
+
+/* flags */
+#define ENCORE_PERIODIC        0x1u   /* periodic box (minimum image), box[] required */
+#define ENCORE_ALLPARITY       0x2u   /* odd-parity multiplets too (Section 3.1) */
+#define ENCORE_DMR             0x4u   /* data-minus-randoms weighting, see build_grid */
+#define ENCORE_NORMALIZE       0x8u   /* zeta = Z / (V prod_k v_{b_k}) */
+#define ENCORE_PREC_FP64       0x00u  /* plain path: FP64 everywhere */
+#define ENCORE_PREC_FP32       0x10u  /* FP32 a_lm and products, FP64 sum over primaries */
+#define ENCORE_PREC_SPLITBF16  0x20u  /* FP32 a_lm, split-bf16 MFMA coupling */
+#define ENCORE_PREC_MASK       0x30u
+#define ENCORE_DEBUG_FULLGRID  0x100u /* encore_debug_alm: gather every point as in encore_npcf */
+
+typedef struct encore_ctx encore_ctx;   /* device, stream, table and workspace cache */
+typedef struct encore_grid encore_grid; /* device-resident cell-sorted catalog */
+
+/* Message for the last failing call on this thread ("" if none).  Owned by the
+ * library, valid until the next call on this thread. */
+const char* encore_last_error(void);
+
+/* Library version string (static). */
+const char* encore_version(void);
+
+/* Create a context on HIP device `hip_device` (>= 0).  *out receives the handle.
+ * Errors: EINVAL (bad device or NULL out), EDEVICE. */
+int encore_create(int hip_device, encore_ctx** out);
+
+/* Destroy a context.  Every grid built on it must be freed first.  NULL is a no-op. */
+int encore_destroy(encore_ctx* ctx);
+
+/*
+ * Build the device-resident cell grid of one catalog (Section 4.1: particles are
+ * placed on a Cartesian grid for the neighbour search).
+ *
+ *  pos    [n][3] FP64 positions, host memory.
+ *  w      [n] FP64 weights, host memory.
+ *  n      number of points (>= 1).
+ *  n_data with ENCORE_DMR: points [0, n_data) are data, [n_data, n) randoms with
+ *         positive input weights; the library replaces the random weights by
+ *         -w_R * sum(w_D) / sum(w_R) on the device in FP64, so the total weight is
+ *         zero (Section 4.2, data-minus-randoms field).  Ignored without ENCORE_DMR.
+ *  box    [3] periodic box side lengths (required with ENCORE_PERIODIC, else ignored).
+ *  r_max  largest separation any later encore_npcf call on this grid will bin
+ *         (> 0; sets the cell size).
+ *  flags  ENCORE_PERIODIC, ENCORE_DMR.
+ *  stream hipStream_t to order the work on (NULL: the context's stream).  The call
+ *         returns after the grid is built.
+ *  out    receives the grid handle.
+ * Errors: EINVAL (non-finite input, n < 1, point outside a periodic box, bad
+ * n_data, zero data or random weight sum), ENOMEM, EDEVICE.
+ */
+int encore_build_grid(encore_ctx* ctx, const double* pos, const double* w, int64_t n,
+                      int64_t n_data, const double* box, double r_max, uint32_t flags,
+                      void* stream, encore_grid** out);
+
+/* As encore_build_grid, but pos and w are device pointers (e.g. torch data_ptr())
+ * on the context's device; they are read, not adopted. */
+int encore_build_grid_device(encore_ctx* ctx, const double* pos, const double* w, int64_t n,
+                             int64_t n_data, const double* box, double r_max, uint32_t flags,
+                             void* stream, encore_grid** out);
+
+/* Free a grid (NULL is a no-op). */
+int encore_free_grid(encore_grid* grid);
+
+/* Number of points of a grid (>= 0), or a negative status. */
+int64_t encore_grid_size(const encore_grid* grid);
+
+/*
+ * NPCF multiplets of a grid's catalog (eq. NPCF-mult-discrete-binned-estimator).
+ *
+ *  npcf    N, 3..6.
+ *  lmax    largest principal ell, 0..10 (N = 3, 4), 0..5 (N = 5), 0..4 (N = 6).
+ *  nbins   number of radial bins (1..16); nbins < N-1 gives zero bin tuples.
+ *  edges   [nbins+1] host FP64, strictly increasing, edges[0] > 0,
+ *          edges[nbins] <= r_max of the grid.
+ *  flags   ENCORE_ALLPARITY, ENCORE_NORMALIZE, one ENCORE_PREC_* value.
+ *  volume  V for ENCORE_NORMALIZE (<= 0: the periodic box volume); else ignored.
+ *  zeta    host FP64 output [n_multiplets * n_bin_tuples].
+ *  zeta_len length of zeta in elements; ESIZE (with the needed length in the
+ *          message) if too small.
+ *  primary_subset  NULL: every point is a primary.  Otherwise [n_subset] indices
+ *          into the catalog (input order) of the primaries to sum over (the sum over
+ *          i restricted; secondaries are always the whole catalog).
+ *  stream  hipStream_t (NULL: the context's stream).  Synchronous: returns once zeta
+ *          is on the host.
+ * Errors: EINVAL, ESIZE, ENOMEM, EDEVICE, EUNSUPPORTED (precision/N/lmax not built).
+ */
+int encore_npcf(encore_ctx* ctx, const encore_grid* grid, int npcf, int lmax, int nbins,
+                const double* edges, uint32_t flags, double volume, double* zeta,
+                size_t zeta_len, const int64_t* primary_subset, int64_t n_subset,
+                void* stream);
+
+/* One-shot form: build a grid from host arrays, run encore_npcf, free the grid.
+ * r_max = edges[nbins]; box may be NULL for a non-periodic catalog. */
+int encore_npcf_simple(const double* pos, const double* w, int64_t n, int npcf, int lmax,
+                       int nbins, const double* edges, const double* box, uint32_t flags,
+                       double* zeta, size_t zeta_len);
+
+/* |multiplets| for (N, lmax, flags & ENCORE_ALLPARITY), or a negative status. */
+int64_t encore_num_multiplets(int npcf, int lmax, uint32_t flags);
+
+/* |bin tuples| = C(nbins, N-1), or a negative status. */
+int64_t encore_num_bin_tuples(int npcf, int nbins);
+
+/* Multiplet table in output order: out[k * width + c], width = 2N-5 for N >= 4
+ * ((l1, l2, l12, l3, l123, l4, l5) truncated to N), width 2 for N = 3.
+ * out_len in elements; ESIZE if too small. */
+int encore_multiplet_table(int npcf, int lmax, uint32_t flags, int32_t* out, size_t out_len);
+
+/*
+ * The coupling terms the device path sums (Appendix B half sum): for every
+ * multiplet and every M with m_{N-1} >= 0 and C^L_M != 0,
+ *   coef = 2 S(m_{N-1}) E(L) C^L_M,  S(0) = 1/2, S(m > 0) = 1,
+ * applied to Re (even L) or Im (odd L) of prod_k a~^{b_k}_{l_k m_k}.
+ * With out arrays NULL, only *n_terms is written.  Otherwise (capacity cap):
+ *   lam[t], l[t*(N-1)+k], m[t*(N-1)+k], coef[t].
+ * Host-only (no device needed).
+ */
+int encore_coupling_terms(int npcf, int lmax, uint32_t flags, int64_t* n_terms, int64_t cap,
+                          int32_t* lam, int32_t* l, int32_t* m, double* coef);
+
+/* Wigner 3j symbol (j1 j2 j3; m1 m2 m3) as the library's host tables use it. */
+double encore_wigner3j(int j1, int j2, int j3, int m1, int m2, int m3);
+
+/*
+ * Raw harmonic coefficients a~^b_lm (eq. binned-discrete-alm without 1/v_b) of k
+ * primaries, computed by the device gather kernel of the given precision.
+ * With ENCORE_DEBUG_FULLGRID the gather runs over every point of the catalog in
+ * the launch configuration encore_npcf uses (one launch), and the requested
+ * primaries' rows are returned.
+ *  primaries [k] catalog indices (input order).
+ *  alm_out   host FP64 [k][nbins][(lmax+1)(lmax+2)/2][2] (re, im), m >= 0 only,
+ *            index l(l+1)/2 + m.
+ */
+int encore_debug_alm(encore_ctx* ctx, const encore_grid* grid, int lmax, int nbins,
+                     const double* edges, uint32_t flags, const int64_t* primaries, int64_t k,
+                     double* alm_out);
+
+/* Timings (milliseconds, HIP events on the work stream) of the last encore_npcf
+ * call on this context: [0] total, [1] gather, [2] coupling, [3] reduce/contract,
+ * [4] number of gather launches, [5] number of accepted (primary, secondary) pairs.
+ * out_len >= 6. */
+int encore_last_timings(const encore_ctx* ctx, double* out, size_t out_len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ENCORE_H */

@@ -1,0 +1,156 @@
+// Coupling step (eq. NPCF-mult-discrete-binned-estimator with the Appendix B half
+// sum), reassociated so that the sum over primaries comes first:
+//
+//   T[t][B]  = sum_i w_i Q_t[ prod_k a~^{b_k}_{l_k m_k}(i) ]          (k_couple)
+//   Z[L][B]  = sum_{terms (L, t)} 2 S(m_{N-1}) E(L) C^L_M  T[t][B]      (k_contract)
+//
+// t runs over the distinct (l_k, m_k)_k tuples with m_{N-1} >= 0 that carry a
+// nonzero coupling; Q_t is Re for parity-even and Im for parity-odd tuples.  The
+// identity is exact in real arithmetic (the coupling does not depend on i).
+// a~ for m < 0 comes from a~_{l,-m} = (-1)^m conj(a~_{l,m}) (Appendix B).
+//
+// k_couple: one thread per (t, B) output, FP64 accumulator; the block stages a tile
+// of primaries' coefficients in LDS and every thread walks the tile.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace encore {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxK = 5;
+
+template <typename T> struct C2;
+template <> struct C2<float> { using type = float2; };
+template <> struct C2<double> { using type = double2; };
+
+template <typename T, int NK>
+__global__ void __launch_bounds__(kBlock) k_couple(CoupleArgs a, int ptile, int chunk)
+{
+    using V = typename C2<T>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    V* tile = reinterpret_cast<V*>(smem);
+    const int per = a.nbins * a.nlm;                       // complex values per primary
+    double* wtile = reinterpret_cast<double*>(smem + sizeof(V) * (size_t)ptile * per);
+
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = gid < (int64_t)a.ntuple * a.nB;
+    const int t = valid ? (int)(gid / a.nB) : 0;
+    const int b = valid ? (int)(gid - (int64_t)t * a.nB) : 0;
+    const int split = blockIdx.y;
+    const int p_lo = split * chunk;
+    const int p_hi = min(a.nprim, p_lo + chunk);
+
+    int off[NK];
+    T cs[NK];
+    int flags = 0;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) { off[k] = 0; cs[k] = (T)1; }
+    if (valid) {
+        flags = a.tuple_flags[t];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            off[k] = a.btab[b * a.nk + k] * a.nlm + a.tuple_off[t * a.nk + k];
+            cs[k] = ((flags >> k) & 1) ? (T)-1 : (T)1;
+        }
+    }
+    const bool take_im = (flags >> 16) & 1;
+    double acc = 0.0;
+
+    for (int p0 = p_lo; p0 < p_hi; p0 += ptile) {
+        const int np = min(ptile, p_hi - p0);
+        __syncthreads();
+        const V* src = reinterpret_cast<const V*>(a.alm) + (size_t)p0 * per;
+        for (int q = threadIdx.x; q < np * per; q += kBlock) tile[q] = src[q];
+        for (int q = threadIdx.x; q < np; q += kBlock) wtile[q] = a.P[a.prim[p0 + q]].w;
+        __syncthreads();
+        if (valid) {
+            for (int pp = 0; pp < np; ++pp) {
+                const V* ap = tile + pp * per;
+                V v = ap[off[0]];
+                T pr = v.x, pi = cs[0] * v.y;
+#pragma unroll
+                for (int k = 1; k < NK; ++k) {
+                    const V u = ap[off[k]];
+                    const T ur = u.x, ui = cs[k] * u.y;
+                    const T nr = pr * ur - pi * ui;
+                    const T ni = pr * ui + pi * ur;
+                    pr = nr; pi = ni;
+                }
+                const T q = take_im ? pi : pr;
+                acc += wtile[pp] * (double)q;
+            }
+        }
+    }
+    if (valid) {
+        if ((flags >> 8) & 1) acc = -acc;
+        double* dst = a.T + ((size_t)split * a.ntuple + t) * a.nB + b;
+        *dst += acc;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_contract(ContractArgs a)
+{
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (gid >= (int64_t)a.nlam * a.nB) return;
+    const int l = (int)(gid / a.nB);
+    const int b = (int)(gid - (int64_t)l * a.nB);
+    double z = 0.0;
+    for (int q = a.term_start[l]; q < a.term_start[l + 1]; ++q) {
+        const int t = a.term_tuple[q];
+        double s = 0.0;
+        for (int sp = 0; sp < a.nsplit; ++sp) s += a.T[((size_t)sp * a.ntuple + t) * a.nB + b];
+        z += a.term_coef[q] * s;
+    }
+    if (a.bscale) z *= a.bscale[b];
+    a.zeta[gid] = z;
+}
+
+}  // namespace
+
+int couple_ptile(int nbins, int nlm, int precision)
+{
+    const int per = nbins * nlm * (precision == 0 ? 16 : 8) + 8;
+    int pt = 32768 / per;
+    return pt < 1 ? 1 : (pt > 64 ? 64 : pt);
+}
+
+int launch_couple(const CoupleArgs& a, int precision, hipStream_t stream)
+{
+    if (a.nk > kMaxK) return (int)hipErrorInvalidValue;
+    const int64_t nthreads = (int64_t)a.ntuple * a.nB;
+    const int64_t nblk = (nthreads + kBlock - 1) / kBlock;
+    if (nblk == 0 || a.nprim == 0) return (int)hipSuccess;
+    const int ptile = couple_ptile(a.nbins, a.nlm, precision);
+    const int chunk = (a.nprim + a.nsplit - 1) / a.nsplit;
+    const size_t lds = (size_t)ptile * a.nbins * a.nlm * (precision == 0 ? 16 : 8) + 8 * (size_t)ptile;
+    dim3 grid((unsigned)nblk, (unsigned)a.nsplit);
+#define ENCORE_COUPLE_CASE(NKV)                                                      \
+    case NKV:                                                                        \
+        if (precision == 0)                                                          \
+            k_couple<double, NKV><<<grid, kBlock, lds, stream>>>(a, ptile, chunk);   \
+        else                                                                         \
+            k_couple<float, NKV><<<grid, kBlock, lds, stream>>>(a, ptile, chunk);    \
+        break;
+    switch (a.nk) {
+        ENCORE_COUPLE_CASE(2)
+        ENCORE_COUPLE_CASE(3)
+        ENCORE_COUPLE_CASE(4)
+        ENCORE_COUPLE_CASE(5)
+    default: return (int)hipErrorInvalidValue;
+    }
+#undef ENCORE_COUPLE_CASE
+    return (int)hipGetLastError();
+}
+
+int launch_contract(const ContractArgs& a, hipStream_t stream)
+{
+    const int64_t n = (int64_t)a.nlam * a.nB;
+    if (n == 0) return (int)hipSuccess;
+    k_contract<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, stream>>>(a);
+    return (int)hipGetLastError();
+}
+
+}  // namespace encore

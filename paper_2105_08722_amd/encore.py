@@ -1,0 +1,282 @@
+"""ctypes binding of libencore (include/encore.h): argument marshalling only.
+
+Every step of the estimator runs in the HIP library; this module converts numpy /
+torch arrays to pointers and status codes to exceptions.  If the shared library is
+missing, importing the binding fails loudly (there is no CPU fallback).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libencore.so")
+
+OK = 0
+EINVAL = -1
+ESIZE = -2
+ENOMEM = -3
+EDEVICE = -4
+EUNSUPPORTED = -5
+
+PERIODIC = 0x1
+ALLPARITY = 0x2
+DMR = 0x4
+NORMALIZE = 0x8
+PREC_FP64 = 0x00
+PREC_FP32 = 0x10
+PREC_SPLITBF16 = 0x20
+PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "splitbf16": PREC_SPLITBF16}
+DEBUG_FULLGRID = 0x100
+
+# every symbol include/encore.h declares, with (restype, argtypes)
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+_U32 = ctypes.c_uint32
+_D = ctypes.c_double
+_SZ = ctypes.c_size_t
+SIGNATURES = {
+    "encore_last_error": (ctypes.c_char_p, []),
+    "encore_version": (ctypes.c_char_p, []),
+    "encore_create": (_I, [_I, ctypes.POINTER(_P)]),
+    "encore_destroy": (_I, [_P]),
+    "encore_build_grid": (_I, [_P, _P, _P, _I64, _I64, _P, _D, _U32, _P, ctypes.POINTER(_P)]),
+    "encore_build_grid_device": (_I, [_P, _P, _P, _I64, _I64, _P, _D, _U32, _P, ctypes.POINTER(_P)]),
+    "encore_free_grid": (_I, [_P]),
+    "encore_grid_size": (_I64, [_P]),
+    "encore_npcf": (_I, [_P, _P, _I, _I, _I, _P, _U32, _D, _P, _SZ, _P, _I64, _P]),
+    "encore_npcf_simple": (_I, [_P, _P, _I64, _I, _I, _I, _P, _P, _U32, _P, _SZ]),
+    "encore_num_multiplets": (_I64, [_I, _I, _U32]),
+    "encore_num_bin_tuples": (_I64, [_I, _I]),
+    "encore_multiplet_table": (_I, [_I, _I, _U32, _P, _SZ]),
+    "encore_coupling_terms": (_I, [_I, _I, _U32, ctypes.POINTER(_I64), _I64, _P, _P, _P, _P]),
+    "encore_wigner3j": (_D, [_I, _I, _I, _I, _I, _I]),
+    "encore_debug_alm": (_I, [_P, _P, _I, _I, _P, _U32, _P, _I64, _P]),
+    "encore_last_timings": (_I, [_P, _P, _SZ]),
+}
+
+_lib = None
+
+
+class EncoreError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("encore error %d: %s" % (code, msg))
+        self.code = code
+
+
+def lib():
+    """Load libencore.so (raises if it has not been built).
+
+    torch is imported first: it ships its own HIP runtime under the same soname
+    (libamdhip64.so.7), and the library must bind to that one so that torch's
+    device pointers and streams and the library's kernels share one runtime."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  (one HIP runtime per process: torch's)
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libencore.so is not built (run __graft_entry__.build() or "
+                              "python paper_2105_08722_amd/build.py); there is no fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise EncoreError(rc, lib().encore_last_error().decode())
+    return rc
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_P)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def version():
+    return lib().encore_version().decode()
+
+
+def num_multiplets(npcf, lmax, allparity=False):
+    r = lib().encore_num_multiplets(npcf, lmax, ALLPARITY if allparity else 0)
+    if r < 0:
+        _check(int(r))
+    return int(r)
+
+
+def num_bin_tuples(npcf, nbins):
+    r = lib().encore_num_bin_tuples(npcf, nbins)
+    if r < 0:
+        _check(int(r))
+    return int(r)
+
+
+def multiplet_table(npcf, lmax, allparity=False):
+    width = 2 if npcf == 3 else 2 * npcf - 5
+    n = num_multiplets(npcf, lmax, allparity)
+    out = np.zeros(n * width, dtype=np.int32)
+    _check(lib().encore_multiplet_table(npcf, lmax, ALLPARITY if allparity else 0, _ptr(out), out.size))
+    return out.reshape(n, width)
+
+
+def coupling_terms(npcf, lmax, allparity=False):
+    """Half-sum terms: (lam[nt], l[nt, N-1], m[nt, N-1], coef[nt])."""
+    flags = ALLPARITY if allparity else 0
+    nt = ctypes.c_int64(0)
+    _check(lib().encore_coupling_terms(npcf, lmax, flags, ctypes.byref(nt), 0, None, None, None, None))
+    n = nt.value
+    k = npcf - 1
+    lam = np.zeros(n, dtype=np.int32)
+    l = np.zeros(n * k, dtype=np.int32)
+    m = np.zeros(n * k, dtype=np.int32)
+    coef = np.zeros(n)
+    _check(lib().encore_coupling_terms(npcf, lmax, flags, ctypes.byref(nt), n, _ptr(lam), _ptr(l),
+                                       _ptr(m), _ptr(coef)))
+    return lam, l.reshape(n, k), m.reshape(n, k), coef
+
+
+def wigner3j(j1, j2, j3, m1, m2, m3):
+    return lib().encore_wigner3j(j1, j2, j3, m1, m2, m3)
+
+
+class Context:
+    """An encore_ctx on one HIP device."""
+
+    def __init__(self, device=0):
+        h = _P()
+        _check(lib().encore_create(int(device), ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            _check(lib().encore_destroy(self.handle))
+        self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def last_timings(self):
+        out = np.zeros(6)
+        _check(lib().encore_last_timings(self.handle, _ptr(out), 6))
+        return dict(total_ms=out[0], gather_ms=out[1], couple_ms=out[2], contract_ms=out[3],
+                    batches=int(out[4]), pairs=int(out[5]))
+
+
+class Grid:
+    """A device-resident cell grid (encore_grid)."""
+
+    def __init__(self, ctx, handle, n):
+        self.ctx = ctx
+        self.handle = handle
+        self.n = n
+
+    def free(self):
+        if self.handle is not None and self.handle.value:
+            _check(lib().encore_free_grid(self.handle))
+        self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+
+def _box3(box):
+    if box is None:
+        return None
+    return _f64(np.broadcast_to(np.asarray(box, dtype=np.float64), (3,)))
+
+
+def build_grid(ctx, pos, w, r_max, box=None, n_data=None, stream=None):
+    """encore_build_grid from host arrays.  n_data: D-R weighting (first n_data are data)."""
+    pos = _f64(pos, (-1, 3))
+    w = _f64(w, (-1,))
+    flags = (PERIODIC if box is not None else 0) | (DMR if n_data is not None else 0)
+    b = _box3(box)
+    h = _P()
+    _check(lib().encore_build_grid(ctx.handle, _ptr(pos), _ptr(w), len(w), int(n_data or 0), _ptr(b),
+                                   float(r_max), flags, stream, ctypes.byref(h)))
+    return Grid(ctx, h, len(w))
+
+
+def build_grid_device(ctx, pos, w, r_max, box=None, n_data=None):
+    """encore_build_grid_device from torch tensors on the GPU (float64, contiguous)."""
+    import torch
+    if pos.dtype != torch.float64 or w.dtype != torch.float64 or not pos.is_cuda:
+        raise ValueError("pos and w must be float64 device tensors")
+    pos = pos.contiguous()
+    w = w.contiguous()
+    flags = (PERIODIC if box is not None else 0) | (DMR if n_data is not None else 0)
+    b = _box3(box)
+    h = _P()
+    stream = torch.cuda.current_stream(pos.device).cuda_stream
+    _check(lib().encore_build_grid_device(ctx.handle, ctypes.c_void_p(pos.data_ptr()),
+                                          ctypes.c_void_p(w.data_ptr()), w.numel(), int(n_data or 0),
+                                          _ptr(b), float(r_max), flags, ctypes.c_void_p(stream),
+                                          ctypes.byref(h)))
+    return Grid(ctx, h, w.numel())
+
+
+def npcf(ctx, grid, N, lmax, edges, precision="fp32", allparity=False, normalize=False, volume=0.0,
+         primaries=None, stream=None):
+    """encore_npcf: Z (or zeta with normalize) as float64 [n_multiplets, n_bin_tuples]."""
+    edges = _f64(edges, (-1,))
+    nbins = len(edges) - 1
+    flags = PRECISIONS[precision] | (ALLPARITY if allparity else 0) | (NORMALIZE if normalize else 0)
+    nlam = num_multiplets(N, lmax, allparity)
+    nB = num_bin_tuples(N, nbins) if nbins >= 0 else 0
+    out = np.zeros(max(nlam * nB, 1))
+    prim = None
+    nsub = 0
+    if primaries is not None:
+        prim = np.ascontiguousarray(primaries, dtype=np.int64)
+        nsub = len(prim)
+        if nsub == 0:
+            prim = np.zeros(1, dtype=np.int64)
+    _check(lib().encore_npcf(ctx.handle, grid.handle, int(N), int(lmax), nbins, _ptr(edges), flags,
+                             float(volume), _ptr(out), out.size, _ptr(prim), nsub, stream))
+    return out[:nlam * nB].reshape(nlam, nB)
+
+
+def debug_alm(ctx, grid, lmax, edges, primaries, precision="fp64", full_launch=False):
+    """encore_debug_alm: complex a~ [k, nbins, (lmax+1)(lmax+2)/2] of the given primaries
+    (full_launch: gather every point in one launch, as encore_npcf does)."""
+    edges = _f64(edges, (-1,))
+    nbins = len(edges) - 1
+    prim = np.ascontiguousarray(primaries, dtype=np.int64)
+    nlm = (lmax + 1) * (lmax + 2) // 2
+    out = np.zeros((len(prim), nbins, nlm, 2))
+    _check(lib().encore_debug_alm(ctx.handle, grid.handle, int(lmax), nbins, _ptr(edges),
+                                  PRECISIONS[precision] | (DEBUG_FULLGRID if full_launch else 0),
+                                  _ptr(prim), len(prim), _ptr(out)))
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def npcf_simple(pos, w, N, lmax, edges, box=None, precision="fp32", allparity=False):
+    """encore_npcf_simple: one-shot grid build + npcf on device 0."""
+    pos = _f64(pos, (-1, 3))
+    w = _f64(w, (-1,))
+    edges = _f64(edges, (-1,))
+    nbins = len(edges) - 1
+    flags = PRECISIONS[precision] | (ALLPARITY if allparity else 0)
+    nlam = num_multiplets(N, lmax, allparity)
+    nB = num_bin_tuples(N, nbins)
+    out = np.zeros(max(nlam * nB, 1))
+    _check(lib().encore_npcf_simple(_ptr(pos), _ptr(w), len(w), int(N), int(lmax), nbins, _ptr(edges),
+                                    _ptr(_box3(box)), flags, _ptr(out), out.size))
+    return out[:nlam * nB].reshape(nlam, nB)

@@ -1,0 +1,272 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances
+  * FP64 path: the device uses the same FP64 bin decisions as the oracle and FP64
+    arithmetic throughout; differences are rounding-order only.  Bound: 1e-10
+    relative to max|Z| (per multiplet normwise <= 1e-10 where the multiplet is not
+    tiny).
+  * FP32 path: FP32 separations/Y_lm/accumulators in the gather and FP32 products
+    in the coupling with FP64 sums over primaries.  Each a~ carries a relative error
+    of a few 1e-7 for catalogs with positive weights; a product of N-1 of them
+    carries (N-1) times that.  Bound used: 2e-5 normwise per multiplet and 1e-5
+    of max|a~| per harmonic coefficient.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_08722_amd import encore, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print("[gpu-parity] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = encore.Context(0)
+    yield c
+    c.close()
+
+
+def _normwise(zg, zo):
+    """Per-multiplet ||zg - zo|| / ||zo|| (multiplets with ||zo|| below 1e-9 max are skipped)."""
+    num = np.linalg.norm(zg - zo, axis=1)
+    den = np.linalg.norm(zo, axis=1)
+    keep = den > 1e-9 * max(den.max(), 1e-300)
+    return np.where(keep, num / np.where(keep, den, 1.0), 0.0)
+
+
+def _uniform(n, L, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0, L, (n, 3)), rng.uniform(0.5, 1.5, n)
+
+
+# ------------------------------------------------------------------ harmonic coefficients
+
+@pytest.mark.parametrize("periodic", [True, False])
+@pytest.mark.parametrize("lmax", [0, 3, 5, 10])
+def test_alm_fp64_matches_oracle(ctx, periodic, lmax):
+    _say("alm fp64 periodic=%s lmax=%d" % (periodic, lmax))
+    pos, w = _uniform(3000, 100.0, 7 + lmax)
+    edges = np.linspace(4.0, 30.0, 9)
+    box = 100.0 if periodic else None
+    prim = np.random.default_rng(1).choice(len(w), 40, replace=False)
+    with encore.build_grid(ctx, pos, w, r_max=edges[-1], box=box) as g:
+        ag = encore.debug_alm(ctx, g, lmax, edges, prim, "fp64")
+    ao = oracle.alm(pos, w, lmax, edges, box=box, primaries=prim)
+    scale = np.max(np.abs(ao))
+    assert np.max(np.abs(ag - ao)) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("lmax", [2, 5, 8])
+def test_alm_fp32_matches_oracle(ctx, lmax):
+    _say("alm fp32 lmax=%d" % lmax)
+    pos, w = _uniform(3000, 100.0, 17)
+    edges = np.linspace(4.0, 30.0, 11)
+    prim = np.arange(0, 3000, 97)
+    with encore.build_grid(ctx, pos, w, r_max=edges[-1], box=100.0) as g:
+        ag = encore.debug_alm(ctx, g, lmax, edges, prim, "fp32")
+    ao = oracle.alm(pos, w, lmax, edges, box=100.0, primaries=prim)
+    for i in range(len(prim)):
+        assert np.max(np.abs(ag[i] - ao[i])) <= 1e-5 * np.max(np.abs(ao[i]))
+
+
+def test_alm_clustered_nonperiodic_offset_box(ctx):
+    """Clustered points, non-periodic, far from the origin; one edge set reaching
+    beyond the catalog (empty bins) and primaries at the corners."""
+    _say("alm clustered non-periodic")
+    pos, w = synth.neyman_scott(4000, 200.0, 5, nbar_parent=5e-5, sigma=3.0)
+    pos = pos + np.array([1000.0, -5000.0, 250.0])
+    w = w * np.random.default_rng(2).uniform(-1, 1, len(w))
+    edges = np.array([1.0, 3.0, 7.0, 15.0, 40.0, 90.0])
+    corner = [int(np.argmin(pos.sum(1))), int(np.argmax(pos.sum(1)))]
+    prim = np.array(corner + list(range(0, 4000, 211)))
+    with encore.build_grid(ctx, pos, w, r_max=edges[-1]) as g:
+        ag = encore.debug_alm(ctx, g, 4, edges, prim, "fp64")
+    ao = oracle.alm(pos, w, 4, edges, primaries=prim)
+    assert np.max(np.abs(ag - ao)) <= 1e-12 * np.max(np.abs(ao))
+
+
+# ------------------------------------------------------------------ multiplets
+
+CASES = [
+    # N, lmax, npts, nbins, periodic, allparity
+    (3, 6, 1500, 7, True, False),
+    (4, 3, 1200, 6, True, False),
+    (4, 3, 900, 5, False, True),
+    (5, 2, 800, 5, True, False),
+    (5, 2, 500, 5, False, True),
+    (6, 1, 500, 6, True, False),
+    (6, 2, 400, 5, False, False),
+]
+
+
+@pytest.mark.parametrize("N,lmax,npts,nbins,periodic,allp", CASES)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_zeta_matches_oracle(ctx, N, lmax, npts, nbins, periodic, allp, precision):
+    _say("zeta N=%d lmax=%d n=%d nb=%d periodic=%s allparity=%s %s"
+         % (N, lmax, npts, nbins, periodic, allp, precision))
+    L = 60.0
+    pos, w = _uniform(npts, L, 100 * N + lmax)
+    edges = np.linspace(3.0, 25.0, nbins + 1)
+    box = L if periodic else None
+    with encore.build_grid(ctx, pos, w, r_max=edges[-1], box=box) as g:
+        zg = encore.npcf(ctx, g, N, lmax, edges, precision=precision, allparity=allp)
+    zo = oracle.zeta(pos, w, N, lmax, edges, box=box, parity="all" if allp else "even")
+    assert zg.shape == zo.shape
+    scale = np.max(np.abs(zo))
+    if precision == "fp64":
+        assert np.max(np.abs(zg - zo)) <= 1e-10 * scale
+        assert np.max(_normwise(zg, zo)) <= 1e-9
+    else:
+        assert np.max(np.abs(zg - zo)) <= 2e-5 * scale
+        assert np.max(_normwise(zg, zo)) <= 5e-4
+
+
+def test_dmr_weights_and_subset(ctx):
+    _say("D-R weighting + primary subset")
+    rng = np.random.default_rng(44)
+    L = 80.0
+    dpos, _ = synth.neyman_scott(700, L, 9, nbar_parent=2e-4, sigma=2.0)
+    rpos = rng.uniform(0, L, (1400, 3))
+    pos = np.concatenate([dpos, rpos])
+    w_in = np.concatenate([np.ones(700), rng.uniform(0.8, 1.2, 1400)])
+    w = oracle.dmr_weights(w_in[:700], w_in[700:])
+    edges = np.linspace(4.0, 30.0, 7)
+    subset = rng.choice(len(w), 300, replace=False)
+    with encore.build_grid(ctx, pos, w_in, r_max=edges[-1], box=L, n_data=700) as g:
+        zg = encore.npcf(ctx, g, 4, 3, edges, precision="fp64", primaries=subset)
+        zg_all = encore.npcf(ctx, g, 4, 3, edges, precision="fp64")
+        rest = np.setdiff1d(np.arange(len(w)), subset)
+        zg_rest = encore.npcf(ctx, g, 4, 3, edges, precision="fp64", primaries=rest)
+    zo = oracle.zeta(pos, w, 4, 3, edges, box=L, primaries=subset)
+    assert np.max(np.abs(zg - zo)) <= 1e-10 * np.max(np.abs(zo))
+    # linearity in the primaries: Z(all) = Z(S) + Z(complement)
+    assert np.max(np.abs(zg_all - zg - zg_rest)) <= 1e-10 * np.max(np.abs(zg_all))
+
+
+def test_normalize_flag(ctx):
+    _say("normalize")
+    pos, w = _uniform(600, 50.0, 5)
+    edges = np.linspace(3.0, 20.0, 5)
+    with encore.build_grid(ctx, pos, w, r_max=edges[-1], box=50.0) as g:
+        zn = encore.npcf(ctx, g, 4, 2, edges, precision="fp64", normalize=True)
+        zr = encore.npcf(ctx, g, 4, 2, edges, precision="fp64")
+    ref = oracle.normalise(zr, 4, edges, 50.0 ** 3)
+    assert np.max(np.abs(zn - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_degenerate_inputs(ctx):
+    _say("degenerate inputs")
+    pos, w = _uniform(200, 30.0, 3)
+    edges = np.linspace(2.0, 10.0, 3)          # 2 bins
+    with encore.build_grid(ctx, pos, w, r_max=10.0, box=30.0) as g:
+        z = encore.npcf(ctx, g, 5, 2, edges)      # needs 4 bins: no bin tuples
+        assert z.shape[1] == 0
+        z0 = encore.npcf(ctx, g, 3, 2, edges, primaries=np.array([], dtype=np.int64))
+        assert z0.shape == (3, 1) and np.all(z0 == 0)
+        with pytest.raises(encore.EncoreError):
+            encore.npcf(ctx, g, 3, 2, np.array([2.0, 20.0]))     # beyond r_max
+        with pytest.raises(encore.EncoreError):
+            encore.npcf(ctx, g, 3, 2, edges, primaries=np.array([5, 200]))  # index out of range
+        with pytest.raises(encore.EncoreError) as e:
+            encore.npcf(ctx, g, 4, 2, edges, precision="splitbf16")
+        assert e.value.code == encore.EUNSUPPORTED
+    # one point: no pairs at all
+    with encore.build_grid(ctx, np.array([[1.0, 2.0, 3.0]]), np.array([2.0]), r_max=10.0) as g:
+        z = encore.npcf(ctx, g, 3, 3, edges, precision="fp64")
+        assert np.all(z == 0)
+    # a point outside the periodic box is rejected
+    bad = pos.copy(); bad[7, 1] = 30.0
+    with pytest.raises(encore.EncoreError) as e:
+        encore.build_grid(ctx, bad, w, r_max=10.0, box=30.0)
+    assert e.value.code == encore.EINVAL
+    nan = pos.copy(); nan[3, 0] = np.nan
+    with pytest.raises(encore.EncoreError):
+        encore.build_grid(ctx, nan, w, r_max=10.0)
+
+
+def test_device_pointer_grid_matches_host(ctx):
+    import torch
+    _say("device-pointer grid")
+    pos, w = _uniform(900, 40.0, 12)
+    edges = np.linspace(2.0, 15.0, 5)
+    tp = torch.from_numpy(pos).cuda()
+    tw = torch.from_numpy(w).cuda()
+    g1 = encore.build_grid_device(ctx, tp, tw, r_max=15.0, box=40.0)
+    torch.cuda.synchronize()
+    with encore.build_grid(ctx, pos, w, r_max=15.0, box=40.0) as g2:
+        z1 = encore.npcf(ctx, g1, 4, 3, edges, precision="fp64")
+        z2 = encore.npcf(ctx, g2, 4, 3, edges, precision="fp64")
+    g1.free()
+    assert np.max(np.abs(z1 - z2)) <= 1e-12 * np.max(np.abs(z2))
+
+
+# ------------------------------------------------------------------ benchmark workloads
+
+def test_config1_3pcf_full(ctx):
+    """The 3PCF workload in full: 2000 uniform points, periodic 500 Mpc/h, lmax = 10,
+    10 bins over [20, 160], FP64."""
+    cfg = synth.config(1)
+    _say(cfg["name"])
+    with encore.build_grid(ctx, cfg["pos"], cfg["w"], r_max=160.0, box=cfg["box"]) as g:
+        zg = encore.npcf(ctx, g, 3, 10, cfg["edges"], precision="fp64")
+        zf = encore.npcf(ctx, g, 3, 10, cfg["edges"], precision="fp32")
+    zo = oracle.zeta(cfg["pos"], cfg["w"], 3, 10, cfg["edges"], box=cfg["box"])
+    assert np.max(np.abs(zg - zo)) <= 1e-10 * np.max(np.abs(zo))
+    assert np.max(np.abs(zf - zo)) <= 2e-5 * np.max(np.abs(zo))
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    return synth.config(2)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_config2_alm_full_launch_sampled(ctx, cfg2, precision):
+    """Full-size 4PCF workload (200k clustered data + 600k randoms, D-R weights):
+    gather over all 800k primaries in one launch, sampled rows vs the oracle."""
+    _say("config2 full-launch alm " + precision)
+    n = len(cfg2["w"])
+    w = oracle.dmr_weights(cfg2["w"][:cfg2["n_data"]], cfg2["w"][cfg2["n_data"]:])
+    rng = np.random.default_rng(2024)
+    prim = np.concatenate([rng.choice(cfg2["n_data"], 12, replace=False),
+                           cfg2["n_data"] + rng.choice(n - cfg2["n_data"], 12, replace=False)])
+    with encore.build_grid(ctx, cfg2["pos"], cfg2["w"], r_max=160.0, box=cfg2["box"],
+                           n_data=cfg2["n_data"]) as g:
+        ag = encore.debug_alm(ctx, g, 5, cfg2["edges"], prim, precision, full_launch=True)
+    ao = oracle.alm(cfg2["pos"], w, 5, cfg2["edges"], box=cfg2["box"], primaries=prim)
+    for i in range(len(prim)):
+        err = np.max(np.abs(ag[i] - ao[i])) / np.max(np.abs(ao[i]))
+        assert err <= (1e-12 if precision == "fp64" else 1e-5), (i, err)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_config2_zeta_sampled_primaries(ctx, cfg2, precision):
+    """4PCF lmax = 5 on the full 800k-point D-R catalog, summed over 48 sampled
+    primaries (all 800k are secondaries), vs the oracle on the same primaries."""
+    _say("config2 zeta sampled " + precision)
+    n = len(cfg2["w"])
+    w = oracle.dmr_weights(cfg2["w"][:cfg2["n_data"]], cfg2["w"][cfg2["n_data"]:])
+    prim = np.random.default_rng(7).choice(n, 48, replace=False)
+    with encore.build_grid(ctx, cfg2["pos"], cfg2["w"], r_max=160.0, box=cfg2["box"],
+                           n_data=cfg2["n_data"]) as g:
+        zg = encore.npcf(ctx, g, 4, 5, cfg2["edges"], precision=precision, primaries=prim)
+    zo, za = oracle.zeta(cfg2["pos"], w, 4, 5, cfg2["edges"], box=cfg2["box"], primaries=prim,
+                         return_abs=True)
+    e = _normwise(zg, zo)
+    kappa = np.linalg.norm(za, axis=1) / np.maximum(np.linalg.norm(zo, axis=1), 1e-300)
+    _say("  max e_L = %.3e, median kappa = %.1f" % (e.max(), np.median(kappa)))
+    if precision == "fp64":
+        assert np.max(np.abs(zg - zo)) <= 1e-10 * np.max(np.abs(zo))
+    else:
+        # FP32 error grows with the D-R cancellation: e_L <~ few u32 * kappa_L
+        assert np.all(e <= 1e-6 * np.maximum(kappa, 1.0) + 1e-6)
