@@ -491,11 +491,9 @@ int encore_npcf(encore_ctx* ctx, const encore_grid* grid, int npcf, int lmax, in
     const int nlm = (lmax + 1) * (lmax + 2) / 2;
     const size_t per_prim = (size_t)nbins * nlm * 2 * (prec == 0 ? 8 : 4);
     const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nprim, (int64_t)((size_t)2 << 30) / per_prim));
-    // splits of the primary range in the coupling kernel (parallelism when ntuple*nB is small)
+    // splits of the primary range in the coupling kernel (parallelism of the sum over i)
     const int64_t outs = tb->ntuple * tb->nB;
-    int64_t nsplit = std::max<int64_t>(1, (int64_t)(1 << 20) / std::max<int64_t>(outs, 1));
-    nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, batch / 16));
-    nsplit = std::min<int64_t>(nsplit, 1024);
+    const int64_t nsplit = couple_nsplit(npcf - 1, nbins, tb->ntuple, tb->nB, batch);
 
     if ((rc = ensure(ctx->alm, per_prim * (size_t)batch))) return rc;
     if ((rc = ensure(ctx->T, sizeof(double) * (size_t)(nsplit * outs)))) return rc;

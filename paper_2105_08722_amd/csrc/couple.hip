@@ -13,6 +13,8 @@
 // of primaries' coefficients in LDS and every thread walks the tile.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.h"
 
 namespace encore {
@@ -91,6 +93,102 @@ __global__ void __launch_bounds__(kBlock) k_couple(CoupleArgs a, int ptile, int 
     }
 }
 
+// 4PCF with 10 radial bins: one block per (b1, 256 tuples, primary split).
+// For each primary each thread loads a~^{b1} of its first factor once, the
+// second-factor a~^{b2} and third-factor a~^{b3} rows once each, forms
+// P = w a1 a2 once per b2 and adds Q[P a3] for every b3 > b2.  Accumulation: FP32
+// over a tile of primaries, then FP64 registers (the FP64 path: FP64 throughout).
+constexpr int kNB4 = 10;
+__host__ __device__ constexpr int pair_count(int b1) { return (kNB4 - 1 - b1) * (kNB4 - 2 - b1) / 2; }
+
+template <typename T, int B1>
+__global__ void __launch_bounds__(kBlock) k_couple4(CoupleArgs a, int ptile, int chunk)
+{
+    using V = typename C2<T>::type;
+    constexpr int NA = pair_count(B1);
+    constexpr int NR = kNB4 - B1;                         // bins b1..9 staged
+    extern __shared__ __align__(16) unsigned char smem[];
+    V* tile = reinterpret_cast<V*>(smem);
+    const int per = NR * a.nlm;                           // staged complex values per primary
+    double* wtile = reinterpret_cast<double*>(smem + sizeof(V) * (size_t)ptile * per);
+
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = t < a.ntuple;
+    const int split = blockIdx.y;
+    const int p_lo = split * chunk;
+    const int p_hi = min(a.nprim, p_lo + chunk);
+
+    int lm0 = 0, lm1 = 0, lm2 = 0, flags = 0;
+    if (valid) {
+        lm0 = a.tuple_off[t * 3 + 0];
+        lm1 = a.tuple_off[t * 3 + 1];
+        lm2 = a.tuple_off[t * 3 + 2];
+        flags = a.tuple_flags[t];
+    }
+    const T c0 = (flags & 1) ? (T)-1 : (T)1;
+    const T c1 = (flags & 2) ? (T)-1 : (T)1;
+    const T c2 = (flags & 4) ? (T)-1 : (T)1;
+    const bool take_im = (flags >> 16) & 1;
+
+    double acc[NA];
+    T part[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) { acc[q] = 0.0; part[q] = (T)0; }
+
+    for (int p0 = p_lo; p0 < p_hi; p0 += ptile) {
+        const int np = min(ptile, p_hi - p0);
+        __syncthreads();
+        // stage bins B1..9 of each primary of the tile
+        const V* src = reinterpret_cast<const V*>(a.alm);
+        const int full = a.nbins * a.nlm;
+        for (int q = threadIdx.x; q < np * per; q += kBlock) {
+            const int pp = q / per, r = q - pp * per;
+            tile[q] = src[(size_t)(p0 + pp) * full + B1 * a.nlm + r];
+        }
+        for (int q = threadIdx.x; q < np; q += kBlock) wtile[q] = a.P[a.prim[p0 + q]].w;
+        __syncthreads();
+        if (valid) {
+            for (int pp = 0; pp < np; ++pp) {
+                const V* ap = tile + pp * per;
+                const T w = (T)wtile[pp];
+                const V v0 = ap[lm0];
+                const T a1r = w * v0.x, a1i = w * (c0 * v0.y);
+                T u3r[NR], u3i[NR];
+#pragma unroll
+                for (int b = 2; b < NR; ++b) {
+                    const V u = ap[b * a.nlm + lm2];
+                    u3r[b] = u.x; u3i[b] = c2 * u.y;
+                }
+                int q = 0;
+#pragma unroll
+                for (int b2 = 1; b2 < NR - 1; ++b2) {
+                    const V u = ap[b2 * a.nlm + lm1];
+                    const T ur = u.x, ui = c1 * u.y;
+                    T pr = a1r * ur - a1i * ui;
+                    T pi = a1r * ui + a1i * ur;
+                    if (take_im) { const T tmp = pr; pr = pi; pi = -tmp; }   // Im(z) = Re(-i z)
+#pragma unroll
+                    for (int b3 = b2 + 1; b3 < NR; ++b3) {
+                        part[q] += pr * u3r[b3] - pi * u3i[b3];
+                        ++q;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NA; ++q) { acc[q] += (double)part[q]; part[q] = (T)0; }
+    }
+    if (valid) {
+        const double sgn = ((flags >> 8) & 1) ? -1.0 : 1.0;
+        // B index of (B1, b2, b3): tuples with first bin < B1 come first
+        int bidx = 0;
+        for (int b = 0; b < B1; ++b) bidx += pair_count(b);
+        double* dst = a.T + ((size_t)split * a.ntuple + t) * a.nB + bidx;
+#pragma unroll
+        for (int q = 0; q < NA; ++q) dst[q] += sgn * acc[q];
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_contract(ContractArgs a)
 {
     const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -110,6 +208,20 @@ __global__ void __launch_bounds__(kBlock) k_contract(ContractArgs a)
 
 }  // namespace
 
+int couple_nsplit(int nk, int nbins, int64_t ntuple, int64_t nB, int64_t nprim)
+{
+    int64_t ns;
+    if (nk == 3 && nbins == kNB4) {
+        // one block per (b1, 256 tuples, split): aim at ~1024 blocks per launch
+        const int64_t tblocks = (ntuple + kBlock - 1) / kBlock;
+        ns = (1024 + tblocks - 1) / std::max<int64_t>(tblocks, 1);
+    } else {
+        ns = (int64_t)(1 << 20) / std::max<int64_t>(ntuple * nB, 1);
+    }
+    ns = std::min<int64_t>(ns, std::max<int64_t>(1, nprim / 64));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(ns, 1024));
+}
+
 int couple_ptile(int nbins, int nlm, int precision)
 {
     const int per = nbins * nlm * (precision == 0 ? 16 : 8) + 8;
@@ -117,9 +229,38 @@ int couple_ptile(int nbins, int nlm, int precision)
     return pt < 1 ? 1 : (pt > 64 ? 64 : pt);
 }
 
+template <typename T, int B1>
+void launch4(const CoupleArgs& a, int ptile, int chunk, hipStream_t stream)
+{
+    const int nblk = (a.ntuple + kBlock - 1) / kBlock;
+    const size_t lds = (size_t)ptile * (kNB4 - B1) * a.nlm * sizeof(typename C2<T>::type) + 8 * (size_t)ptile;
+    k_couple4<T, B1><<<dim3((unsigned)nblk, (unsigned)a.nsplit), kBlock, lds, stream>>>(a, ptile, chunk);
+}
+
+template <typename T>
+void launch4_all(const CoupleArgs& a, int ptile, int chunk, hipStream_t stream)
+{
+    launch4<T, 0>(a, ptile, chunk, stream);
+    launch4<T, 1>(a, ptile, chunk, stream);
+    launch4<T, 2>(a, ptile, chunk, stream);
+    launch4<T, 3>(a, ptile, chunk, stream);
+    launch4<T, 4>(a, ptile, chunk, stream);
+    launch4<T, 5>(a, ptile, chunk, stream);
+    launch4<T, 6>(a, ptile, chunk, stream);
+    launch4<T, 7>(a, ptile, chunk, stream);
+}
+
 int launch_couple(const CoupleArgs& a, int precision, hipStream_t stream)
 {
     if (a.nk > kMaxK) return (int)hipErrorInvalidValue;
+    if (a.nk == 3 && a.nbins == kNB4) {
+        if (a.nprim == 0 || a.ntuple == 0) return (int)hipSuccess;
+        const int ptile = std::max(1, std::min(64, 32768 / (kNB4 * a.nlm * (precision == 0 ? 16 : 8) + 8)));
+        const int chunk = (a.nprim + a.nsplit - 1) / a.nsplit;
+        if (precision == 0) launch4_all<double>(a, ptile, chunk, stream);
+        else launch4_all<float>(a, ptile, chunk, stream);
+        return (int)hipGetLastError();
+    }
     const int64_t nthreads = (int64_t)a.ntuple * a.nB;
     const int64_t nblk = (nthreads + kBlock - 1) / kBlock;
     if (nblk == 0 || a.nprim == 0) return (int)hipSuccess;

@@ -39,6 +39,8 @@ int launch_map_subset(const int64_t* idx, int64_t k, const int32_t* inv, int64_t
 int launch_fill(double* p, int64_t n, double v, hipStream_t stream);
 int launch_to_double(const void* src, int precision, int64_t n, double* dst, hipStream_t stream);
 int couple_ptile(int nbins, int nlm, int precision);
+// primary splits of the coupling kernels (parallelism across the sum over primaries)
+int couple_nsplit(int nk, int nbins, int64_t ntuple, int64_t nB, int64_t nprim);
 
 // ------------------------------------------------------------------ gather
 // Harmonic coefficient gather (eq. binned-discrete-alm): for every primary of the

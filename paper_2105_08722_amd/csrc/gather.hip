@@ -53,17 +53,23 @@ template <> struct Entry<float> { using type = float4; };
 template <> struct Entry<double> { using type = double4; };
 
 template <typename T> __device__ __forceinline__ T rsqrt_t(T v);
-template <> __device__ __forceinline__ float rsqrt_t<float>(float v) { return rsqrtf(v); }
+template <> __device__ __forceinline__ float rsqrt_t<float>(float v) { return __builtin_amdgcn_rsqf(v); }
 template <> __device__ __forceinline__ double rsqrt_t<double>(double v) { return 1.0 / sqrt(v); }
 
+// LDS of one wave: the per-bin rings (reused as the reduction scratch), the
+// per-lane segment slots and the compacted segment list of one row batch.
+template <typename T, int NBG>
+__host__ __device__ constexpr int ring_bytes()
+{
+    return (NBG * kCap * (int)sizeof(typename Entry<T>::type) > 32 * 65 * (int)sizeof(T))
+               ? NBG * kCap * (int)sizeof(typename Entry<T>::type)
+               : 32 * 65 * (int)sizeof(T);
+}
 template <typename T, int NBG>
 __host__ __device__ constexpr int wave_lds_bytes()
 {
-    // ring storage (reused as the reduction scratch) + tails + segment lists
-    return ((NBG * kCap * (int)sizeof(typename Entry<T>::type) > 32 * 65 * (int)sizeof(T))
-                ? NBG * kCap * (int)sizeof(typename Entry<T>::type)
-                : 32 * 65 * (int)sizeof(T)) +
-           16 * 4 + 3 * kSegCap * 4 + kWave * 4;
+    // ring | slot_stc[kSegCap] slot_len[kSegCap] | seg_stc[kSegCap] seg_flat[kSegCap + 1]
+    return ring_bytes<T, NBG>() + 4 * (4 * kSegCap + 4);
 }
 
 // Add w*Y_lm for m in [M0, M1] of one pair into acc (layout [lm][re, im]).
@@ -85,9 +91,12 @@ __device__ __forceinline__ void accum_pair(T dx, T dy, T dz, T w, T (&acc)[nlm_o
 #pragma unroll
     for (int m = M0; m <= M1; ++m) {
         if (m > M0) {
-            const T nr = ur * x - ui * y;
-            const T ni = ur * y + ui * x;
-            ur = nr; ui = ni;
+            if (m == 1) { ur = x; ui = y; }
+            else {
+                const T nr = ur * x - ui * y;
+                const T ni = ur * y + ui * x;
+                ur = nr; ui = ni;
+            }
         }
         T r0 = w, r1 = zw;
         if (m == 0) {
@@ -115,14 +124,51 @@ __device__ __forceinline__ void accum_pair(T dx, T dy, T dz, T w, T (&acc)[nlm_o
     }
 }
 
-__device__ __forceinline__ double dmul(double a, double b) { return __dmul_rn(a, b); }
-__device__ __forceinline__ double dadd(double a, double b) { return __dadd_rn(a, b); }
+// Separation and squared distance exactly as the definition orders the FP64
+// operations: (x_j - x_i) + image shift, then (dx*dx + dy*dy) + dz*dz, with no
+// fused multiply-add anywhere (the bin decision must match the definition bit for
+// bit).  The image shift is exactly +-L or 0.
+__device__ __forceinline__ double sep(double xj, double xi, double shift)
+{
+#pragma clang fp contract(off)
+    return (xj - xi) + shift;
+}
+__device__ __forceinline__ double dist2(double dx, double dy, double dz)
+{
+#pragma clang fp contract(off)
+    return (dx * dx + dy * dy) + dz * dz;
+}
 
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
+
+// wave-uniform copies (the value must already be uniform)
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uni(double v)
+{
+    const unsigned long long u = __double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+    return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int wave_excl_scan(int v, int lane, int* total)
+{
+    int incl = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int t = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += t;
+    }
+    *total = uni(__shfl(incl, kWave - 1, kWave));
+    return incl - v;
+}
+
+constexpr int kCodeShift = 26;               // segment start | (image code << 26)
+constexpr int kStartMask = (1 << kCodeShift) - 1;
 
 template <typename T, int L, int NBG, int M0, int M1>
 __global__ void __launch_bounds__(kWave * kWavesPerBlock, 2) k_gather(GatherArgs a)
@@ -145,15 +191,12 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, 2) k_gather(GatherArgs
     if (p >= a.nprim) return;
 
     unsigned char* base = smem + wib * wave_lds_bytes<T, NBG>();
-    constexpr int ring_bytes = (NBG * kCap * (int)sizeof(E) > CH * 65 * (int)sizeof(T))
-                                   ? NBG * kCap * (int)sizeof(E) : CH * 65 * (int)sizeof(T);
     E* ring = reinterpret_cast<E*>(base);
     T* scratch = reinterpret_cast<T*>(base);
-    int* tails = reinterpret_cast<int*>(base + ring_bytes);
-    int* seg_start = tails + 16;
-    int* seg_end = seg_start + kSegCap;
-    int* seg_code = seg_end + kSegCap;
-    int* seg_count = seg_code + kSegCap;
+    int* slot_stc = reinterpret_cast<int*>(base + ring_bytes<T, NBG>());
+    int* slot_len = slot_stc + kSegCap;
+    int* seg_stc = slot_len + kSegCap;
+    int* seg_flat = seg_stc + kSegCap;
 
     // recurrence coefficients -> registers (uniform)
     T gam[NLM];
@@ -162,32 +205,30 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, 2) k_gather(GatherArgs
 
     const int ip = a.prim[p];
     const double4 Pi = a.P[ip];
-    const double xi = Pi.x, yi = Pi.y, zi = Pi.z;
+    const double xi = uni(Pi.x), yi = uni(Pi.y), zi = uni(Pi.z);
     const int b_lo = grp * NBG;
     const int b_hi = min(b_lo + NBG, a.nbins);
-    const double R2in = a.e2[b_lo], R2out = a.e2[b_hi];
+    const double R2in = uni(a.e2[b_lo]), R2out = uni(a.e2[b_hi]);
+    // interior squared edges of the group (+inf past the last bin of the group)
+    double e2k[NBG];
+#pragma unroll
+    for (int q = 1; q < NBG; ++q) e2k[q] = uni((b_lo + q < b_hi) ? a.e2[min(b_lo + q, kMaxBins)] : INFINITY);
+    // periodic images: shift per axis for image codes 0, 1, 2 (-L, 0, +L)
+    const double Lx = a.Lx, Ly = a.Ly, Lz = a.Lz;
     // culling uses slightly enlarged cells and radius; the bin test below is exact
     const double eps = 1e-7 * fmin(a.csx, fmin(a.csy, a.csz));
     const double Rc = sqrt(R2out) + eps;
     const double Rc2 = Rc * Rc;
     const double Rin = sqrt(R2in);
 
-    if (lane < 16) tails[lane] = 0;
-    int head[NBG];
+    int head[NBG], tail[NBG];
 #pragma unroll
-    for (int k = 0; k < NBG; ++k) head[k] = 0;
+    for (int k = 0; k < NBG; ++k) { head[k] = 0; tail[k] = 0; }
     T acc[NBG][NLM][2];
 #pragma unroll
     for (int k = 0; k < NBG; ++k)
 #pragma unroll
         for (int q = 0; q < NLM; ++q) { acc[k][q][0] = (T)0; acc[k][q][1] = (T)0; }
-    wave_sync();
-
-    auto drain = [&](auto kc, int hd) {
-        constexpr int k = decltype(kc)::value;
-        const E e = ring[k * kCap + ((hd + lane) & (kCap - 1))];
-        accum_pair<T, L, M0, M1>(e.x, e.y, e.z, e.w, acc[k], gam);
-    };
 
     // row range (unwrapped cell indices)
     int ky0 = (int)floor((yi - Rc - a.oy) / a.csy), ky1 = (int)floor((yi + Rc - a.oy) / a.csy);
@@ -201,9 +242,9 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, 2) k_gather(GatherArgs
 
     for (int rb = 0; rb < nrows; rb += kRowsPerBatch) {
         // ---- 1. lane-parallel row set-up: lane r writes its <= kSegPerRow pieces to
-        //         slots [lane * kSegPerRow, ...) and its count to seg_count[lane]
+        //         slots [lane * kSegPerRow, ...)
+        int ns = 0, nlen = 0;
         {
-            int ns = 0;
             const int r = rb + lane;
             if (r < nrows) {
                 const int ky = ky0 + r % nyr, kz = kz0 + r / nyr;
@@ -257,79 +298,128 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, 2) k_gather(GatherArgs
                             const int en = a.cell_start[rowbase + phi + 1];
                             if (en > st) {
                                 const int slot = lane * kSegPerRow + ns;
-                                seg_start[slot] = st;
-                                seg_end[slot] = en;
-                                seg_code[slot] = (sx + 1) | code_yz;
+                                slot_stc[slot] = st | (((sx + 1) | code_yz) << kCodeShift);
+                                slot_len[slot] = en - st;
+                                nlen += en - st;
                                 ++ns;
                             }
                         }
                     }
                 }
             }
-            seg_count[lane] = ns;
         }
+        // compact the segments in (lane, piece) order with their flat offsets
+        int nseg = 0, total = 0;
+        const int sbase = wave_excl_scan(ns, lane, &nseg);
+        int fbase = wave_excl_scan(nlen, lane, &total);
+        wave_sync();
+        for (int q = 0; q < ns; ++q) {
+            seg_stc[sbase + q] = slot_stc[lane * kSegPerRow + q];
+            seg_flat[sbase + q] = fbase;
+            fbase += slot_len[lane * kSegPerRow + q];
+        }
+        if (lane == 0) seg_flat[nseg] = total;
         wave_sync();
 
-        // ---- 2./3. candidates and drains
-        const int nlanes = min(kWave, nrows - rb);
-        for (int sl = 0; sl < nlanes * kSegPerRow; ++sl) {
-            const int owner = sl / kSegPerRow;
-            if (sl - owner * kSegPerRow >= __builtin_amdgcn_readfirstlane(seg_count[owner])) continue;
-            const int st = __builtin_amdgcn_readfirstlane(seg_start[sl]);
-            const int en = __builtin_amdgcn_readfirstlane(seg_end[sl]);
-            const int code = __builtin_amdgcn_readfirstlane(seg_code[sl]);
-            const double shx = (double)((code & 3) - 1) * a.Lx;
-            const double shy = (double)(((code >> 2) & 3) - 1) * a.Ly;
-            const double shz = (double)(((code >> 4) & 3) - 1) * a.Lz;
-            const bool shifted = (code != 0x15);
-            for (int c = st; c < en; c += kWave) {
-                const int j = c + lane;
-                bool ok = false;
-                double dx = 0.0, dy = 0.0, dz = 0.0, wj = 0.0;
-                if (j < en) {
-                    const double4 q = a.P[j];
-                    dx = q.x - xi; dy = q.y - yi; dz = q.z - zi; wj = q.w;
-                    if (shifted) { dx = dadd(dx, shx); dy = dadd(dy, shy); dz = dadd(dz, shz); }
-                    const double r2 = dadd(dadd(dmul(dx, dx), dmul(dy, dy)), dmul(dz, dz));
-                    ok = (r2 >= R2in) && (r2 < R2out);
-                    if (ok) {
-                        int k = 0;
-#pragma unroll
-                        for (int q2 = 1; q2 < NBG; ++q2)
-                            if (b_lo + q2 < b_hi && r2 >= a.e2[b_lo + q2]) k = q2;
-                        const int slot = atomicAdd(&tails[k], 1);
-                        E ev;
-                        ev.x = (T)dx; ev.y = (T)dy; ev.z = (T)dz; ev.w = (T)wj;
-                        ring[k * kCap + (slot & (kCap - 1))] = ev;
-                    }
-                }
-                wave_sync();
-                [&]<int... K>(std::integer_sequence<int, K...>) {
-                    ([&] {
-                        const int t = __builtin_amdgcn_readfirstlane(tails[K]);
-                        if (t - head[K] >= kWave) {
-                            drain(std::integral_constant<int, K>{}, head[K]);
-                            head[K] += kWave;
-                        }
-                    }(), ...);
-                }(std::make_integer_sequence<int, NBG>{});
-                wave_sync();
+        // ---- 2./3. dense 64-candidate chunks across segments; pushes and drains.
+        // Software pipeline: the segment lookup and the global load of chunk c+1
+        // are issued before chunk c is processed.
+        int s_cur = 0;
+        int cur_stc = uni(seg_stc[0]), cur_fl = 0, nxt_fl = uni(seg_flat[1]);
+        // lane -> (candidate index, image code) of the chunk starting at f0
+        auto lookup = [&](int f0, int& jout, int& cout) {
+            while (nxt_fl <= f0) {
+                ++s_cur;
+                cur_stc = uni(seg_stc[s_cur]);
+                cur_fl = nxt_fl;
+                nxt_fl = uni(seg_flat[s_cur + 1]);
             }
+            const int f = f0 + lane;
+            int my_stc = cur_stc, my_fl = cur_fl;
+            int sn = s_cur + 1;
+            int fn = nxt_fl;
+            while (sn < nseg && fn < f0 + kWave) {
+                const int stc_n = uni(seg_stc[sn]);
+                const int fnext = uni(seg_flat[sn + 1]);
+                if (f >= fn) { my_stc = stc_n; my_fl = fn; }
+                ++sn;
+                fn = fnext;
+            }
+            jout = (my_stc & kStartMask) + (f - my_fl);
+            cout = (int)((unsigned)my_stc >> kCodeShift);
+        };
+        int j_nx = 0, code_nx = 0;
+        double4 q_nx = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (total > 0) {
+            lookup(0, j_nx, code_nx);
+            if (lane < total) q_nx = a.P[j_nx];
         }
+        for (int f0 = 0; f0 < total; f0 += kWave) {
+            const double4 q = q_nx;
+            const int code = code_nx;
+            const bool valid = f0 + lane < total;
+            if (f0 + kWave < total) {
+                lookup(f0 + kWave, j_nx, code_nx);
+                if (f0 + kWave + lane < total) q_nx = a.P[j_nx];
+            }
+            bool ok = false;
+            int k = 0;
+            double dx = 0.0, dy = 0.0, dz = 0.0;
+            if (valid) {
+                // x_j - x_i first, then the periodic image (+/- L or exactly 0)
+                const double shx = (double)((code & 3) - 1) * Lx;
+                const double shy = (double)(((code >> 2) & 3) - 1) * Ly;
+                const double shz = (double)(((code >> 4) & 3) - 1) * Lz;
+                dx = sep(q.x, xi, shx);
+                dy = sep(q.y, yi, shy);
+                dz = sep(q.z, zi, shz);
+                const double r2 = dist2(dx, dy, dz);
+                ok = (r2 >= R2in) && (r2 < R2out);
+#pragma unroll
+                for (int q2 = 1; q2 < NBG; ++q2) k += (r2 >= e2k[q2]) ? 1 : 0;
+            }
+            // ring slots from ballots: tails stay wave-uniform, no LDS round trip
+            int slot = 0;
+#pragma unroll
+            for (int q2 = 0; q2 < NBG; ++q2) {
+                const bool mine = ok && (k == q2);
+                const unsigned long long m = __builtin_amdgcn_ballot_w64(mine);
+                const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                slot = mine ? tail[q2] + rank : slot;
+                tail[q2] += __popcll(m);
+            }
+            if (ok) {
+                E ev;
+                ev.x = (T)dx; ev.y = (T)dy; ev.z = (T)dz; ev.w = (T)q.w;
+                ring[k * kCap + (slot & (kCap - 1))] = ev;
+            }
+            [&]<int... K>(std::integer_sequence<int, K...>) {
+                ([&] {
+                    if (tail[K] - head[K] >= kWave) {
+                        wave_sync();
+                        const E e = ring[K * kCap + ((head[K] + lane) & (kCap - 1))];
+                        accum_pair<T, L, M0, M1>(e.x, e.y, e.z, e.w, acc[K], gam);
+                        head[K] += kWave;
+                    }
+                }(), ...);
+            }(std::make_integer_sequence<int, NBG>{});
+        }
+        wave_sync();
     }
 
     if (a.npairs && lane == 0) {
         unsigned long long tot = 0;
 #pragma unroll
-        for (int k = 0; k < NBG; ++k) tot += (unsigned long long)tails[k];
+        for (int k = 0; k < NBG; ++k) tot += (unsigned long long)tail[k];
         atomicAdd(a.npairs, tot);
     }
 
     // ---- flush partial rings (missing lanes add zero-weight pairs)
+    wave_sync();
     [&]<int... K>(std::integer_sequence<int, K...>) {
         ([&] {
-            const int t = __builtin_amdgcn_readfirstlane(tails[K]);
-            const int rem = t - head[K];
+            const int rem = tail[K] - head[K];
             if (rem > 0) {
                 E e = ring[K * kCap + ((head[K] + lane) & (kCap - 1))];
                 if (lane >= rem) { e.x = (T)1; e.y = (T)0; e.z = (T)0; e.w = (T)0; }
@@ -339,7 +429,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, 2) k_gather(GatherArgs
     }(std::make_integer_sequence<int, NBG>{});
     wave_sync();
 
-    // ---- 4. reduce over lanes through LDS and write
+    // ---- 4. reduce over lanes through LDS (FP64, 8 interleaved partial sums) and write
     constexpr int NV = NBG * NLM * 2;
     T* accf = &acc[0][0][0];
     const int nvalid = (b_hi - b_lo) * NLM * 2;
@@ -347,17 +437,20 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, 2) k_gather(GatherArgs
 #pragma unroll
     for (int v0 = 0; v0 < NV; v0 += CH) {
 #pragma unroll
-        for (int c = 0; c < CH; ++c) {
+        for (int c = 0; c < CH; ++c)
             if (v0 + c < NV) scratch[c * 65 + lane] = accf[v0 + c];
-        }
         wave_sync();
         const int v = v0 + lane;
         if (lane < CH && v < nvalid) {
             const int lm = (v >> 1) % NLM;
             const int m = m_of_lm(lm);
             if (m >= M0 && m <= M1) {
-                double s = 0.0;
-                for (int l2 = 0; l2 < kWave; ++l2) s += (double)scratch[lane * 65 + l2];
+                double s8[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s8[u] = 0.0;
+#pragma unroll
+                for (int l2 = 0; l2 < kWave; ++l2) s8[l2 & 7] += (double)scratch[lane * 65 + l2];
+                const double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
                 out[v] = (T)(s * a.kappa[lm]);
             }
         }

@@ -303,7 +303,12 @@ int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, in
     g.n = n;
     g.periodic = periodic ? 1 : 0;
     g.r_max = r_max;
-    if (n > INT32_MAX - 1) { snprintf(errbuf, errlen, "n too large"); return -1; }
+    // the gather packs a particle index and a 6-bit image code into one int
+    if (n >= (int64_t(1) << 26)) {
+        snprintf(errbuf, errlen, "catalog of %lld points exceeds the 2^26-point limit of one grid",
+                 (long long)n);
+        return -1;
+    }
 
     HIPCHK(hipMalloc(&d_flags, sizeof(int)));
     HIPCHK(hipMemsetAsync(d_flags, 0, sizeof(int), stream));
