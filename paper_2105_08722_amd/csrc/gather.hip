@@ -25,6 +25,7 @@
 // N_lm = kappa_lm R_lm with R_mm = 1, R_{m+1,m} = z, R_lm = z R_{l-1,m} - gamma_lm R_{l-2,m}.
 #include <hip/hip_runtime.h>
 #include <cmath>
+#include <cstdlib>
 #include <utility>
 
 #include "device.h"
@@ -170,8 +171,16 @@ __device__ __forceinline__ int wave_excl_scan(int v, int lane, int* total)
 constexpr int kCodeShift = 26;               // segment start | (image code << 26)
 constexpr int kStartMask = (1 << kCodeShift) - 1;
 
+// waves per SIMD the kernel is compiled for, from its accumulator registers
 template <typename T, int L, int NBG, int M0, int M1>
-__global__ void __launch_bounds__(kWave * kWavesPerBlock, 2) k_gather(GatherArgs a)
+__host__ __device__ constexpr int gather_wpe()
+{
+    constexpr int acc = NBG * ((L + 1) * (L + 1)) * (int)(sizeof(T) / 4);
+    return acc <= 48 ? 4 : (acc <= 90 ? 3 : 2);
+}
+
+template <typename T, int L, int NBG, int M0, int M1>
+__global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG, M0, M1>())) k_gather(GatherArgs a)
 {
     using E = typename Entry<T>::type;
     constexpr int NLM = nlm_of(L);
@@ -378,16 +387,29 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, 2) k_gather(GatherArgs
 #pragma unroll
                 for (int q2 = 1; q2 < NBG; ++q2) k += (r2 >= e2k[q2]) ? 1 : 0;
             }
-            // ring slots from ballots: tails stay wave-uniform, no LDS round trip
-            int slot = 0;
+            // ring slots: one ballot per bit of the bin index; the lanes of the
+            // same bin are those agreeing on every bit; tails stay wave-uniform
+            constexpr int NBITS = (NBG <= 1) ? 0 : (NBG <= 2) ? 1 : (NBG <= 4) ? 2 : (NBG <= 8) ? 3 : 4;
+            const unsigned long long okm = __builtin_amdgcn_ballot_w64(ok);
+            unsigned long long bm[NBITS > 0 ? NBITS : 1];
+            unsigned long long same = okm;
+#pragma unroll
+            for (int bb = 0; bb < NBITS; ++bb) {
+                bm[bb] = __builtin_amdgcn_ballot_w64(ok && ((k >> bb) & 1));
+                same &= ((k >> bb) & 1) ? bm[bb] : ~bm[bb];
+            }
+            const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(same >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((unsigned)same, 0u));
+            int tk = tail[0];
+#pragma unroll
+            for (int q2 = 1; q2 < NBG; ++q2) tk = (k == q2) ? tail[q2] : tk;
+            const int slot = tk + rank;
 #pragma unroll
             for (int q2 = 0; q2 < NBG; ++q2) {
-                const bool mine = ok && (k == q2);
-                const unsigned long long m = __builtin_amdgcn_ballot_w64(mine);
-                const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                slot = mine ? tail[q2] + rank : slot;
-                tail[q2] += __popcll(m);
+                unsigned long long mq = okm;
+#pragma unroll
+                for (int bb = 0; bb < NBITS; ++bb) mq &= ((q2 >> bb) & 1) ? bm[bb] : ~bm[bb];
+                tail[q2] += __popcll(mq);
             }
             if (ok) {
                 E ev;
@@ -489,19 +511,39 @@ KernelCfg cfg2()
     return c;
 }
 
+// Bins per work item for the FP32 lmax = 5 kernel: an autotune knob
+// (ENCORE_GATHER_NBG in {2, 3, 5}).  Fewer bins per item means more passes over
+// the candidates but fewer accumulator registers, hence more resident waves to
+// hide the LDS and L2 latency of the candidate stream; 2 measured best.
+int nbg_override()
+{
+    static int v = [] {
+        const char* s = getenv("ENCORE_GATHER_NBG");
+        const int x = s ? atoi(s) : 0;
+        return (x == 2 || x == 3 || x == 5) ? x : 0;
+    }();
+    return v;
+}
+
 KernelCfg config(int lmax, int precision)
 {
+    if (precision == 1 && lmax == 5) {
+        switch (nbg_override()) {
+        case 3: return cfg1<float, 5, 3>();
+        case 5: return cfg1<float, 5, 5>();
+        default: return cfg1<float, 5, 2>();
+        }
+    }
     if (precision == 1) {
         switch (lmax) {
         case 0: return cfg1<float, 0, 16>();
         case 1: return cfg1<float, 1, 16>();
-        case 2: return cfg1<float, 2, 16>();
-        case 3: return cfg1<float, 3, 10>();
-        case 4: return cfg1<float, 4, 5>();
-        case 5: return cfg1<float, 5, 5>();
-        case 6: return cfg1<float, 6, 3>();
-        case 7: return cfg1<float, 7, 2>();
-        case 8: return cfg1<float, 8, 2>();
+        case 2: return cfg1<float, 2, 6>();
+        case 3: return cfg1<float, 3, 4>();
+        case 4: return cfg1<float, 4, 3>();
+        case 6: return cfg1<float, 6, 2>();
+        case 7: return cfg1<float, 7, 1>();
+        case 8: return cfg1<float, 8, 1>();
         case 9: return cfg1<float, 9, 1>();
         case 10: return cfg1<float, 10, 1>();
         }
