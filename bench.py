@@ -41,6 +41,22 @@ def gather_flops_per_pair(L):
     return f
 
 
+def gather_traffic(pairs):
+    """HBM bytes per gather launch from the committed counter summary, or None when
+    the gather source has changed since the counters were taken."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2105_08722_amd", "csrc", "gather.hip")
+    summ = os.path.join(ROOT, "profiles", "k_gather_traffic.json")
+    if not os.path.exists(summ):
+        return None
+    rec = json.load(open(summ))
+    if rec.get("gather_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    if rec.get("pairs_per_launch") != pairs:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def cpu_baseline(cfg, target_s):
     """The FP64 oracle on the host cores, over a seeded sample of primaries (all
     800k points stay secondaries)."""
@@ -75,6 +91,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one plain device-to-device copy of MIB MiB (the reference "
+                         "dispatch for scaling FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -95,6 +114,14 @@ def main():
     tp = torch.from_numpy(cfg["pos"]).to(dev)
     tw = torch.from_numpy(cfg["w"]).to(dev)
     torch.cuda.synchronize()
+    if args.calibrate_copy > 0:
+        src = torch.empty(args.calibrate_copy << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d MiB read + %d MiB written" % (args.calibrate_copy, args.calibrate_copy))
+        del src, dst
     ctx = encore.Context(0)
 
     def step(prec):
@@ -127,8 +154,8 @@ def main():
     flops = gather_flops_per_pair(L) * pairs
     achieved = flops / (g_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None,
-                "kernel": "k_gather<float,5,5> (harmonic-coefficient gather)",
+                "frac": achieved / PEAK_ALU_TFLOPS, "traffic": gather_traffic(pairs),
+                "kernel": "k_gather<float,5,2,0,5> (harmonic-coefficient gather)",
                 "launch_ms": g_ms, "pairs_per_launch": pairs,
                 "flops_per_pair": gather_flops_per_pair(L)}
 

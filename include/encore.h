@@ -48,6 +48,7 @@ extern "C" {
 #define ENCORE_ENOMEM       -3   /* device or host allocation failed */
 #define ENCORE_EDEVICE      -4   /* HIP runtime error */
 #define ENCORE_EUNSUPPORTED -5   /* combination not built */
+#define ENCORE_EAGAIN       -6   /* encore_server_wait: job not finished within the timeout */
 
 /* flags */
 #define ENCORE_PERIODIC        0x1u   /* periodic box (minimum image), box[] required */
@@ -138,6 +139,88 @@ int encore_npcf(encore_ctx* ctx, const encore_grid* grid, int npcf, int lmax, in
                 const double* edges, uint32_t flags, double volume, double* zeta,
                 size_t zeta_len, const int64_t* primary_subset, int64_t n_subset,
                 void* stream);
+
+/*
+ * The same multiplets for several catalogs at once (one job per grid), with every
+ * point of each catalog a primary.  All jobs share npcf, lmax, the bins and the
+ * flags.  The gather runs as ONE persistent launch per slice of primaries: waves
+ * pull (catalog, primary, bin group) work items from device work queues, so
+ * catalogs of uneven size and neighbour count share the GPU without per-job
+ * launches.  The coupling and FP64 sums stay per job.
+ *  grids   [njobs] grids built on ctx (may repeat).
+ *  zeta    host FP64 [njobs][n_multiplets * n_bin_tuples].
+ *  zeta_len length of zeta in elements (>= njobs * n_multiplets * n_bin_tuples).
+ * ENCORE_NORMALIZE uses each periodic grid's box volume.  Errors as encore_npcf.
+ */
+int encore_npcf_batch(encore_ctx* ctx, const encore_grid* const* grids, int njobs, int npcf,
+                      int lmax, int nbins, const double* edges, uint32_t flags, double* zeta,
+                      size_t zeta_len, void* stream);
+
+/*
+ * Serving loop.  A server accepts catalog jobs from any thread and runs them on
+ * its lanes (worker threads, each with its own HIP stream and workspaces) on the
+ * context's device.  Every job is the estimator of encore_npcf over every point
+ * of its catalog (Section 3.2.1), with its own N, lmax, bins and precision.
+ *
+ *  - Admission: jobs wait in arrival order; the head is admitted while its
+ *    device-memory footprint fits in hbm_budget minus what admitted jobs hold,
+ *    and fewer than max_active jobs are admitted.  An admitted job keeps its grid
+ *    and accumulated sums on the device until it completes.
+ *  - Continuous batching: each lane iteration runs one slice of at most
+ *    slice_rows primaries taken, oldest job first, from every admitted idle job
+ *    of the same class (same npcf, lmax, bins, precision and parity) in one
+ *    persistent gather launch; jobs that arrive meanwhile join at the next
+ *    iteration.  Lanes run concurrently, so their work overlaps on the device.
+ *  - A job's rows are reduced in a fixed order that depends only on the job, so
+ *    its result is bit-identical to encore_npcf on the same catalog whatever it
+ *    shares the device with.
+ *  - A job that fails (invalid catalog, device allocation failure) fails alone;
+ *    its error is returned by encore_server_wait.
+ * Lane workspaces (a~ of one slice, coupling partial sums) come on top of the
+ * budget: at most slice_rows x (nbins x (lmax+1)(lmax+2)/2 x 8 bytes in FP32,
+ * 16 in FP64) each, plus a few MB.
+ */
+typedef struct encore_server encore_server;
+
+/* Create a server on ctx (which must outlive it).
+ *  hbm_budget  device bytes that admitted jobs may hold together (> 0).
+ *  n_lanes     worker threads / streams (1..8).
+ *  max_active  admitted jobs at once (>= 1).
+ *  slice_rows  primaries per lane iteration (>= 1).
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+int encore_server_create(encore_ctx* ctx, size_t hbm_budget, int n_lanes, int max_active,
+                         int64_t slice_rows, encore_server** out);
+
+/* Submit one job; the catalog (host pos [n][3], w [n], box[3] when periodic) and
+ * edges are copied, so the caller may free them on return.  flags: precision,
+ * ENCORE_ALLPARITY, ENCORE_PERIODIC (box required), ENCORE_DMR (n_data as in
+ * encore_build_grid), ENCORE_NORMALIZE (periodic only: V = box volume).  r_max is
+ * edges[nbins].  *job_id receives the job's id.
+ * Errors: EINVAL (bad arguments, server shutting down), ESIZE (footprint larger
+ * than the whole budget), EUNSUPPORTED.  Errors found while the job runs
+ * (non-finite input, points outside the box) are reported by encore_server_wait. */
+int encore_server_submit(encore_server* srv, const double* pos, const double* w, int64_t n,
+                         int64_t n_data, const double* box, int npcf, int lmax, int nbins,
+                         const double* edges, uint32_t flags, int64_t* job_id);
+
+/* Wait for a job (timeout_s < 0: no limit; 0: poll).  On success writes zeta
+ * (host FP64 [n_multiplets * n_bin_tuples], layout as encore_npcf) and, if times
+ * is not NULL, times[4] = submit, admit, first slice start, done, in seconds since
+ * the server was created; the job's record is then released (wait once per job).
+ * Errors: EAGAIN (not finished: the record is kept), ESIZE (zeta_len too small:
+ * record kept), EINVAL (unknown or collected id), or the job's own failure code
+ * (record released). */
+int encore_server_wait(encore_server* srv, int64_t job_id, double timeout_s, double* zeta,
+                       size_t zeta_len, double* times);
+
+/* Counters: out[12] = submitted, done, failed, queued, admitted, bytes held by
+ * admitted jobs, peak of that, primaries run, slices run, gather ms, coupling ms
+ * (summed over lanes), lane workspace bytes.  Errors: EINVAL, ESIZE (out_len < 12). */
+int encore_server_stats(encore_server* srv, double* out, size_t out_len);
+
+/* Finish every submitted job, stop the lanes and free the server (NULL: no-op).
+ * Results not collected with encore_server_wait are discarded. */
+int encore_server_destroy(encore_server* srv);
 
 /* One-shot form: build a grid from host arrays, run encore_npcf, free the grid.
  * r_max = edges[nbins]; box may be NULL for a non-periodic catalog. */

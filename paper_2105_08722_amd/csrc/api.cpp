@@ -1,7 +1,6 @@
-// C ABI of libencore (declared in include/encore.h).
-//
-// One encore_npcf call runs, on one HIP stream:
-//   primary list -> [gather a~ for a batch of primaries -> couple into T] x batches
+// C ABI of libencore (declared in include/encore.h): contexts, grids and the
+// synchronous entry points.  One encore_npcf call runs on one HIP stream:
+//   primary list -> [gather a~ for a slice of primaries -> couple -> reduce into T] x slices
 //   -> contract T with the coupling terms -> zeta (FP64) -> host.
 #include <hip/hip_runtime.h>
 
@@ -10,261 +9,46 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
-#include <tuple>
 #include <vector>
 
-#include "../../include/encore.h"
-#include "device.h"
-#include "internal.h"
-
-namespace encore {
-
-static thread_local std::string g_err;
-void set_error(const std::string& msg) { g_err = msg; }
-const char* get_error() { return g_err.c_str(); }
-
-}  // namespace encore
+#include "engine.h"
 
 using namespace encore;
 
 namespace {
 
-// device copies of the tables for one (N, lmax, parity, nbins)
-struct DevTables {
-    int N = 0, lmax = 0, nbins = 0;
-    bool allparity = false;
-    int64_t nlam = 0, nB = 0, ntuple = 0, nterm = 0;
-    int32_t* tuple_off = nullptr;
-    int32_t* tuple_flags = nullptr;
-    int32_t* btab = nullptr;
-    int32_t* term_start = nullptr;
-    int32_t* term_tuple = nullptr;
-    double* term_coef = nullptr;
-    double* kappa = nullptr;
-    double* gamma = nullptr;
-};
-
-struct Buf {
-    void* p = nullptr;
-    size_t n = 0;
-};
-
-}  // namespace
-
-struct encore_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    std::map<std::tuple<int, int, bool, int>, DevTables> tables;
-    Buf alm, T, zeta, prim, bscale, misc;
-    double timings[6] = {0, 0, 0, 0, 0, 0};
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    int live_grids = 0;
-    std::mutex mu;
-};
-
-struct encore_grid {
-    encore_ctx* ctx = nullptr;
-    DevGrid g;
-};
-
-namespace {
-
-int fail(int code, const std::string& msg)
+// Primary list (sorted indices) into x.prim; returns count in *np.
+int make_primaries(Exec& x, const encore_grid* grid, const int64_t* subset, int64_t k, int64_t* np)
 {
-    set_error(msg);
-    return code;
-}
-
-int hip_fail(hipError_t e, const char* what)
-{
-    return fail(e == hipErrorOutOfMemory ? ENCORE_ENOMEM : ENCORE_EDEVICE,
-                std::string(what) + ": " + hipGetErrorString(e));
-}
-
-#define HIPTRY(x)                                          \
-    do {                                                   \
-        hipError_t e__ = (x);                              \
-        if (e__ != hipSuccess) return hip_fail(e__, #x);   \
-    } while (0)
-
-int ensure(Buf& b, size_t bytes)
-{
-    if (b.n >= bytes && b.p) return ENCORE_OK;
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.n = 0;
-    const size_t want = std::max<size_t>(bytes, 256);
-    hipError_t e = hipMalloc(&b.p, want);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
-    b.n = want;
-    return ENCORE_OK;
-}
-
-bool valid_lmax(int N, int lmax)
-{
-    if (lmax < 0) return false;
-    switch (N) {
-    case 3: case 4: return lmax <= kMaxLmax;
-    case 5: return lmax <= 5;
-    case 6: return lmax <= 4;
-    }
-    return false;
-}
-
-template <typename V>
-int upload(V*& dst, const std::vector<V>& src)
-{
-    const size_t bytes = std::max<size_t>(1, src.size()) * sizeof(V);
-    HIPTRY(hipMalloc(&dst, bytes));
-    if (!src.empty()) HIPTRY(hipMemcpy(dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice));
-    return ENCORE_OK;
-}
-
-int get_tables(encore_ctx* ctx, int N, int lmax, bool allparity, int nbins, DevTables** out)
-{
-    auto key = std::make_tuple(N, lmax, allparity, nbins);
-    auto it = ctx->tables.find(key);
-    if (it != ctx->tables.end()) { *out = &it->second; return ENCORE_OK; }
-    const TermTable& tt = term_table(N, lmax, allparity);
-    DevTables d;
-    d.N = N; d.lmax = lmax; d.nbins = nbins; d.allparity = allparity;
-    d.nlam = tt.nlam;
-    const int K = N - 1;
-    std::vector<int32_t> bt = enumerate_bin_tuples(N, nbins);
-    d.nB = (int64_t)bt.size() / K;
-    d.ntuple = tt.ntuple;
-    d.nterm = (int64_t)tt.coef.size();
-    std::vector<int32_t> toff(tt.ntuple * K), tflags(tt.ntuple);
-    for (int64_t t = 0; t < tt.ntuple; ++t) {
-        int f = 0, neg = 0;
-        for (int k = 0; k < K; ++k) {
-            const int l = tt.tuple_l[t * K + k], m = tt.tuple_m[t * K + k];
-            toff[t * K + k] = l * (l + 1) / 2 + std::abs(m);
-            if (m < 0) {
-                f |= 1 << k;                 // conjugate
-                if (std::abs(m) & 1) neg ^= 1;  // (-1)^m
-            }
-        }
-        if (neg) f |= 1 << 8;
-        if (tt.tuple_odd[t]) f |= 1 << 16;
-        tflags[t] = f;
-    }
-    // terms sorted by multiplet (they are generated in multiplet order)
-    std::vector<int32_t> tstart(tt.nlam + 1, 0);
-    for (int32_t l : tt.lam) tstart[l + 1]++;
-    for (int64_t l = 0; l < tt.nlam; ++l) tstart[l + 1] += tstart[l];
-    const int nlm = (lmax + 1) * (lmax + 2) / 2;
-    std::vector<double> kap(nlm), gam(nlm);
-    gather_tables(lmax, kap.data(), gam.data());
-    int rc;
-    if ((rc = upload(d.tuple_off, toff)) || (rc = upload(d.tuple_flags, tflags)) ||
-        (rc = upload(d.btab, bt)) || (rc = upload(d.term_start, tstart)) ||
-        (rc = upload(d.term_tuple, tt.term_tuple)) || (rc = upload(d.term_coef, tt.coef)) ||
-        (rc = upload(d.kappa, kap)) || (rc = upload(d.gamma, gam)))
-        return rc;
-    auto res = ctx->tables.emplace(key, d);
-    *out = &res.first->second;
-    return ENCORE_OK;
-}
-
-void free_tables(DevTables& d)
-{
-    for (void* p : {(void*)d.tuple_off, (void*)d.tuple_flags, (void*)d.btab, (void*)d.term_start,
-                    (void*)d.term_tuple, (void*)d.term_coef, (void*)d.kappa, (void*)d.gamma})
-        if (p) (void)hipFree(p);
-}
-
-int check_edges(const double* edges, int nbins)
-{
-    if (!edges) return fail(ENCORE_EINVAL, "edges is NULL");
-    if (nbins < 1 || nbins > kMaxBins)
-        return fail(ENCORE_EINVAL, "nbins must be in 1.." + std::to_string(kMaxBins));
-    if (!(edges[0] > 0.0) || !std::isfinite(edges[0]))
-        return fail(ENCORE_EINVAL, "edges[0] must be > 0 (zero separations have no direction)");
-    for (int b = 0; b < nbins; ++b)
-        if (!(edges[b + 1] > edges[b]) || !std::isfinite(edges[b + 1]))
-            return fail(ENCORE_EINVAL, "edges must be finite and strictly increasing");
-    return ENCORE_OK;
-}
-
-int precision_of(uint32_t flags, int* prec)
-{
-    switch (flags & ENCORE_PREC_MASK) {
-    case ENCORE_PREC_FP64: *prec = 0; return ENCORE_OK;
-    case ENCORE_PREC_FP32: *prec = 1; return ENCORE_OK;
-    case ENCORE_PREC_SPLITBF16:
-        return fail(ENCORE_EUNSUPPORTED, "ENCORE_PREC_SPLITBF16 coupling is not built in this version");
-    }
-    return fail(ENCORE_EINVAL, "unknown precision flag");
-}
-
-int check_grid_edges(const encore_grid* grid, const double* edges, int nbins)
-{
-    const DevGrid& g = grid->g;
-    if (edges[nbins] > g.r_max * (1.0 + 1e-12))
-        return fail(ENCORE_EINVAL, "edges[nbins] exceeds the r_max the grid was built for");
-    if (g.periodic && (2.0 * edges[nbins] > g.Lx || 2.0 * edges[nbins] > g.Ly || 2.0 * edges[nbins] > g.Lz))
-        return fail(ENCORE_EINVAL, "periodic box: edges[nbins] must be <= box/2 on every axis");
-    return ENCORE_OK;
-}
-
-// Primary list (sorted indices) into ctx->prim; returns count in *np.
-int make_primaries(encore_ctx* ctx, const encore_grid* grid, const int64_t* subset, int64_t k,
-                   int64_t* np, hipStream_t s)
-{
+    const hipStream_t s = x.s;
     const int64_t n = grid->g.n;
     if (!subset) {
-        int rc = ensure(ctx->prim, sizeof(int32_t) * std::max<int64_t>(n, 1));
+        int rc = ensure(x.prim, sizeof(int32_t) * std::max<int64_t>(n, 1));
         if (rc) return rc;
-        HIPTRY((hipError_t)launch_iota((int32_t*)ctx->prim.p, n, s));
+        HIPTRY((hipError_t)launch_iota((int32_t*)x.prim.p, n, s));
         *np = n;
         return ENCORE_OK;
     }
     if (k < 0) return fail(ENCORE_EINVAL, "n_subset < 0");
-    int rc = ensure(ctx->prim, sizeof(int32_t) * std::max<int64_t>(k, 1));
+    int rc = ensure(x.prim, sizeof(int32_t) * std::max<int64_t>(k, 1));
     if (rc) return rc;
-    if ((rc = ensure(ctx->misc, sizeof(int64_t) * std::max<int64_t>(k, 1) + 16))) return rc;
-    int* d_bad = (int*)ctx->misc.p;
-    int64_t* d_idx = (int64_t*)((char*)ctx->misc.p + 16);
+    if ((rc = ensure(x.misc, sizeof(int64_t) * std::max<int64_t>(k, 1) + 16))) return rc;
+    int* d_bad = (int*)x.misc.p;
+    int64_t* d_idx = (int64_t*)((char*)x.misc.p + 16);
     int bad = 0;
     HIPTRY(hipMemcpyAsync(d_bad, &bad, sizeof(int), hipMemcpyHostToDevice, s));
     if (k > 0) {
         HIPTRY(hipMemcpyAsync(d_idx, subset, sizeof(int64_t) * k, hipMemcpyHostToDevice, s));
-        HIPTRY((hipError_t)launch_map_subset(d_idx, k, grid->g.inv, n, (int32_t*)ctx->prim.p, d_bad, s));
+        HIPTRY((hipError_t)launch_map_subset(d_idx, k, grid->g.inv, n, (int32_t*)x.prim.p, d_bad, s));
     }
     HIPTRY(hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPTRY(hipStreamSynchronize(s));
     if (bad) return fail(ENCORE_EINVAL, "primary_subset holds an index outside [0, n)");
     *np = k;
     return ENCORE_OK;
-}
-
-void fill_gather_args(GatherArgs& a, const DevGrid& g, const double* edges, int nbins)
-{
-    memset(&a, 0, sizeof(a));
-    a.P = g.P;
-    a.cell_start = g.cell_start;
-    a.ncx = g.ncx; a.ncy = g.ncy; a.ncz = g.ncz;
-    a.ox = g.ox; a.oy = g.oy; a.oz = g.oz;
-    a.csx = g.csx; a.csy = g.csy; a.csz = g.csz;
-    a.periodic = g.periodic;
-    a.Lx = g.Lx; a.Ly = g.Ly; a.Lz = g.Lz;
-    a.nbins = nbins;
-    for (int b = 0; b <= nbins; ++b) a.e2[b] = edges[b] * edges[b];
-}
-
-double cell_divisor()
-{
-    const char* s = getenv("ENCORE_CELL_DIVISOR");
-    if (s) {
-        const double v = atof(s);
-        if (v >= 1.0 && v <= 32.0) return v;
-    }
-    return 6.0;   // cell side r_max / 6: measured best of {4, 6, 8, 10}
 }
 
 int build_grid_impl(encore_ctx* ctx, const double* pos, const double* w, int64_t n, int64_t n_data,
@@ -276,16 +60,13 @@ int build_grid_impl(encore_ctx* ctx, const double* pos, const double* w, int64_t
     if (n < 1) return fail(ENCORE_EINVAL, "n must be >= 1");
     if (!(r_max > 0.0) || !std::isfinite(r_max)) return fail(ENCORE_EINVAL, "r_max must be finite and > 0");
     const bool periodic = flags & ENCORE_PERIODIC;
-    double bx[3] = {0, 0, 0};
     if (periodic) {
         if (!box) return fail(ENCORE_EINVAL, "ENCORE_PERIODIC needs box");
-        for (int a = 0; a < 3; ++a) {
+        for (int a = 0; a < 3; ++a)
             if (!(box[a] > 0.0) || !std::isfinite(box[a])) return fail(ENCORE_EINVAL, "box must be > 0");
-            bx[a] = box[a];
-        }
     }
     HIPTRY(hipSetDevice(ctx->device));
-    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    const hipStream_t s = stream ? (hipStream_t)stream : ctx->main.s;
     const double* d_pos = pos;
     const double* d_w = w;
     double* tmp_pos = nullptr;
@@ -304,21 +85,136 @@ int build_grid_impl(encore_ctx* ctx, const double* pos, const double* w, int64_t
     }
     auto* gr = new encore_grid();
     gr->ctx = ctx;
-    char err[256] = {0};
-    const int rc = grid_build(gr->g, d_pos, d_w, n, n_data, (flags & ENCORE_DMR) != 0, periodic, bx, r_max,
-                              r_max / cell_divisor(), s, err, sizeof(err));
+    const int rc = build_grid_dev(ctx->device, d_pos, d_w, n, n_data, (flags & ENCORE_DMR) != 0,
+                                  periodic ? box : nullptr, r_max, s, gr->g);
     if (tmp_pos) (void)hipFree(tmp_pos);
     if (tmp_w) (void)hipFree(tmp_w);
     if (rc != 0) {
         delete gr;
-        return fail(rc == -1 ? ENCORE_EINVAL : (rc == -3 ? ENCORE_ENOMEM : ENCORE_EDEVICE), err);
+        return rc;
     }
-    {
-        std::lock_guard<std::mutex> lock(ctx->mu);
-        ctx->live_grids++;
-    }
+    ctx->live_grids++;
     *out = gr;
     return ENCORE_OK;
+}
+
+// Grids of the call: checks and the volume used by ENCORE_NORMALIZE.
+int check_grids(const encore_grid* const* grids, int njobs, const encore_ctx* ctx, const double* edges,
+                int nbins, uint32_t flags, double volume)
+{
+    int rc;
+    for (int j = 0; j < njobs; ++j) {
+        if (!grids[j]) return fail(ENCORE_EINVAL, "NULL grid");
+        if (grids[j]->ctx != ctx) return fail(ENCORE_EINVAL, "grid belongs to another context");
+        if ((rc = check_grid_edges(grids[j]->g, edges, nbins))) return rc;
+        if ((flags & ENCORE_NORMALIZE) && !(volume > 0.0) && !grids[j]->g.periodic)
+            return fail(ENCORE_EINVAL, "ENCORE_NORMALIZE needs volume > 0 without a periodic box");
+    }
+    return ENCORE_OK;
+}
+
+struct JobRows {
+    const encore_grid* grid;
+    const int32_t* prim;   // device
+    int64_t nprim;
+};
+
+// The hot path over several jobs on the context's main exec (ctx->mu held):
+// slices of at most cap_rows rows, cut only at each job's split boundaries,
+// then one contraction per job; zeta [njobs][nlam][nB] to the host.
+int run_jobs(encore_ctx* ctx, const std::vector<JobRows>& jobs, const NpcfPlan& pl, uint32_t flags,
+             const double* edges, double volume, double* zeta)
+{
+    Exec& x = ctx->main;
+    const hipStream_t s = x.s;
+    const int njobs = (int)jobs.size();
+    const size_t need = (size_t)(pl.nlam * pl.nB);
+    int rc;
+    DevTables* tb = nullptr;
+    if ((rc = get_tables(ctx, pl.N, pl.lmax, pl.allparity, pl.nbins, &tb))) return rc;
+    const int64_t outs = tb->ntuple * tb->nB;
+    const int64_t cap = cap_rows(pl);
+    if ((rc = ensure(x.Tjob, sizeof(double) * (size_t)(njobs * outs)))) return rc;
+    if ((rc = ensure(x.zeta, sizeof(double) * (size_t)njobs * std::max<size_t>(need, 1)))) return rc;
+    if ((rc = ensure(x.misc, 64))) return rc;
+    unsigned long long* d_pairs = (unsigned long long*)x.misc.p;
+    HIPTRY((hipError_t)launch_fill((double*)x.Tjob.p, njobs * outs, 0.0, s));
+    HIPTRY((hipError_t)launch_fill((double*)d_pairs, 1, 0.0, s));   // zero bits = 0ull
+
+    std::vector<int64_t> srows(jobs.size());
+    for (size_t j = 0; j < jobs.size(); ++j) srows[j] = job_split_rows(pl, tb, jobs[j].nprim, cap);
+
+    double t_gather = 0.0, t_couple = 0.0;
+    int nslice = 0;
+    size_t jcur = 0;
+    int64_t jpos = 0;   // rows of jobs[jcur] already done
+    std::vector<Chunk> chunks;
+    while (jcur < jobs.size()) {
+        chunks.clear();
+        int64_t rows = 0;
+        while (jcur < jobs.size() && rows < cap && chunks.size() < 4096) {
+            const JobRows& J = jobs[jcur];
+            const int64_t sr = srows[jcur];
+            int64_t take = J.nprim - jpos;
+            if (take > cap - rows) take = (cap - rows) / sr * sr;   // whole splits only
+            if (take == 0 && J.nprim > jpos) break;                  // next slice
+            if (take > 0) {
+                chunks.push_back(Chunk{&J.grid->g, J.prim, jpos, jpos + take, sr,
+                                       (double*)x.Tjob.p + (size_t)jcur * outs});
+                rows += take;
+                jpos += take;
+            }
+            if (jpos >= J.nprim) { ++jcur; jpos = 0; }
+        }
+        if (rows == 0) break;
+        if ((rc = run_slice(x, pl, tb, edges, chunks, &t_gather, &t_couple))) return rc;
+        ++nslice;
+    }
+    std::vector<double> sc;
+    if (flags & ENCORE_NORMALIZE) {
+        if ((rc = ensure(x.bscale, sizeof(double) * (size_t)(njobs * std::max<int64_t>(pl.nB, 1))))) return rc;
+        for (int j = 0; j < njobs; ++j) {
+            const DevGrid& g = jobs[j].grid->g;
+            const double V = volume > 0.0 ? volume : g.Lx * g.Ly * g.Lz;
+            std::vector<double> one = bin_scale(pl, edges, V);
+            sc.insert(sc.end(), one.begin(), one.end());
+        }
+        HIPTRY(hipMemcpyAsync(x.bscale.p, sc.data(), sizeof(double) * sc.size(), hipMemcpyHostToDevice, s));
+    }
+    HIPTRY(hipEventRecord(x.ev[1], s));
+    for (int j = 0; j < njobs; ++j) {
+        const double* bs = (flags & ENCORE_NORMALIZE) ? (const double*)x.bscale.p + (size_t)j * pl.nB : nullptr;
+        if ((rc = contract_job(x, pl, tb, (const double*)x.Tjob.p + (size_t)j * outs, bs,
+                               (double*)x.zeta.p + (size_t)j * need)))
+            return rc;
+    }
+    HIPTRY(hipEventRecord(x.ev[2], s));
+    HIPTRY(hipMemcpyAsync(zeta, x.zeta.p, sizeof(double) * need * njobs, hipMemcpyDeviceToHost, s));
+    HIPTRY(hipEventRecord(x.ev[3], s));
+    HIPTRY(hipEventSynchronize(x.ev[3]));
+    float ms_c = 0.f, ms_tot = 0.f;
+    HIPTRY(hipEventElapsedTime(&ms_c, x.ev[1], x.ev[2]));
+    HIPTRY(hipEventElapsedTime(&ms_tot, x.ev[0], x.ev[3]));
+    unsigned long long pairs = 0;
+    HIPTRY(hipMemcpy(&pairs, d_pairs, sizeof(pairs), hipMemcpyDeviceToHost));
+    ctx->timings[0] = ms_tot;
+    ctx->timings[1] = t_gather;
+    ctx->timings[2] = t_couple;
+    ctx->timings[3] = ms_c;
+    ctx->timings[4] = nslice;
+    ctx->timings[5] = (double)pairs;
+    return ENCORE_OK;
+}
+
+// Runs f with the main exec on the caller's stream (if any); ctx->mu is held.
+template <typename F>
+int on_stream(encore_ctx* ctx, void* stream, F&& f)
+{
+    hipStream_t own = ctx->main.s;
+    if (stream) ctx->main.s = (hipStream_t)stream;
+    const int rc = f();
+    ctx->main.s = own;
+    return rc;
 }
 
 }  // namespace
@@ -327,7 +223,7 @@ extern "C" {
 
 const char* encore_last_error(void) { return get_error(); }
 
-const char* encore_version(void) { return "encore-mi355x 0.1 (gfx950)"; }
+const char* encore_version(void) { return "encore-mi355x 0.2 (gfx950)"; }
 
 int encore_create(int hip_device, encore_ctx** out)
 {
@@ -339,11 +235,11 @@ int encore_create(int hip_device, encore_ctx** out)
     HIPTRY(hipSetDevice(hip_device));
     auto* c = new encore_ctx();
     c->device = hip_device;
-    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
-    for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&c->ev[i]);
-    if (e != hipSuccess) {
+    const int rc = exec_init(c->main);
+    if (rc) {
+        exec_release(c->main);
         delete c;
-        return hip_fail(e, "encore_create");
+        return rc;
     }
     *out = c;
     return ENCORE_OK;
@@ -354,13 +250,13 @@ int encore_destroy(encore_ctx* ctx)
     if (!ctx) return ENCORE_OK;
     if (ctx->live_grids > 0) return fail(ENCORE_EINVAL, "free every grid before destroying the context");
     (void)hipSetDevice(ctx->device);
-    (void)hipStreamSynchronize(ctx->stream);
-    for (auto& kv : ctx->tables) free_tables(kv.second);
-    for (Buf* b : {&ctx->alm, &ctx->T, &ctx->zeta, &ctx->prim, &ctx->bscale, &ctx->misc})
-        if (b->p) (void)hipFree(b->p);
-    for (int i = 0; i < 4; ++i)
-        if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
-    (void)hipStreamDestroy(ctx->stream);
+    exec_release(ctx->main);
+    for (auto& kv : ctx->tables) {
+        DevTables& d = kv.second;
+        for (void* p : {(void*)d.tuple_off, (void*)d.tuple_flags, (void*)d.btab, (void*)d.term_start,
+                        (void*)d.term_tuple, (void*)d.term_coef, (void*)d.kappa, (void*)d.gamma})
+            if (p) (void)hipFree(p);
+    }
     delete ctx;
     return ENCORE_OK;
 }
@@ -384,10 +280,7 @@ int encore_free_grid(encore_grid* grid)
     (void)hipSetDevice(grid->ctx->device);
     (void)hipDeviceSynchronize();
     grid_free(grid->g);
-    {
-        std::lock_guard<std::mutex> lock(grid->ctx->mu);
-        grid->ctx->live_grids--;
-    }
+    grid->ctx->live_grids--;
     delete grid;
     return ENCORE_OK;
 }
@@ -454,136 +347,63 @@ int encore_npcf(encore_ctx* ctx, const encore_grid* grid, int npcf, int lmax, in
                 const int64_t* primary_subset, int64_t n_subset, void* stream)
 {
     if (!ctx || !grid) return fail(ENCORE_EINVAL, "NULL ctx or grid");
-    if (grid->ctx != ctx) return fail(ENCORE_EINVAL, "grid belongs to another context");
-    if (npcf < 3 || npcf > 6) return fail(ENCORE_EINVAL, "npcf must be 3..6");
-    if (!valid_lmax(npcf, lmax)) return fail(ENCORE_EINVAL, "lmax out of range for this N");
+    NpcfPlan pl;
     int rc;
-    if ((rc = check_edges(edges, nbins))) return rc;
-    if ((rc = check_grid_edges(grid, edges, nbins))) return rc;
-    int prec = 0;
-    if ((rc = precision_of(flags, &prec))) return rc;
-    const bool allparity = flags & ENCORE_ALLPARITY;
-    const int64_t nlam = (int64_t)enumerate_multiplets(npcf, lmax, allparity).size() / multiplet_width(npcf);
-    const int64_t nB = binomial(nbins, npcf - 1);
-    const size_t need = (size_t)(nlam * nB);
+    if ((rc = plan_call(npcf, lmax, nbins, edges, flags, &pl))) return rc;
+    if ((rc = check_grids(&grid, 1, ctx, edges, nbins, flags, volume))) return rc;
+    const size_t need = (size_t)(pl.nlam * pl.nB);
     if (!zeta && need > 0) return fail(ENCORE_EINVAL, "zeta is NULL");
     if (zeta_len < need) return fail(ENCORE_ESIZE, "zeta needs " + std::to_string(need) + " elements");
-    double V = 0.0;
-    if (flags & ENCORE_NORMALIZE) {
-        V = volume;
-        if (!(V > 0.0)) {
-            if (!grid->g.periodic) return fail(ENCORE_EINVAL, "ENCORE_NORMALIZE needs volume > 0 without a periodic box");
-            V = grid->g.Lx * grid->g.Ly * grid->g.Lz;
-        }
-    }
     std::lock_guard<std::mutex> lock(ctx->mu);
     for (double& t : ctx->timings) t = 0.0;
     if (need == 0) return ENCORE_OK;
     HIPTRY(hipSetDevice(ctx->device));
-    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
-    HIPTRY(hipEventRecord(ctx->ev[0], s));
+    return on_stream(ctx, stream, [&]() {
+        Exec& x = ctx->main;
+        HIPTRY(hipEventRecord(x.ev[0], x.s));
+        int64_t nprim = 0;
+        int rc2;
+        if ((rc2 = make_primaries(x, grid, primary_subset, n_subset, &nprim))) return rc2;
+        std::vector<JobRows> jobs{JobRows{grid, (const int32_t*)x.prim.p, nprim}};
+        return run_jobs(ctx, jobs, pl, flags, edges, volume, zeta);
+    });
+}
 
-    DevTables* tb = nullptr;
-    if ((rc = get_tables(ctx, npcf, lmax, allparity, nbins, &tb))) return rc;
-    int64_t nprim = 0;
-    if ((rc = make_primaries(ctx, grid, primary_subset, n_subset, &nprim, s))) return rc;
-
-    const int nlm = (lmax + 1) * (lmax + 2) / 2;
-    const size_t per_prim = (size_t)nbins * nlm * 2 * (prec == 0 ? 8 : 4);
-    const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nprim, (int64_t)((size_t)2 << 30) / per_prim));
-    // splits of the primary range in the coupling kernel (parallelism of the sum over i)
-    const int64_t outs = tb->ntuple * tb->nB;
-    const int64_t nsplit = couple_nsplit(npcf - 1, nbins, tb->ntuple, tb->nB, batch);
-
-    if ((rc = ensure(ctx->alm, per_prim * (size_t)batch))) return rc;
-    if ((rc = ensure(ctx->T, sizeof(double) * (size_t)(nsplit * outs)))) return rc;
-    if ((rc = ensure(ctx->zeta, sizeof(double) * need))) return rc;
-    HIPTRY((hipError_t)launch_fill((double*)ctx->T.p, nsplit * outs, 0.0, s));
-    const double* d_bscale = nullptr;
-    if (flags & ENCORE_NORMALIZE) {
-        std::vector<int32_t> bt = enumerate_bin_tuples(npcf, nbins);
-        std::vector<double> sc(nB);
-        const int K = npcf - 1;
-        for (int64_t b = 0; b < nB; ++b) {
-            double v = V;
-            for (int k = 0; k < K; ++k) {
-                const double lo = edges[bt[b * K + k]], hi = edges[bt[b * K + k] + 1];
-                v *= 4.0 * M_PI / 3.0 * (hi * hi * hi - lo * lo * lo);
-            }
-            sc[b] = 1.0 / v;
+int encore_npcf_batch(encore_ctx* ctx, const encore_grid* const* grids, int njobs, int npcf, int lmax,
+                      int nbins, const double* edges, uint32_t flags, double* zeta, size_t zeta_len,
+                      void* stream)
+{
+    if (!ctx || !grids) return fail(ENCORE_EINVAL, "NULL ctx or grids");
+    if (njobs < 1) return fail(ENCORE_EINVAL, "njobs must be >= 1");
+    NpcfPlan pl;
+    int rc;
+    if ((rc = plan_call(npcf, lmax, nbins, edges, flags, &pl))) return rc;
+    if ((rc = check_grids(grids, njobs, ctx, edges, nbins, flags, 0.0))) return rc;
+    const size_t need = (size_t)(pl.nlam * pl.nB);
+    if (!zeta && need > 0) return fail(ENCORE_EINVAL, "zeta is NULL");
+    if (zeta_len < need * (size_t)njobs)
+        return fail(ENCORE_ESIZE, "zeta needs " + std::to_string(need * njobs) + " elements");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    for (double& t : ctx->timings) t = 0.0;
+    if (need == 0) return ENCORE_OK;
+    HIPTRY(hipSetDevice(ctx->device));
+    return on_stream(ctx, stream, [&]() {
+        Exec& x = ctx->main;
+        HIPTRY(hipEventRecord(x.ev[0], x.s));
+        // primaries: every point of every catalog, in each grid's cell order
+        int64_t tot = 0;
+        for (int j = 0; j < njobs; ++j) tot += grids[j]->g.n;
+        int rc2;
+        if ((rc2 = ensure(x.prim, sizeof(int32_t) * (size_t)std::max<int64_t>(tot, 1)))) return rc2;
+        std::vector<JobRows> jobs(njobs);
+        int64_t off = 0;
+        for (int j = 0; j < njobs; ++j) {
+            HIPTRY((hipError_t)launch_iota((int32_t*)x.prim.p + off, grids[j]->g.n, x.s));
+            jobs[j] = JobRows{grids[j], (const int32_t*)x.prim.p + off, grids[j]->g.n};
+            off += grids[j]->g.n;
         }
-        if ((rc = ensure(ctx->bscale, sizeof(double) * nB))) return rc;
-        HIPTRY(hipMemcpyAsync(ctx->bscale.p, sc.data(), sizeof(double) * nB, hipMemcpyHostToDevice, s));
-        HIPTRY(hipStreamSynchronize(s));
-        d_bscale = (const double*)ctx->bscale.p;
-    }
-
-    GatherArgs ga;
-    fill_gather_args(ga, grid->g, edges, nbins);
-    ga.kappa = tb->kappa;
-    ga.gamma = tb->gamma;
-    ga.alm = ctx->alm.p;
-    if ((rc = ensure(ctx->misc, 64))) return rc;
-    unsigned long long* d_pairs = (unsigned long long*)ctx->misc.p;
-    HIPTRY(hipMemsetAsync(d_pairs, 0, sizeof(unsigned long long), s));
-    ga.npairs = d_pairs;
-    CoupleArgs ca;
-    memset(&ca, 0, sizeof(ca));
-    ca.alm = ctx->alm.p;
-    ca.P = grid->g.P;
-    ca.nbins = nbins; ca.nlm = nlm; ca.nk = npcf - 1;
-    ca.ntuple = (int)tb->ntuple; ca.nB = (int)tb->nB;
-    ca.tuple_off = tb->tuple_off; ca.tuple_flags = tb->tuple_flags; ca.btab = tb->btab;
-    ca.nsplit = (int)nsplit;
-    ca.T = (double*)ctx->T.p;
-
-    double t_gather = 0.0, t_couple = 0.0;
-    int nlaunch = 0;
-    for (int64_t p0 = 0; p0 < nprim; p0 += batch) {
-        const int np = (int)std::min<int64_t>(batch, nprim - p0);
-        ga.prim = (const int32_t*)ctx->prim.p + p0;
-        ga.nprim = np;
-        HIPTRY(hipEventRecord(ctx->ev[1], s));
-        HIPTRY((hipError_t)launch_gather(ga, lmax, prec, s));
-        HIPTRY(hipEventRecord(ctx->ev[2], s));
-        ca.prim = ga.prim;
-        ca.nprim = np;
-        HIPTRY((hipError_t)launch_couple(ca, prec, s));
-        HIPTRY(hipEventRecord(ctx->ev[3], s));
-        HIPTRY(hipEventSynchronize(ctx->ev[3]));
-        float ms = 0.f;
-        HIPTRY(hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
-        t_gather += ms;
-        HIPTRY(hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]));
-        t_couple += ms;
-        ++nlaunch;
-    }
-    ContractArgs xa;
-    xa.T = (const double*)ctx->T.p;
-    xa.nsplit = (int)nsplit; xa.ntuple = (int)tb->ntuple; xa.nB = (int)tb->nB; xa.nlam = (int)nlam;
-    xa.term_start = tb->term_start; xa.term_tuple = tb->term_tuple; xa.term_coef = tb->term_coef;
-    xa.bscale = d_bscale;
-    xa.zeta = (double*)ctx->zeta.p;
-    HIPTRY(hipEventRecord(ctx->ev[1], s));
-    HIPTRY((hipError_t)launch_contract(xa, s));
-    HIPTRY(hipEventRecord(ctx->ev[2], s));
-    std::vector<double> host(need);
-    HIPTRY(hipMemcpyAsync(host.data(), ctx->zeta.p, sizeof(double) * need, hipMemcpyDeviceToHost, s));
-    HIPTRY(hipEventRecord(ctx->ev[3], s));
-    HIPTRY(hipEventSynchronize(ctx->ev[3]));
-    float ms_c = 0.f, ms_tot = 0.f;
-    HIPTRY(hipEventElapsedTime(&ms_c, ctx->ev[1], ctx->ev[2]));
-    HIPTRY(hipEventElapsedTime(&ms_tot, ctx->ev[0], ctx->ev[3]));
-    unsigned long long pairs = 0;
-    HIPTRY(hipMemcpy(&pairs, d_pairs, sizeof(pairs), hipMemcpyDeviceToHost));
-    std::copy(host.begin(), host.end(), zeta);
-    ctx->timings[5] = (double)pairs;
-    ctx->timings[0] = ms_tot;
-    ctx->timings[1] = t_gather;
-    ctx->timings[2] = t_couple;
-    ctx->timings[3] = ms_c;
-    ctx->timings[4] = nlaunch;
-    return ENCORE_OK;
+        return run_jobs(ctx, jobs, pl, flags, edges, 0.0, zeta);
+    });
 }
 
 int encore_npcf_simple(const double* pos, const double* w, int64_t n, int npcf, int lmax, int nbins,
@@ -615,7 +435,7 @@ int encore_debug_alm(encore_ctx* ctx, const encore_grid* grid, int lmax, int nbi
     if (lmax < 0 || lmax > kMaxLmax) return fail(ENCORE_EINVAL, "lmax must be 0..10");
     int rc;
     if ((rc = check_edges(edges, nbins))) return rc;
-    if ((rc = check_grid_edges(grid, edges, nbins))) return rc;
+    if ((rc = check_grid_edges(grid->g, edges, nbins))) return rc;
     int prec = 0;
     if ((flags & ENCORE_PREC_MASK) == ENCORE_PREC_SPLITBF16) prec = 1;   // same FP32 gather
     else if ((rc = precision_of(flags, &prec))) return rc;
@@ -623,42 +443,54 @@ int encore_debug_alm(encore_ctx* ctx, const encore_grid* grid, int lmax, int nbi
     const bool full = flags & ENCORE_DEBUG_FULLGRID;
     std::lock_guard<std::mutex> lock(ctx->mu);
     HIPTRY(hipSetDevice(ctx->device));
-    hipStream_t s = ctx->stream;
+    Exec& x = ctx->main;
+    const hipStream_t s = x.s;
     const int nlm = (lmax + 1) * (lmax + 2) / 2;
     const int64_t per = (int64_t)nbins * nlm * 2;     // reals per primary
-    const int64_t nval = k * per;
-    // requested rows -> sorted indices (ctx->prim), validated
+    // requested rows -> sorted indices (x.prim), validated
     int64_t np = 0;
-    if ((rc = make_primaries(ctx, grid, primaries, k, &np, s))) return rc;
+    if ((rc = make_primaries(x, grid, primaries, k, &np))) return rc;
     std::vector<int32_t> sorted_rows(k);
-    HIPTRY(hipMemcpy(sorted_rows.data(), ctx->prim.p, sizeof(int32_t) * k, hipMemcpyDeviceToHost));
+    HIPTRY(hipMemcpy(sorted_rows.data(), x.prim.p, sizeof(int32_t) * k, hipMemcpyDeviceToHost));
     const int64_t nlaunch = full ? grid->g.n : k;
-    if (full) {
-        if ((rc = make_primaries(ctx, grid, nullptr, 0, &np, s))) return rc;
-    }
-    if ((rc = ensure(ctx->alm, (size_t)(nlaunch * per) * (prec == 0 ? 8 : 4)))) return rc;
-    if ((rc = ensure(ctx->zeta, sizeof(double) * (size_t)(nlaunch * per)))) return rc;
+    if (full && (rc = make_primaries(x, grid, nullptr, 0, &np))) return rc;
+    if ((rc = ensure(x.alm, (size_t)(nlaunch * per) * (prec == 0 ? 8 : 4)))) return rc;
+    if ((rc = ensure(x.zeta, sizeof(double) * (size_t)(nlaunch * per)))) return rc;
+    if ((rc = ensure(x.wprim, sizeof(double) * (size_t)nlaunch))) return rc;
+    if ((rc = ensure(x.segs, sizeof(GatherSeg)))) return rc;
     std::vector<double> kap(nlm), gam(nlm);
     gather_tables(lmax, kap.data(), gam.data());
     double* d_kg = nullptr;
     HIPTRY(hipMalloc(&d_kg, sizeof(double) * 2 * nlm));
     hipError_t e = hipMemcpy(d_kg, kap.data(), sizeof(double) * nlm, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_kg + nlm, gam.data(), sizeof(double) * nlm, hipMemcpyHostToDevice);
+    const DevGrid& g = grid->g;
+    GatherSeg gs;
+    gs.P = g.P; gs.cell_start = g.cell_start; gs.prim = (const int32_t*)x.prim.p;
+    gs.ncx = g.ncx; gs.ncy = g.ncy; gs.ncz = g.ncz; gs.periodic = g.periodic;
+    gs.ox = g.ox; gs.oy = g.oy; gs.oz = g.oz;
+    gs.csx = g.csx; gs.csy = g.csy; gs.csz = g.csz;
+    gs.Lx = g.Lx; gs.Ly = g.Ly; gs.Lz = g.Lz;
+    gs.row0 = 0; gs.nprim = (int)nlaunch;
+    if (e == hipSuccess) e = hipMemcpy(x.segs.p, &gs, sizeof(gs), hipMemcpyHostToDevice);
     GatherArgs ga;
-    fill_gather_args(ga, grid->g, edges, nbins);
+    memset(&ga, 0, sizeof(ga));
+    ga.nbins = nbins;
+    for (int b = 0; b <= nbins; ++b) ga.e2[b] = edges[b] * edges[b];
     ga.kappa = d_kg;
     ga.gamma = d_kg + nlm;
-    ga.alm = ctx->alm.p;
-    ga.prim = (const int32_t*)ctx->prim.p;
-    ga.nprim = (int)nlaunch;
-    if (e == hipSuccess) e = (hipError_t)launch_gather(ga, lmax, prec, s);
-    if (e == hipSuccess)
-        e = (hipError_t)launch_to_double(ctx->alm.p, prec, nlaunch * per, (double*)ctx->zeta.p, s);
+    ga.alm = x.alm.p;
+    ga.wprim = (double*)x.wprim.p;
+    ga.segs = (const GatherSeg*)x.segs.p;
+    ga.nseg = 1;
+    ga.nrows = (int)nlaunch;
+    if (e == hipSuccess) e = (hipError_t)launch_gather(ga, lmax, prec, false, s);
+    if (e == hipSuccess) e = (hipError_t)launch_to_double(x.alm.p, prec, nlaunch * per, (double*)x.zeta.p, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     for (int64_t r = 0; r < k && e == hipSuccess; ++r) {
         // full launch: row of sorted index sorted_rows[r]; else row r
         const int64_t row = full ? sorted_rows[r] : r;
-        e = hipMemcpy(alm_out + r * per, (double*)ctx->zeta.p + row * per, sizeof(double) * per,
+        e = hipMemcpy(alm_out + r * per, (double*)x.zeta.p + row * per, sizeof(double) * per,
                       hipMemcpyDeviceToHost);
     }
     (void)hipFree(d_kg);

@@ -29,7 +29,7 @@ template <> struct C2<float> { using type = float2; };
 template <> struct C2<double> { using type = double2; };
 
 template <typename T, int NK>
-__global__ void __launch_bounds__(kBlock) k_couple(CoupleArgs a, int ptile, int chunk)
+__global__ void __launch_bounds__(kBlock) k_couple(CoupleArgs a, int ptile)
 {
     using V = typename C2<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -42,8 +42,8 @@ __global__ void __launch_bounds__(kBlock) k_couple(CoupleArgs a, int ptile, int 
     const int t = valid ? (int)(gid / a.nB) : 0;
     const int b = valid ? (int)(gid - (int64_t)t * a.nB) : 0;
     const int split = blockIdx.y;
-    const int p_lo = split * chunk;
-    const int p_hi = min(a.nprim, p_lo + chunk);
+    const int p_lo = a.split_lo[split];
+    const int p_hi = a.split_hi[split];
 
     int off[NK];
     T cs[NK];
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(kBlock) k_couple(CoupleArgs a, int ptile, int 
         __syncthreads();
         const V* src = reinterpret_cast<const V*>(a.alm) + (size_t)p0 * per;
         for (int q = threadIdx.x; q < np * per; q += kBlock) tile[q] = src[q];
-        for (int q = threadIdx.x; q < np; q += kBlock) wtile[q] = a.P[a.prim[p0 + q]].w;
+        for (int q = threadIdx.x; q < np; q += kBlock) wtile[q] = a.wprim[p0 + q];
         __syncthreads();
         if (valid) {
             for (int pp = 0; pp < np; ++pp) {
@@ -88,8 +88,7 @@ __global__ void __launch_bounds__(kBlock) k_couple(CoupleArgs a, int ptile, int 
     }
     if (valid) {
         if ((flags >> 8) & 1) acc = -acc;
-        double* dst = a.T + ((size_t)split * a.ntuple + t) * a.nB + b;
-        *dst += acc;
+        a.T[((size_t)split * a.ntuple + t) * a.nB + b] = acc;
     }
 }
 
@@ -102,7 +101,7 @@ constexpr int kNB4 = 10;
 __host__ __device__ constexpr int pair_count(int b1) { return (kNB4 - 1 - b1) * (kNB4 - 2 - b1) / 2; }
 
 template <typename T, int B1>
-__global__ void __launch_bounds__(kBlock) k_couple4(CoupleArgs a, int ptile, int chunk)
+__global__ void __launch_bounds__(kBlock) k_couple4(CoupleArgs a, int ptile)
 {
     using V = typename C2<T>::type;
     constexpr int NA = pair_count(B1);
@@ -115,8 +114,8 @@ __global__ void __launch_bounds__(kBlock) k_couple4(CoupleArgs a, int ptile, int
     const int t = blockIdx.x * kBlock + threadIdx.x;
     const bool valid = t < a.ntuple;
     const int split = blockIdx.y;
-    const int p_lo = split * chunk;
-    const int p_hi = min(a.nprim, p_lo + chunk);
+    const int p_lo = a.split_lo[split];
+    const int p_hi = a.split_hi[split];
 
     int lm0 = 0, lm1 = 0, lm2 = 0, flags = 0;
     if (valid) {
@@ -145,7 +144,7 @@ __global__ void __launch_bounds__(kBlock) k_couple4(CoupleArgs a, int ptile, int
             const int pp = q / per, r = q - pp * per;
             tile[q] = src[(size_t)(p0 + pp) * full + B1 * a.nlm + r];
         }
-        for (int q = threadIdx.x; q < np; q += kBlock) wtile[q] = a.P[a.prim[p0 + q]].w;
+        for (int q = threadIdx.x; q < np; q += kBlock) wtile[q] = a.wprim[p0 + q];
         __syncthreads();
         if (valid) {
             for (int pp = 0; pp < np; ++pp) {
@@ -185,7 +184,7 @@ __global__ void __launch_bounds__(kBlock) k_couple4(CoupleArgs a, int ptile, int
         for (int b = 0; b < B1; ++b) bidx += pair_count(b);
         double* dst = a.T + ((size_t)split * a.ntuple + t) * a.nB + bidx;
 #pragma unroll
-        for (int q = 0; q < NA; ++q) dst[q] += sgn * acc[q];
+        for (int q = 0; q < NA; ++q) dst[q] = sgn * acc[q];
     }
 }
 
@@ -208,7 +207,7 @@ __global__ void __launch_bounds__(kBlock) k_contract(ContractArgs a)
 
 }  // namespace
 
-int couple_nsplit(int nk, int nbins, int64_t ntuple, int64_t nB, int64_t nprim)
+int couple_split_rows(int nk, int nbins, int64_t ntuple, int64_t nB, int64_t nrows)
 {
     int64_t ns;
     if (nk == 3 && nbins == kNB4) {
@@ -218,8 +217,29 @@ int couple_nsplit(int nk, int nbins, int64_t ntuple, int64_t nB, int64_t nprim)
     } else {
         ns = (int64_t)(1 << 20) / std::max<int64_t>(ntuple * nB, 1);
     }
-    ns = std::min<int64_t>(ns, std::max<int64_t>(1, nprim / 64));
-    return (int)std::max<int64_t>(1, std::min<int64_t>(ns, 1024));
+    ns = std::max<int64_t>(1, std::min<int64_t>(ns, 1024));
+    int64_t rows = (nrows + ns - 1) / ns;
+    return (int)std::max<int64_t>(64, rows);
+}
+
+__global__ void k_reduce(ReduceArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= a.per) return;
+    // left fold from the running total, split by split in row order: the same
+    // association however the job's splits were distributed over slices
+    double* dst = a.dst[r] + i;
+    double s = *dst;
+    for (int y = a.red_lo[r]; y < a.red_hi[r]; ++y) s += a.T[(size_t)y * a.per + i];
+    *dst = s;
+}
+
+int launch_reduce(const ReduceArgs& a, hipStream_t stream)
+{
+    if (a.nred == 0 || a.per == 0) return (int)hipSuccess;
+    k_reduce<<<dim3((unsigned)((a.per + kBlock - 1) / kBlock), (unsigned)a.nred), kBlock, 0, stream>>>(a);
+    return (int)hipGetLastError();
 }
 
 int couple_ptile(int nbins, int nlm, int precision)
@@ -230,50 +250,49 @@ int couple_ptile(int nbins, int nlm, int precision)
 }
 
 template <typename T, int B1>
-void launch4(const CoupleArgs& a, int ptile, int chunk, hipStream_t stream)
+void launch4(const CoupleArgs& a, int ptile, hipStream_t stream)
 {
     const int nblk = (a.ntuple + kBlock - 1) / kBlock;
     const size_t lds = (size_t)ptile * (kNB4 - B1) * a.nlm * sizeof(typename C2<T>::type) + 8 * (size_t)ptile;
-    k_couple4<T, B1><<<dim3((unsigned)nblk, (unsigned)a.nsplit), kBlock, lds, stream>>>(a, ptile, chunk);
+    k_couple4<T, B1><<<dim3((unsigned)nblk, (unsigned)a.nsplit), kBlock, lds, stream>>>(a, ptile);
 }
 
 template <typename T>
-void launch4_all(const CoupleArgs& a, int ptile, int chunk, hipStream_t stream)
+void launch4_all(const CoupleArgs& a, int ptile, hipStream_t stream)
 {
-    launch4<T, 0>(a, ptile, chunk, stream);
-    launch4<T, 1>(a, ptile, chunk, stream);
-    launch4<T, 2>(a, ptile, chunk, stream);
-    launch4<T, 3>(a, ptile, chunk, stream);
-    launch4<T, 4>(a, ptile, chunk, stream);
-    launch4<T, 5>(a, ptile, chunk, stream);
-    launch4<T, 6>(a, ptile, chunk, stream);
-    launch4<T, 7>(a, ptile, chunk, stream);
+    launch4<T, 0>(a, ptile, stream);
+    launch4<T, 1>(a, ptile, stream);
+    launch4<T, 2>(a, ptile, stream);
+    launch4<T, 3>(a, ptile, stream);
+    launch4<T, 4>(a, ptile, stream);
+    launch4<T, 5>(a, ptile, stream);
+    launch4<T, 6>(a, ptile, stream);
+    launch4<T, 7>(a, ptile, stream);
+    // bins 8 and 9 cannot be the first bin of a triple: their rows of T are absent
 }
 
 int launch_couple(const CoupleArgs& a, int precision, hipStream_t stream)
 {
     if (a.nk > kMaxK) return (int)hipErrorInvalidValue;
+    if (a.nsplit == 0 || a.ntuple == 0) return (int)hipSuccess;
     if (a.nk == 3 && a.nbins == kNB4) {
-        if (a.nprim == 0 || a.ntuple == 0) return (int)hipSuccess;
         const int ptile = std::max(1, std::min(64, 32768 / (kNB4 * a.nlm * (precision == 0 ? 16 : 8) + 8)));
-        const int chunk = (a.nprim + a.nsplit - 1) / a.nsplit;
-        if (precision == 0) launch4_all<double>(a, ptile, chunk, stream);
-        else launch4_all<float>(a, ptile, chunk, stream);
+        if (precision == 0) launch4_all<double>(a, ptile, stream);
+        else launch4_all<float>(a, ptile, stream);
         return (int)hipGetLastError();
     }
     const int64_t nthreads = (int64_t)a.ntuple * a.nB;
     const int64_t nblk = (nthreads + kBlock - 1) / kBlock;
-    if (nblk == 0 || a.nprim == 0) return (int)hipSuccess;
+    if (nblk == 0) return (int)hipSuccess;
     const int ptile = couple_ptile(a.nbins, a.nlm, precision);
-    const int chunk = (a.nprim + a.nsplit - 1) / a.nsplit;
     const size_t lds = (size_t)ptile * a.nbins * a.nlm * (precision == 0 ? 16 : 8) + 8 * (size_t)ptile;
     dim3 grid((unsigned)nblk, (unsigned)a.nsplit);
 #define ENCORE_COUPLE_CASE(NKV)                                                      \
     case NKV:                                                                        \
         if (precision == 0)                                                          \
-            k_couple<double, NKV><<<grid, kBlock, lds, stream>>>(a, ptile, chunk);   \
+            k_couple<double, NKV><<<grid, kBlock, lds, stream>>>(a, ptile);          \
         else                                                                         \
-            k_couple<float, NKV><<<grid, kBlock, lds, stream>>>(a, ptile, chunk);    \
+            k_couple<float, NKV><<<grid, kBlock, lds, stream>>>(a, ptile);           \
         break;
     switch (a.nk) {
         ENCORE_COUPLE_CASE(2)

@@ -37,57 +37,79 @@ int launch_iota(int32_t* out, int64_t n, hipStream_t stream);
 int launch_map_subset(const int64_t* idx, int64_t k, const int32_t* inv, int64_t n, int32_t* out,
                       int* bad, hipStream_t stream);
 int launch_fill(double* p, int64_t n, double v, hipStream_t stream);
+int launch_fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t stream);
 int launch_to_double(const void* src, int precision, int64_t n, double* dst, hipStream_t stream);
-int couple_ptile(int nbins, int nlm, int precision);
-// primary splits of the coupling kernels (parallelism across the sum over primaries)
-int couple_nsplit(int nk, int nbins, int64_t ntuple, int64_t nB, int64_t nprim);
 
 // ------------------------------------------------------------------ gather
-// Harmonic coefficient gather (eq. binned-discrete-alm): for every primary of the
-// launch, a~^b_lm over all secondaries, written as complex [nprim][nbins][nlm].
-struct GatherArgs {
+// Harmonic coefficient gather (eq. binned-discrete-alm).  A launch covers a
+// "slice" of primaries that may come from several catalogs (jobs): segment s
+// holds nprim consecutive slice rows starting at row0, all from one catalog.
+// Work item = (slice row, bin group); rows are written as complex
+// alm[row][nbins][nlm] plus the primary's weight wprim[row].
+struct GatherSeg {
     const double4* P;
     const int32_t* cell_start;
-    int ncx, ncy, ncz;
+    const int32_t* prim;   // sorted indices of this segment's primaries
+    int ncx, ncy, ncz, periodic;
     double ox, oy, oz, csx, csy, csz;
-    int periodic;
     double Lx, Ly, Lz;
-    const int32_t* prim;   // sorted indices of the primaries
-    int nprim;
-    int nbins;
-    int ngroups;           // bin groups per primary (work items per primary)
-    int group_bins;        // bins per group (last group may have fewer)
-    double e2[kMaxBins + 1];  // squared edges
-    void* alm;             // output
-    const double* kappa;   // [nlm] final scale of the monic recurrence
-    const double* gamma;   // [nlm] recurrence coefficients
-    unsigned long long* npairs;  // optional: += accepted pairs (null: not counted)
+    int row0, nprim;
 };
-// precision: 0 = FP64, 1 = FP32.  Returns hipError_t as int.
-int launch_gather(const GatherArgs& a, int lmax, int precision, hipStream_t stream);
-// bins per work item the kernel for (lmax, precision) keeps in registers
+struct GatherArgs {
+    const GatherSeg* segs;   // device array
+    int nseg;
+    int nrows;               // slice rows (sum of segment nprim)
+    int nbins;
+    int ngroups;             // bin groups per primary (work items per primary)
+    int group_bins;          // bins per group (last group may have fewer)
+    double e2[kMaxBins + 1]; // squared edges
+    void* alm;               // output rows
+    double* wprim;           // output: weight of each row's primary
+    const double* kappa;     // [nlm] final scale of the monic recurrence
+    const double* gamma;     // [nlm] recurrence coefficients
+    unsigned long long* npairs;  // optional: += accepted pairs (null: not counted)
+    // persistent mode (queues != null): waves pull items from 8 queues (one per
+    // XCD, contiguous item ranges) and steal from the others when theirs is empty
+    unsigned* queues;        // [8] counters, zero at launch
+};
+// precision: 0 = FP64, 1 = FP32.  persistent: grid sized to the resident waves.
+int launch_gather(const GatherArgs& a, int lmax, int precision, bool persistent, hipStream_t stream);
 int gather_group_bins(int lmax, int precision);
-// fill kappa/gamma tables for the monic Legendre recurrence used by the gather
 void gather_tables(int lmax, double* kappa, double* gamma);
 
 // ------------------------------------------------------------------ coupling
-// T[split][t][B] = sum over the split's primaries p of w_p Q_t[prod_k a^{b_k}_{l_k m_k}(p)],
-// Q_t = Re or Im; then zeta[L][B] = sum_terms coef * sum_split T.
+// For every split y: T[y][t][B] = sum over rows p in [split_lo[y], split_hi[y]) of
+// w_p Q_t[prod_k a~^{b_k}_{l_k m_k}(p)], Q_t = Re or Im (written, not accumulated).
 struct CoupleArgs {
-    const void* alm;          // [nprim][nbins][nlm] complex
-    const double4* P;         // for the primary weights
-    const int32_t* prim;      // sorted indices of the primaries
-    int nprim;
+    const void* alm;          // [nrows][nbins][nlm] complex
+    const double* wprim;      // [nrows]
     int nbins, nlm, nk;       // nk = N - 1
     int ntuple, nB;
     const int32_t* tuple_off;   // [ntuple][nk] lm index of factor k
-    const int32_t* tuple_flags; // [ntuple] bit k: factor k has m < 0; bits 8..12: (-1)^m sign of
-                                // factor k negative; bit 16: take Im
+    const int32_t* tuple_flags; // [ntuple] bit k: factor k has m < 0 (conjugate); bit 8:
+                                // overall (-1)^m sign negative; bit 16: take Im
     const int32_t* btab;      // [nB][nk]
     int nsplit;
-    double* T;                // [nsplit][ntuple][nB]  (accumulated: +=)
+    const int32_t* split_lo;  // [nsplit]
+    const int32_t* split_hi;  // [nsplit]
+    double* T;                // [nsplit][ntuple][nB]
 };
 int launch_couple(const CoupleArgs& a, int precision, hipStream_t stream);
+// rows per split that keep the coupling kernels' blocks busy
+int couple_split_rows(int nk, int nbins, int64_t ntuple, int64_t nB, int64_t nrows);
+int couple_ptile(int nbins, int nlm, int precision);
+
+// dst[r][..] += sum over splits y in [red_lo[r], red_hi[r]) of T[y][..], left to
+// right starting from the current dst[r] (one entry per job and slice).
+struct ReduceArgs {
+    const double* T;          // [nsplit][ntuple * nB]
+    int64_t per;              // ntuple * nB
+    int nred;
+    const int32_t* red_lo;
+    const int32_t* red_hi;
+    double* const* dst;       // [nred] device pointers, each [per]
+};
+int launch_reduce(const ReduceArgs& a, hipStream_t stream);
 
 struct ContractArgs {
     const double* T;          // [nsplit][ntuple][nB]

@@ -1,0 +1,371 @@
+// Host-side execution engine: tables on the device, workspaces, and the slice
+// runner shared by the synchronous entry points and the server.
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+namespace encore {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+const char* get_error() { return g_err.c_str(); }
+
+int fail(int code, const std::string& msg)
+{
+    set_error(msg);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(e == hipErrorOutOfMemory ? ENCORE_ENOMEM : ENCORE_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int ensure(Buf& b, size_t bytes)
+{
+    if (b.n >= bytes && b.p) return ENCORE_OK;
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.n = 0;
+    const size_t want = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
+    b.n = want;
+    return ENCORE_OK;
+}
+
+static Buf* exec_bufs(Exec& x, int i)
+{
+    Buf* all[] = {&x.alm, &x.wprim, &x.T, &x.segs, &x.splits, &x.redp, &x.queues,
+                  &x.misc, &x.zeta, &x.bscale, &x.prim, &x.Tjob};
+    return i < (int)(sizeof(all) / sizeof(all[0])) ? all[i] : nullptr;
+}
+
+int exec_init(Exec& x)
+{
+    HIPTRY(hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking));
+    for (int i = 0; i < 4; ++i) HIPTRY(hipEventCreate(&x.ev[i]));
+    return ENCORE_OK;
+}
+
+void exec_release(Exec& x)
+{
+    if (x.s) (void)hipStreamSynchronize(x.s);
+    for (int i = 0; Buf* b = exec_bufs(x, i); ++i) {
+        if (b->p) (void)hipFree(b->p);
+        b->p = nullptr;
+        b->n = 0;
+    }
+    for (int i = 0; i < 4; ++i) {
+        if (x.ev[i]) (void)hipEventDestroy(x.ev[i]);
+        x.ev[i] = nullptr;
+    }
+    if (x.s) (void)hipStreamDestroy(x.s);
+    x.s = nullptr;
+}
+
+size_t exec_bytes(const Exec& x)
+{
+    size_t t = 0;
+    for (int i = 0; Buf* b = exec_bufs(const_cast<Exec&>(x), i); ++i) t += b->n;
+    return t;
+}
+
+bool valid_lmax(int N, int lmax)
+{
+    if (lmax < 0) return false;
+    switch (N) {
+    case 3: case 4: return lmax <= kMaxLmax;
+    case 5: return lmax <= 5;
+    case 6: return lmax <= 4;
+    }
+    return false;
+}
+
+int check_edges(const double* edges, int nbins)
+{
+    if (!edges) return fail(ENCORE_EINVAL, "edges is NULL");
+    if (nbins < 1 || nbins > kMaxBins)
+        return fail(ENCORE_EINVAL, "nbins must be in 1.." + std::to_string(kMaxBins));
+    if (!(edges[0] > 0.0) || !std::isfinite(edges[0]))
+        return fail(ENCORE_EINVAL, "edges[0] must be > 0 (zero separations have no direction)");
+    for (int b = 0; b < nbins; ++b)
+        if (!(edges[b + 1] > edges[b]) || !std::isfinite(edges[b + 1]))
+            return fail(ENCORE_EINVAL, "edges must be finite and strictly increasing");
+    return ENCORE_OK;
+}
+
+int precision_of(uint32_t flags, int* prec)
+{
+    switch (flags & ENCORE_PREC_MASK) {
+    case ENCORE_PREC_FP64: *prec = 0; return ENCORE_OK;
+    case ENCORE_PREC_FP32: *prec = 1; return ENCORE_OK;
+    case ENCORE_PREC_SPLITBF16:
+        return fail(ENCORE_EUNSUPPORTED, "ENCORE_PREC_SPLITBF16 coupling is not built in this version");
+    }
+    return fail(ENCORE_EINVAL, "unknown precision flag");
+}
+
+int check_grid_edges(const DevGrid& g, const double* edges, int nbins)
+{
+    if (edges[nbins] > g.r_max * (1.0 + 1e-12))
+        return fail(ENCORE_EINVAL, "edges[nbins] exceeds the r_max the grid was built for");
+    if (g.periodic && (2.0 * edges[nbins] > g.Lx || 2.0 * edges[nbins] > g.Ly || 2.0 * edges[nbins] > g.Lz))
+        return fail(ENCORE_EINVAL, "periodic box: edges[nbins] must be <= box/2 on every axis");
+    return ENCORE_OK;
+}
+
+int plan_call(int npcf, int lmax, int nbins, const double* edges, uint32_t flags, NpcfPlan* pl)
+{
+    if (npcf < 3 || npcf > 6) return fail(ENCORE_EINVAL, "npcf must be 3..6");
+    if (!valid_lmax(npcf, lmax)) return fail(ENCORE_EINVAL, "lmax out of range for this N");
+    int rc;
+    if ((rc = check_edges(edges, nbins))) return rc;
+    if ((rc = precision_of(flags, &pl->prec))) return rc;
+    pl->N = npcf; pl->lmax = lmax; pl->nbins = nbins;
+    pl->allparity = flags & ENCORE_ALLPARITY;
+    pl->nlam = (int64_t)enumerate_multiplets(npcf, lmax, pl->allparity).size() / multiplet_width(npcf);
+    pl->nB = binomial(nbins, npcf - 1);
+    return ENCORE_OK;
+}
+
+template <typename V>
+static int upload(V*& dst, const std::vector<V>& src)
+{
+    const size_t bytes = std::max<size_t>(1, src.size()) * sizeof(V);
+    HIPTRY(hipMalloc(&dst, bytes));
+    if (!src.empty()) HIPTRY(hipMemcpy(dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice));
+    return ENCORE_OK;
+}
+
+int get_tables(encore_ctx* ctx, int N, int lmax, bool allparity, int nbins, DevTables** out)
+{
+    std::lock_guard<std::mutex> lock(ctx->tab_mu);
+    auto key = std::make_tuple(N, lmax, allparity, nbins);
+    auto it = ctx->tables.find(key);
+    if (it != ctx->tables.end()) { *out = &it->second; return ENCORE_OK; }
+    const TermTable& tt = term_table(N, lmax, allparity);
+    DevTables d;
+    d.N = N; d.lmax = lmax; d.nbins = nbins; d.allparity = allparity;
+    d.nlam = tt.nlam;
+    const int K = N - 1;
+    std::vector<int32_t> bt = enumerate_bin_tuples(N, nbins);
+    d.nB = (int64_t)bt.size() / K;
+    d.ntuple = tt.ntuple;
+    d.nterm = (int64_t)tt.coef.size();
+    std::vector<int32_t> toff(tt.ntuple * K), tflags(tt.ntuple);
+    for (int64_t t = 0; t < tt.ntuple; ++t) {
+        int f = 0, neg = 0;
+        for (int k = 0; k < K; ++k) {
+            const int l = tt.tuple_l[t * K + k], m = tt.tuple_m[t * K + k];
+            toff[t * K + k] = l * (l + 1) / 2 + std::abs(m);
+            if (m < 0) {
+                f |= 1 << k;                    // conjugate
+                if (std::abs(m) & 1) neg ^= 1;  // (-1)^m
+            }
+        }
+        if (neg) f |= 1 << 8;
+        if (tt.tuple_odd[t]) f |= 1 << 16;
+        tflags[t] = f;
+    }
+    // terms sorted by multiplet (they are generated in multiplet order)
+    std::vector<int32_t> tstart(tt.nlam + 1, 0);
+    for (int32_t l : tt.lam) tstart[l + 1]++;
+    for (int64_t l = 0; l < tt.nlam; ++l) tstart[l + 1] += tstart[l];
+    const int nlm = (lmax + 1) * (lmax + 2) / 2;
+    std::vector<double> kap(nlm), gam(nlm);
+    gather_tables(lmax, kap.data(), gam.data());
+    int rc;
+    if ((rc = upload(d.tuple_off, toff)) || (rc = upload(d.tuple_flags, tflags)) ||
+        (rc = upload(d.btab, bt)) || (rc = upload(d.term_start, tstart)) ||
+        (rc = upload(d.term_tuple, tt.term_tuple)) || (rc = upload(d.term_coef, tt.coef)) ||
+        (rc = upload(d.kappa, kap)) || (rc = upload(d.gamma, gam)))
+        return rc;
+    auto res = ctx->tables.emplace(key, d);
+    *out = &res.first->second;
+    return ENCORE_OK;
+}
+
+size_t alm_row_bytes(const NpcfPlan& pl)
+{
+    const int nlm = (pl.lmax + 1) * (pl.lmax + 2) / 2;
+    return (size_t)pl.nbins * nlm * 2 * (pl.prec == 0 ? 8 : 4);
+}
+
+int64_t cap_rows(const NpcfPlan& pl)
+{
+    int64_t cap = std::max<int64_t>(1, (int64_t)((size_t)2 << 30) / alm_row_bytes(pl));
+    if (const char* e = getenv("ENCORE_MAX_SLICE_ROWS")) {   // smaller slices (tests of slicing)
+        const long long v = atoll(e);
+        if (v > 0) cap = std::min<int64_t>(cap, v);
+    }
+    return cap;
+}
+
+int64_t job_split_rows(const NpcfPlan& pl, const DevTables* tb, int64_t nprim, int64_t cap)
+{
+    return std::min<int64_t>(
+        cap, couple_split_rows(pl.N - 1, pl.nbins, tb->ntuple, tb->nB, std::max<int64_t>(nprim, 1)));
+}
+
+int run_slice(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double* edges,
+              const std::vector<Chunk>& chunks, double* ms_gather, double* ms_couple)
+{
+    const hipStream_t s = x.s;
+    const int nlm = (pl.lmax + 1) * (pl.lmax + 2) / 2;
+    const int64_t outs = tb->ntuple * tb->nB;
+    std::vector<GatherSeg> hsegs;
+    std::vector<int32_t> slo, shi, rlo, rhi;
+    std::vector<double*> rdst;
+    int64_t rows = 0;
+    for (const Chunk& c : chunks) {
+        const int64_t take = c.r1 - c.r0;
+        if (take <= 0) continue;
+        const DevGrid& g = *c.g;
+        GatherSeg gs;
+        gs.P = g.P; gs.cell_start = g.cell_start; gs.prim = c.prim + c.r0;
+        gs.ncx = g.ncx; gs.ncy = g.ncy; gs.ncz = g.ncz; gs.periodic = g.periodic;
+        gs.ox = g.ox; gs.oy = g.oy; gs.oz = g.oz;
+        gs.csx = g.csx; gs.csy = g.csy; gs.csz = g.csz;
+        gs.Lx = g.Lx; gs.Ly = g.Ly; gs.Lz = g.Lz;
+        gs.row0 = (int)rows; gs.nprim = (int)take;
+        hsegs.push_back(gs);
+        rlo.push_back((int32_t)slo.size());
+        for (int64_t r = 0; r < take; r += c.split_rows) {
+            slo.push_back((int32_t)(rows + r));
+            shi.push_back((int32_t)(rows + std::min<int64_t>(take, r + c.split_rows)));
+        }
+        rhi.push_back((int32_t)slo.size());
+        rdst.push_back(c.Tdst);
+        rows += take;
+    }
+    if (rows == 0) return ENCORE_OK;
+    if (rows > INT32_MAX || hsegs.size() > 65535) return fail(ENCORE_ESIZE, "slice too large");
+    const int nsplit = (int)slo.size(), nred = (int)rlo.size();
+    int rc;
+    if ((rc = ensure(x.alm, alm_row_bytes(pl) * (size_t)rows))) return rc;
+    if ((rc = ensure(x.wprim, sizeof(double) * (size_t)rows))) return rc;
+    if ((rc = ensure(x.T, sizeof(double) * (size_t)nsplit * (size_t)outs))) return rc;
+    if ((rc = ensure(x.segs, sizeof(GatherSeg) * hsegs.size()))) return rc;
+    if ((rc = ensure(x.splits, sizeof(int32_t) * (size_t)(2 * nsplit + 2 * nred)))) return rc;
+    if ((rc = ensure(x.redp, sizeof(double*) * (size_t)nred))) return rc;
+    if ((rc = ensure(x.queues, 64))) return rc;
+    if ((rc = ensure(x.misc, 64))) return rc;
+    std::vector<int32_t> hsplit;
+    hsplit.insert(hsplit.end(), slo.begin(), slo.end());
+    hsplit.insert(hsplit.end(), shi.begin(), shi.end());
+    hsplit.insert(hsplit.end(), rlo.begin(), rlo.end());
+    hsplit.insert(hsplit.end(), rhi.begin(), rhi.end());
+    HIPTRY(hipMemcpyAsync(x.segs.p, hsegs.data(), sizeof(GatherSeg) * hsegs.size(), hipMemcpyHostToDevice, s));
+    HIPTRY(hipMemcpyAsync(x.splits.p, hsplit.data(), sizeof(int32_t) * hsplit.size(), hipMemcpyHostToDevice, s));
+    HIPTRY(hipMemcpyAsync(x.redp.p, rdst.data(), sizeof(double*) * rdst.size(), hipMemcpyHostToDevice, s));
+    const int32_t* dsp = (const int32_t*)x.splits.p;
+
+    GatherArgs ga;
+    memset(&ga, 0, sizeof(ga));
+    ga.nbins = pl.nbins;
+    for (int b = 0; b <= pl.nbins; ++b) ga.e2[b] = edges[b] * edges[b];
+    ga.kappa = tb->kappa;
+    ga.gamma = tb->gamma;
+    ga.alm = x.alm.p;
+    ga.wprim = (double*)x.wprim.p;
+    ga.npairs = (unsigned long long*)x.misc.p;
+    ga.queues = (unsigned*)x.queues.p;
+    ga.segs = (const GatherSeg*)x.segs.p;
+    ga.nseg = (int)hsegs.size();
+    ga.nrows = (int)rows;
+
+    CoupleArgs ca;
+    memset(&ca, 0, sizeof(ca));
+    ca.alm = x.alm.p;
+    ca.wprim = (const double*)x.wprim.p;
+    ca.nbins = pl.nbins; ca.nlm = nlm; ca.nk = pl.N - 1;
+    ca.ntuple = (int)tb->ntuple; ca.nB = (int)tb->nB;
+    ca.tuple_off = tb->tuple_off; ca.tuple_flags = tb->tuple_flags; ca.btab = tb->btab;
+    ca.T = (double*)x.T.p;
+    ca.nsplit = nsplit;
+    ca.split_lo = dsp;
+    ca.split_hi = dsp + nsplit;
+
+    ReduceArgs ra;
+    ra.T = (const double*)x.T.p;
+    ra.per = outs;
+    ra.nred = nred;
+    ra.red_lo = dsp + 2 * nsplit;
+    ra.red_hi = dsp + 2 * nsplit + nred;
+    ra.dst = (double* const*)x.redp.p;
+
+    HIPTRY(hipEventRecord(x.ev[1], s));
+    HIPTRY((hipError_t)launch_gather(ga, pl.lmax, pl.prec, hsegs.size() > 1, s));
+    HIPTRY(hipEventRecord(x.ev[2], s));
+    HIPTRY((hipError_t)launch_couple(ca, pl.prec, s));
+    HIPTRY((hipError_t)launch_reduce(ra, s));
+    HIPTRY(hipEventRecord(x.ev[3], s));
+    HIPTRY(hipEventSynchronize(x.ev[3]));   // the host tables above are reused by the next slice
+    float ms = 0.f;
+    HIPTRY(hipEventElapsedTime(&ms, x.ev[1], x.ev[2]));
+    if (ms_gather) *ms_gather += ms;
+    HIPTRY(hipEventElapsedTime(&ms, x.ev[2], x.ev[3]));
+    if (ms_couple) *ms_couple += ms;
+    return ENCORE_OK;
+}
+
+int contract_job(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double* T,
+                 const double* bscale, double* zeta)
+{
+    ContractArgs xa;
+    xa.nsplit = 1; xa.ntuple = (int)tb->ntuple; xa.nB = (int)tb->nB; xa.nlam = (int)pl.nlam;
+    xa.term_start = tb->term_start; xa.term_tuple = tb->term_tuple; xa.term_coef = tb->term_coef;
+    xa.T = T;
+    xa.bscale = bscale;
+    xa.zeta = zeta;
+    HIPTRY((hipError_t)launch_contract(xa, x.s));
+    return ENCORE_OK;
+}
+
+std::vector<double> bin_scale(const NpcfPlan& pl, const double* edges, double V)
+{
+    const std::vector<int32_t> bt = enumerate_bin_tuples(pl.N, pl.nbins);
+    const int K = pl.N - 1;
+    std::vector<double> sc((size_t)pl.nB);
+    for (int64_t b = 0; b < pl.nB; ++b) {
+        double v = V;
+        for (int k = 0; k < K; ++k) {
+            const double lo = edges[bt[b * K + k]], hi = edges[bt[b * K + k] + 1];
+            v *= 4.0 * M_PI / 3.0 * (hi * hi * hi - lo * lo * lo);
+        }
+        sc[b] = 1.0 / v;
+    }
+    return sc;
+}
+
+double cell_divisor()
+{
+    const char* s = getenv("ENCORE_CELL_DIVISOR");
+    if (s) {
+        const double v = atof(s);
+        if (v >= 1.0 && v <= 32.0) return v;
+    }
+    return 6.0;   // cell side r_max / 6: measured best of {4, 6, 8, 10}
+}
+
+int build_grid_dev(int device, const double* d_pos, const double* d_w, int64_t n, int64_t n_data,
+                   bool dmr, const double* box, double r_max, hipStream_t s, DevGrid& out)
+{
+    HIPTRY(hipSetDevice(device));
+    double bx[3] = {0, 0, 0};
+    if (box)
+        for (int a = 0; a < 3; ++a) bx[a] = box[a];
+    char err[256] = {0};
+    const int rc = grid_build(out, d_pos, d_w, n, n_data, dmr, box != nullptr, bx, r_max,
+                              r_max / cell_divisor(), s, err, sizeof(err));
+    if (rc != 0) return fail(rc == -1 ? ENCORE_EINVAL : (rc == -3 ? ENCORE_ENOMEM : ENCORE_EDEVICE), err);
+    return ENCORE_OK;
+}
+
+}  // namespace encore

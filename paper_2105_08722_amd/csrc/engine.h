@@ -1,0 +1,135 @@
+// Host-side execution engine of libencore (internal, not part of the ABI).
+//
+// An Exec is one HIP stream with its own workspaces; the context owns one for
+// the synchronous entry points and the server owns one per lane.  run_slice()
+// runs gather -> coupling -> in-order reduction for a list of row chunks that
+// may come from several catalogs; contract_job() turns a job's accumulated T
+// into zeta.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/encore.h"
+#include "device.h"
+#include "internal.h"
+
+namespace encore {
+
+// device copies of the tables for one (N, lmax, parity, nbins)
+struct DevTables {
+    int N = 0, lmax = 0, nbins = 0;
+    bool allparity = false;
+    int64_t nlam = 0, nB = 0, ntuple = 0, nterm = 0;
+    int32_t* tuple_off = nullptr;
+    int32_t* tuple_flags = nullptr;
+    int32_t* btab = nullptr;
+    int32_t* term_start = nullptr;
+    int32_t* term_tuple = nullptr;
+    double* term_coef = nullptr;
+    double* kappa = nullptr;
+    double* gamma = nullptr;
+};
+
+struct Buf {
+    void* p = nullptr;
+    size_t n = 0;
+};
+
+// One stream and the workspaces of the hot path on it.
+struct Exec {
+    hipStream_t s = nullptr;
+    Buf alm, wprim, T, segs, splits, redp, queues, misc, zeta, bscale, prim, Tjob;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+int exec_init(Exec& x);
+void exec_release(Exec& x);
+// bytes held by the workspaces
+size_t exec_bytes(const Exec& x);
+
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define HIPTRY(x)                                                    \
+    do {                                                             \
+        hipError_t e__ = (x);                                        \
+        if (e__ != hipSuccess) return ::encore::hip_fail(e__, #x);   \
+    } while (0)
+
+// grow-only device buffer
+int ensure(Buf& b, size_t bytes);
+
+bool valid_lmax(int N, int lmax);
+int check_edges(const double* edges, int nbins);
+int precision_of(uint32_t flags, int* prec);
+int check_grid_edges(const DevGrid& g, const double* edges, int nbins);
+
+// Validated call parameters shared by every entry point that computes zeta.
+struct NpcfPlan {
+    int N = 0, lmax = 0, nbins = 0, prec = 0;
+    bool allparity = false;
+    int64_t nlam = 0, nB = 0;
+};
+int plan_call(int npcf, int lmax, int nbins, const double* edges, uint32_t flags, NpcfPlan* pl);
+
+// bytes of a~ per primary row
+size_t alm_row_bytes(const NpcfPlan& pl);
+// rows of a~ held at once (2 GiB of coefficients; ENCORE_MAX_SLICE_ROWS may lower it)
+int64_t cap_rows(const NpcfPlan& pl);
+// Coupling split length of a job: a function of the job alone, so that a job's
+// zeta does not depend on what shares a launch with it.
+int64_t job_split_rows(const NpcfPlan& pl, const DevTables* tb, int64_t nprim, int64_t cap);
+
+// Rows [r0, r1) of one job's primary list inside a slice.  r0 is a multiple of
+// split_rows; Tdst receives += (in split order) the job's T over those rows.
+struct Chunk {
+    const DevGrid* g;
+    const int32_t* prim;   // device: the job's sorted primary indices
+    int64_t r0, r1;
+    int64_t split_rows;
+    double* Tdst;          // device [ntuple * nB]
+};
+// Gather + couple + reduce for the chunks (at most cap_rows rows in total).
+// Synchronises x.s before returning; adds the gather / coupling milliseconds.
+// x.misc holds the accepted-pair counter (cleared by the caller).
+int run_slice(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double* edges,
+              const std::vector<Chunk>& chunks, double* ms_gather, double* ms_couple);
+// zeta[nlam][nB] (device) from a job's T (device); bscale[nB] (device) or null.
+int contract_job(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double* T,
+                 const double* bscale, double* zeta);
+// 1 / (V prod_k shell volume) per bin tuple (normalisation of eq. 2.7's estimator)
+std::vector<double> bin_scale(const NpcfPlan& pl, const double* edges, double V);
+
+// Cell grid of a catalog already on the device (pos [n][3], w [n]).
+int build_grid_dev(int device, const double* d_pos, const double* d_w, int64_t n, int64_t n_data,
+                   bool dmr, const double* box, double r_max, hipStream_t s, DevGrid& out);
+double cell_divisor();
+
+}  // namespace encore
+
+struct encore_ctx {
+    int device = 0;
+    encore::Exec main;
+    std::map<std::tuple<int, int, bool, int>, encore::DevTables> tables;
+    std::mutex tab_mu;   // tables
+    std::mutex mu;       // main exec, timings
+    double timings[6] = {0, 0, 0, 0, 0, 0};
+    std::atomic<int> live_grids{0};
+};
+
+struct encore_grid {
+    encore_ctx* ctx = nullptr;
+    encore::DevGrid g;
+};
+
+namespace encore {
+// thread-safe; the returned tables live as long as the context
+int get_tables(encore_ctx* ctx, int N, int lmax, bool allparity, int nbins, DevTables** out);
+}  // namespace encore

@@ -24,6 +24,7 @@
 // Y_lm = N_lm(z) (x + i y)^m for a unit vector (Condon-Shortley phase inside N_lm);
 // N_lm = kappa_lm R_lm with R_mm = 1, R_{m+1,m} = z, R_lm = z R_{l-1,m} - gamma_lm R_{l-2,m}.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <utility>
@@ -156,6 +157,30 @@ __device__ __forceinline__ double uni(double v)
     return __longlong_as_double(((unsigned long long)hi << 32) | lo);
 }
 
+template <typename PT>
+__device__ __forceinline__ PT* uni(PT* v)
+{
+    const unsigned long long u = (unsigned long long)v;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+    return (PT*)(((unsigned long long)hi << 32) | lo);
+}
+
+// a segment descriptor with every field made wave-uniform (SGPRs)
+__device__ __forceinline__ GatherSeg load_seg(const GatherSeg* segs, int s)
+{
+    GatherSeg g = segs[s];
+    g.P = uni(g.P);
+    g.cell_start = uni(g.cell_start);
+    g.prim = uni(g.prim);
+    g.ncx = uni(g.ncx); g.ncy = uni(g.ncy); g.ncz = uni(g.ncz); g.periodic = uni(g.periodic);
+    g.ox = uni(g.ox); g.oy = uni(g.oy); g.oz = uni(g.oz);
+    g.csx = uni(g.csx); g.csy = uni(g.csy); g.csz = uni(g.csz);
+    g.Lx = uni(g.Lx); g.Ly = uni(g.Ly); g.Lz = uni(g.Lz);
+    g.row0 = uni(g.row0); g.nprim = uni(g.nprim);
+    return g;
+}
+
 __device__ __forceinline__ int wave_excl_scan(int v, int lane, int* total)
 {
     int incl = v;
@@ -189,16 +214,6 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wib = threadIdx.x / kWave;
-    // XCD-aware block order: the grid is a multiple of 8 blocks and block b runs on
-    // XCD b % 8; give each XCD a contiguous run of work items so that neighbouring
-    // primaries (same cells) share that XCD's L2.
-    const int nblk = gridDim.x;
-    const int bid = (blockIdx.x % 8) * (nblk / 8) + blockIdx.x / 8;
-    const int item = bid * kWavesPerBlock + wib;
-    const int p = item / a.ngroups;
-    const int grp = item - p * a.ngroups;
-    if (p >= a.nprim) return;
-
     unsigned char* base = smem + wib * wave_lds_bytes<T, NBG>();
     E* ring = reinterpret_cast<E*>(base);
     T* scratch = reinterpret_cast<T*>(base);
@@ -212,8 +227,42 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
 #pragma unroll
     for (int q = 0; q < NLM; ++q) gam[q] = (T)a.gamma[q];
 
-    const int ip = a.prim[p];
-    const double4 Pi = a.P[ip];
+    const int64_t nitems = (int64_t)a.nrows * a.ngroups;
+    // Item order: a static grid gives each XCD (block b runs on XCD b % 8) a
+    // contiguous run of items, so neighbouring primaries (same cells) share that
+    // XCD's L2; the persistent grid pulls items from 8 contiguous queues the same way.
+    const int home = blockIdx.x & 7;
+    auto pop = [&]() -> int64_t {
+        for (int t = 0; t < 8; ++t) {
+            const int qi = (home + t) & 7;
+            const int64_t lo = nitems * qi / 8, hi = nitems * (qi + 1) / 8;
+            unsigned got = 0;
+            if (lane == 0) got = atomicAdd(&a.queues[qi], 1u);
+            got = __builtin_amdgcn_readfirstlane(got);
+            if (lo + (int64_t)got < hi) return lo + (int64_t)got;
+        }
+        return -1;
+    };
+    int64_t item;
+    if (a.queues) {
+        item = pop();
+    } else {
+        const int nblk = gridDim.x;
+        const int bid = (blockIdx.x % 8) * (nblk / 8) + blockIdx.x / 8;
+        item = (int64_t)bid * kWavesPerBlock + wib;
+    }
+    while (item >= 0 && item < nitems) {
+    const int row = uni((int)(item / a.ngroups));
+    const int grp = uni((int)(item - (int64_t)row * a.ngroups));
+    // segment (catalog) of this row: binary search over the segments' first rows
+    int slo = 0, shi = a.nseg - 1;
+    while (slo < shi) {
+        const int mid = (slo + shi + 1) >> 1;
+        if (uni(a.segs[mid].row0) <= row) slo = mid; else shi = mid - 1;
+    }
+    const GatherSeg g = load_seg(a.segs, uni(slo));
+    const int ip = uni(g.prim[row - g.row0]);
+    const double4 Pi = g.P[ip];
     const double xi = uni(Pi.x), yi = uni(Pi.y), zi = uni(Pi.z);
     const int b_lo = grp * NBG;
     const int b_hi = min(b_lo + NBG, a.nbins);
@@ -223,9 +272,9 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
 #pragma unroll
     for (int q = 1; q < NBG; ++q) e2k[q] = uni((b_lo + q < b_hi) ? a.e2[min(b_lo + q, kMaxBins)] : INFINITY);
     // periodic images: shift per axis for image codes 0, 1, 2 (-L, 0, +L)
-    const double Lx = a.Lx, Ly = a.Ly, Lz = a.Lz;
+    const double Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
     // culling uses slightly enlarged cells and radius; the bin test below is exact
-    const double eps = 1e-7 * fmin(a.csx, fmin(a.csy, a.csz));
+    const double eps = 1e-7 * fmin(g.csx, fmin(g.csy, g.csz));
     const double Rc = sqrt(R2out) + eps;
     const double Rc2 = Rc * Rc;
     const double Rin = sqrt(R2in);
@@ -240,11 +289,11 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         for (int q = 0; q < NLM; ++q) { acc[k][q][0] = (T)0; acc[k][q][1] = (T)0; }
 
     // row range (unwrapped cell indices)
-    int ky0 = (int)floor((yi - Rc - a.oy) / a.csy), ky1 = (int)floor((yi + Rc - a.oy) / a.csy);
-    int kz0 = (int)floor((zi - Rc - a.oz) / a.csz), kz1 = (int)floor((zi + Rc - a.oz) / a.csz);
-    if (!a.periodic) {
-        ky0 = max(ky0, 0); ky1 = min(ky1, a.ncy - 1);
-        kz0 = max(kz0, 0); kz1 = min(kz1, a.ncz - 1);
+    int ky0 = (int)floor((yi - Rc - g.oy) / g.csy), ky1 = (int)floor((yi + Rc - g.oy) / g.csy);
+    int kz0 = (int)floor((zi - Rc - g.oz) / g.csz), kz1 = (int)floor((zi + Rc - g.oz) / g.csz);
+    if (!g.periodic) {
+        ky0 = max(ky0, 0); ky1 = min(ky1, g.ncy - 1);
+        kz0 = max(kz0, 0); kz1 = min(kz1, g.ncz - 1);
     }
     const int nyr = ky1 - ky0 + 1, nzr = kz1 - kz0 + 1;
     const int nrows = (nyr > 0 && nzr > 0) ? nyr * nzr : 0;
@@ -258,19 +307,19 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
             if (r < nrows) {
                 const int ky = ky0 + r % nyr, kz = kz0 + r / nyr;
                 int wy = ky, wz = kz, sy = 0, sz = 0;
-                if (a.periodic) {
-                    wy = ((ky % a.ncy) + a.ncy) % a.ncy; sy = (ky - wy) / a.ncy;
-                    wz = ((kz % a.ncz) + a.ncz) % a.ncz; sz = (kz - wz) / a.ncz;
+                if (g.periodic) {
+                    wy = ((ky % g.ncy) + g.ncy) % g.ncy; sy = (ky - wy) / g.ncy;
+                    wz = ((kz % g.ncz) + g.ncz) % g.ncz; sz = (kz - wz) / g.ncz;
                 }
-                const double ylo = a.oy + ky * a.csy - eps, yhi = a.oy + (ky + 1) * a.csy + eps;
-                const double zlo = a.oz + kz * a.csz - eps, zhi = a.oz + (kz + 1) * a.csz + eps;
+                const double ylo = g.oy + ky * g.csy - eps, yhi = g.oy + (ky + 1) * g.csy + eps;
+                const double zlo = g.oz + kz * g.csz - eps, zhi = g.oz + (kz + 1) * g.csz + eps;
                 const double dymin = fmax(0.0, fmax(ylo - yi, yi - yhi));
                 const double dzmin = fmax(0.0, fmax(zlo - zi, zi - zhi));
                 const double rho2 = dymin * dymin + dzmin * dzmin;
                 if (rho2 < Rc2) {
                     const double h = sqrt(Rc2 - rho2) + eps;
-                    int kx0 = (int)floor((xi - h - a.ox) / a.csx), kx1 = (int)floor((xi + h - a.ox) / a.csx);
-                    if (!a.periodic) { kx0 = max(kx0, 0); kx1 = min(kx1, a.ncx - 1); }
+                    int kx0 = (int)floor((xi - h - g.ox) / g.csx), kx1 = (int)floor((xi + h - g.ox) / g.csx);
+                    if (!g.periodic) { kx0 = max(kx0, 0); kx1 = min(kx1, g.ncx - 1); }
                     const double dymax = fmax(fabs(ylo - yi), fabs(yhi - yi));
                     const double dzmax = fmax(fabs(zlo - zi), fabs(zhi - zi));
                     const double rhomax2 = dymax * dymax + dzmax * dzmax;
@@ -278,11 +327,11 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
                     if (Rin > 0.0 && rhomax2 < R2in) {
                         const double hin = sqrt(R2in - rhomax2) - eps;
                         if (hin > 0.0) {
-                            kin0 = (int)ceil((xi - hin - a.ox) / a.csx);
-                            kin1 = (int)floor((xi + hin - a.ox) / a.csx) - 1;
+                            kin0 = (int)ceil((xi - hin - g.ox) / g.csx);
+                            kin1 = (int)floor((xi + hin - g.ox) / g.csx) - 1;
                         }
                     }
-                    const int rowbase = (wz * a.ncy + wy) * a.ncx;
+                    const int rowbase = (wz * g.ncy + wy) * g.ncx;
                     const int code_yz = ((sy + 1) << 2) | ((sz + 1) << 4);
                     // at most two x ranges: left of and right of the inner hole
                     for (int q = 0; q < 2; ++q) {
@@ -296,15 +345,15 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
                         }
                         if (lo > hi) continue;
                         int sxa = 0, sxb = 0;
-                        if (a.periodic) {
-                            sxa = (lo >= 0) ? lo / a.ncx : -((-lo + a.ncx - 1) / a.ncx);
-                            sxb = (hi >= 0) ? hi / a.ncx : -((-hi + a.ncx - 1) / a.ncx);
+                        if (g.periodic) {
+                            sxa = (lo >= 0) ? lo / g.ncx : -((-lo + g.ncx - 1) / g.ncx);
+                            sxb = (hi >= 0) ? hi / g.ncx : -((-hi + g.ncx - 1) / g.ncx);
                         }
                         for (int sx = sxa; sx <= sxb && ns < kSegPerRow; ++sx) {
-                            const int plo = max(lo, sx * a.ncx) - sx * a.ncx;
-                            const int phi = min(hi, sx * a.ncx + a.ncx - 1) - sx * a.ncx;
-                            const int st = a.cell_start[rowbase + plo];
-                            const int en = a.cell_start[rowbase + phi + 1];
+                            const int plo = max(lo, sx * g.ncx) - sx * g.ncx;
+                            const int phi = min(hi, sx * g.ncx + g.ncx - 1) - sx * g.ncx;
+                            const int st = g.cell_start[rowbase + plo];
+                            const int en = g.cell_start[rowbase + phi + 1];
                             if (en > st) {
                                 const int slot = lane * kSegPerRow + ns;
                                 slot_stc[slot] = st | (((sx + 1) | code_yz) << kCodeShift);
@@ -361,7 +410,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         double4 q_nx = make_double4(0.0, 0.0, 0.0, 0.0);
         if (total > 0) {
             lookup(0, j_nx, code_nx);
-            if (lane < total) q_nx = a.P[j_nx];
+            if (lane < total) q_nx = g.P[j_nx];
         }
         for (int f0 = 0; f0 < total; f0 += kWave) {
             const double4 q = q_nx;
@@ -369,7 +418,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
             const bool valid = f0 + lane < total;
             if (f0 + kWave < total) {
                 lookup(f0 + kWave, j_nx, code_nx);
-                if (f0 + kWave + lane < total) q_nx = a.P[j_nx];
+                if (f0 + kWave + lane < total) q_nx = g.P[j_nx];
             }
             bool ok = false;
             int k = 0;
@@ -455,7 +504,8 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
     constexpr int NV = NBG * NLM * 2;
     T* accf = &acc[0][0][0];
     const int nvalid = (b_hi - b_lo) * NLM * 2;
-    T* out = reinterpret_cast<T*>(a.alm) + ((size_t)p * a.nbins + b_lo) * NLM * 2;
+    T* out = reinterpret_cast<T*>(a.alm) + ((size_t)row * a.nbins + b_lo) * NLM * 2;
+    if (grp == 0 && lane == 0) a.wprim[row] = Pi.w;
 #pragma unroll
     for (int v0 = 0; v0 < NV; v0 += CH) {
 #pragma unroll
@@ -478,7 +528,11 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         }
         wave_sync();
     }
+    wave_sync();
+    item = a.queues ? pop() : -1;
+    }
 }
+
 
 // --------------------------------------------------------------- configurations
 struct KernelCfg {
@@ -595,18 +649,38 @@ void gather_tables(int lmax, double* kappa, double* gamma)
     }
 }
 
-int launch_gather(const GatherArgs& a0, int lmax, int precision, hipStream_t stream)
+int launch_gather(const GatherArgs& a0, int lmax, int precision, bool persistent, hipStream_t stream)
 {
     const KernelCfg c = config(lmax, precision);
     if (!c.fn[0]) return (int)hipErrorInvalidValue;
     GatherArgs a = a0;
     a.group_bins = c.nbg;
     a.ngroups = (a.nbins + c.nbg - 1) / c.nbg;
-    const int64_t items = (int64_t)a.nprim * a.ngroups;
-    int64_t blocks = (items + kWavesPerBlock - 1) / kWavesPerBlock;
-    blocks = (blocks + 7) / 8 * 8;
-    if (blocks > INT32_MAX) return (int)hipErrorInvalidValue;
+    if (!persistent) a.queues = nullptr;
+    if (persistent && !a.queues) return (int)hipErrorInvalidValue;
+    const int64_t items = (int64_t)a.nrows * a.ngroups;
+    if (items == 0) return (int)hipSuccess;
     for (int g = 0; g < c.nm; ++g) {
+        int64_t blocks;
+        if (persistent) {
+            // one block per resident wave slot (blocks are one wave each)
+            int dev = 0, per_cu = 0;
+            hipDeviceProp_t prop;
+            hipError_t e = hipGetDevice(&dev);
+            if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+            if (e == hipSuccess)
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c.fn[g], kWave * kWavesPerBlock,
+                                                                 (size_t)c.lds);
+            if (e != hipSuccess) return (int)e;
+            blocks = std::max(1, per_cu) * (int64_t)prop.multiProcessorCount;
+            blocks = std::min<int64_t>(blocks, (items + kWavesPerBlock - 1) / kWavesPerBlock);
+            const int rc = launch_fill_u32(a.queues, 8, 0u, stream);
+            if (rc != 0) return rc;
+        } else {
+            blocks = (items + kWavesPerBlock - 1) / kWavesPerBlock;
+        }
+        blocks = (blocks + 7) / 8 * 8;
+        if (blocks > INT32_MAX) return (int)hipErrorInvalidValue;
         void* args[] = {&a};
         hipError_t e = hipLaunchKernel(c.fn[g], dim3((unsigned)blocks), dim3(kWave * kWavesPerBlock),
                                        args, (size_t)c.lds, stream);

@@ -226,6 +226,12 @@ __global__ void k_fill(double* p, int64_t n, double v)
     if (i < n) p[i] = v;
 }
 
+__global__ void k_fill_u32(unsigned* p, int64_t n, unsigned v)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ void k_f2d(const float* s, int64_t n, double* d)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -251,6 +257,13 @@ int launch_fill(double* p, int64_t n, double v, hipStream_t stream)
 {
     if (n <= 0) return 0;
     k_fill<<<nblocks(n), kBlock, 0, stream>>>(p, n, v);
+    return (int)hipGetLastError();
+}
+
+int launch_fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t stream)
+{
+    if (n <= 0) return 0;
+    k_fill_u32<<<nblocks(n), kBlock, 0, stream>>>(p, n, v);
     return (int)hipGetLastError();
 }
 

@@ -1,0 +1,417 @@
+// Serving loop (encore_server_*): catalog jobs are submitted from any thread,
+// admitted by device-memory footprint, and run by lane threads, each with its
+// own HIP stream and workspaces.  Every iteration a lane takes one slice of
+// primary rows from the admitted jobs of one class (continuous batching: jobs
+// that arrive while slices run join at the next iteration), runs gather ->
+// coupling -> reduction into each job's resident T, and finishes the jobs whose
+// rows are all done (contraction, zeta to the host, device memory released).
+// Lanes run concurrently, so one lane's coupling overlaps another's gather.
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <thread>
+
+#include "engine.h"
+#include "sched.h"
+
+using namespace encore;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct SrvJob {
+    SchedJob sj;
+    // request
+    int64_t n = 0, n_data = 0;
+    uint32_t flags = 0;
+    bool periodic = false;
+    double box[3] = {0, 0, 0};
+    std::vector<double> edges;
+    std::vector<double> pos, w;   // host copies until the grid is built
+    NpcfPlan pl;
+    // device state
+    DevTables* tb = nullptr;
+    DevGrid g;
+    bool has_grid = false;
+    int32_t* prim = nullptr;
+    double* T = nullptr;
+    double* bscale = nullptr;
+    // result
+    std::vector<double> zeta;
+    int rc = ENCORE_OK;
+    std::string err;
+    bool started = false;
+    double t_submit = 0, t_admit = 0, t_start = 0, t_done = 0;
+};
+
+}  // namespace
+
+struct encore_server {
+    encore_ctx* ctx = nullptr;
+    Scheduler sch;
+    int64_t slice_rows = 0;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::map<int64_t, std::unique_ptr<SrvJob>> jobs;
+    std::map<std::vector<double>, uint64_t> classes;   // class key -> id
+    int64_t next_id = 1;
+    std::vector<Exec> lanes;
+    std::vector<std::thread> threads;
+    bool stop = false;
+    Clock::time_point t0;
+    // statistics
+    int64_t n_submitted = 0, n_done = 0, n_failed = 0, rows_done = 0, slices = 0;
+    double ms_gather = 0, ms_couple = 0;
+
+    encore_server(size_t budget, int max_active) : sch(budget, max_active) {}
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+};
+
+namespace {
+
+void release_job(SrvJob* j)
+{
+    if (j->has_grid) grid_free(j->g);
+    j->has_grid = false;
+    for (void* p : {(void*)j->prim, (void*)j->T, (void*)j->bscale})
+        if (p) (void)hipFree(p);
+    j->prim = nullptr;
+    j->T = nullptr;
+    j->bscale = nullptr;
+    std::vector<double>().swap(j->pos);
+    std::vector<double>().swap(j->w);
+}
+
+// Grid, primary list, T and tables of an admitted job, on lane x.
+int setup_job(encore_server* S, SrvJob* j, Exec& x)
+{
+    const hipStream_t s = x.s;
+    int rc;
+    if ((rc = get_tables(S->ctx, j->pl.N, j->pl.lmax, j->pl.allparity, j->pl.nbins, &j->tb))) return rc;
+    double* d_pos = nullptr;
+    double* d_w = nullptr;
+    HIPTRY(hipMalloc(&d_pos, sizeof(double) * 3 * j->n));
+    hipError_t e = hipMalloc(&d_w, sizeof(double) * j->n);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_pos, j->pos.data(), sizeof(double) * 3 * j->n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_w, j->w.data(), sizeof(double) * j->n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        rc = build_grid_dev(S->ctx->device, d_pos, d_w, j->n, j->n_data, (j->flags & ENCORE_DMR) != 0,
+                            j->periodic ? j->box : nullptr, j->edges[j->pl.nbins], s, j->g);
+        j->has_grid = rc == ENCORE_OK;
+    }
+    if (d_pos) (void)hipFree(d_pos);
+    if (d_w) (void)hipFree(d_w);
+    if (e != hipSuccess) return hip_fail(e, "server: catalog upload");
+    if (rc) return rc;
+    std::vector<double>().swap(j->pos);
+    std::vector<double>().swap(j->w);
+    const int64_t outs = j->tb->ntuple * j->tb->nB;
+    HIPTRY(hipMalloc(&j->prim, sizeof(int32_t) * j->n));
+    HIPTRY(hipMalloc(&j->T, sizeof(double) * std::max<int64_t>(outs, 1)));
+    HIPTRY((hipError_t)launch_iota(j->prim, j->n, s));
+    HIPTRY((hipError_t)launch_fill(j->T, outs, 0.0, s));
+    if (j->flags & ENCORE_NORMALIZE) {
+        const std::vector<double> sc = bin_scale(j->pl, j->edges.data(), j->box[0] * j->box[1] * j->box[2]);
+        HIPTRY(hipMalloc(&j->bscale, sizeof(double) * std::max<size_t>(sc.size(), 1)));
+        HIPTRY(hipMemcpyAsync(j->bscale, sc.data(), sizeof(double) * sc.size(), hipMemcpyHostToDevice, s));
+    }
+    HIPTRY(hipStreamSynchronize(s));
+    j->sj.split_rows = job_split_rows(j->pl, j->tb, j->n, cap_rows(j->pl));
+    return ENCORE_OK;
+}
+
+// Contraction of a job whose rows are all reduced; zeta to the host.
+int finish_job(SrvJob* j, Exec& x)
+{
+    const size_t need = (size_t)(j->pl.nlam * j->pl.nB);
+    int rc;
+    if ((rc = ensure(x.zeta, sizeof(double) * std::max<size_t>(need, 1)))) return rc;
+    if ((rc = contract_job(x, j->pl, j->tb, j->T, j->bscale, (double*)x.zeta.p))) return rc;
+    j->zeta.resize(need);
+    HIPTRY(hipMemcpyAsync(j->zeta.data(), x.zeta.p, sizeof(double) * need, hipMemcpyDeviceToHost, x.s));
+    HIPTRY(hipStreamSynchronize(x.s));
+    return ENCORE_OK;
+}
+
+void lane_main(encore_server* S, int li)
+{
+    (void)hipSetDevice(S->ctx->device);
+    Exec& x = S->lanes[li];
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        std::vector<SchedJob*> adm = S->sch.admit();
+        if (!adm.empty()) {
+            const double t = S->now();
+            for (SchedJob* sj : adm) static_cast<SrvJob*>(sj->user)->t_admit = t;
+            lk.unlock();
+            std::vector<int> rcs;
+            std::vector<std::string> errs;
+            for (SchedJob* sj : adm) {
+                SrvJob* j = static_cast<SrvJob*>(sj->user);
+                const int rc = setup_job(S, j, x);
+                rcs.push_back(rc);
+                errs.push_back(rc ? get_error() : "");
+                if (rc) release_job(j);
+            }
+            lk.lock();
+            for (size_t k = 0; k < adm.size(); ++k) {
+                SrvJob* j = static_cast<SrvJob*>(adm[k]->user);
+                if (rcs[k] == ENCORE_OK) {
+                    S->sch.ready(adm[k]);
+                } else {
+                    j->rc = rcs[k];
+                    j->err = errs[k];
+                    j->t_done = S->now();
+                    S->sch.finish(adm[k], false);
+                    S->n_failed++;
+                }
+            }
+            S->cv.notify_all();
+            continue;
+        }
+        std::vector<SchedChunk> picked = S->sch.pick(S->slice_rows);
+        if (picked.empty()) {
+            if (S->stop && S->sch.queued() == 0 && S->sch.active() == 0) break;
+            S->cv.wait(lk);
+            continue;
+        }
+        const double t = S->now();
+        for (const SchedChunk& c : picked) {
+            SrvJob* j = static_cast<SrvJob*>(c.job->user);
+            if (!j->started) { j->started = true; j->t_start = t; }
+        }
+        lk.unlock();
+        SrvJob* j0 = static_cast<SrvJob*>(picked[0].job->user);
+        std::vector<Chunk> chunks;
+        int64_t rows = 0;
+        for (const SchedChunk& c : picked) {
+            SrvJob* j = static_cast<SrvJob*>(c.job->user);
+            chunks.push_back(Chunk{&j->g, j->prim, c.r0, c.r1, j->sj.split_rows, j->T});
+            rows += c.r1 - c.r0;
+        }
+        double mg = 0, mc = 0;
+        int rc = run_slice(x, j0->pl, j0->tb, j0->edges.data(), chunks, &mg, &mc);
+        std::string err = rc ? get_error() : "";
+        lk.lock();
+        S->slices++;
+        S->rows_done += rows;
+        S->ms_gather += mg;
+        S->ms_couple += mc;
+        std::vector<SchedJob*> complete = S->sch.slice_done(picked);
+        if (rc) {
+            // a failed slice fails every job in it; the others are not touched
+            for (const SchedChunk& c : picked) {
+                SrvJob* j = static_cast<SrvJob*>(c.job->user);
+                if (j->sj.state == SchedJob::READY) {
+                    j->rc = rc;
+                    j->err = err;
+                    j->sj.busy = true;
+                }
+            }
+            complete.clear();
+            for (const SchedChunk& c : picked) complete.push_back(c.job);
+        }
+        lk.unlock();
+        std::vector<int> rcs;
+        std::vector<std::string> errs;
+        for (SchedJob* sj : complete) {
+            SrvJob* j = static_cast<SrvJob*>(sj->user);
+            int r = j->rc;
+            if (r == ENCORE_OK) r = finish_job(j, x);
+            rcs.push_back(r);
+            errs.push_back(r ? (j->rc ? j->err : std::string(get_error())) : "");
+            release_job(j);
+        }
+        lk.lock();
+        for (size_t k = 0; k < complete.size(); ++k) {
+            SrvJob* j = static_cast<SrvJob*>(complete[k]->user);
+            if (j->sj.state != SchedJob::READY) continue;   // already finished
+            j->rc = rcs[k];
+            j->err = errs[k];
+            j->t_done = S->now();
+            S->sch.finish(complete[k], rcs[k] == ENCORE_OK);
+            if (rcs[k] == ENCORE_OK) S->n_done++;
+            else S->n_failed++;
+        }
+        S->cv.notify_all();
+    }
+    S->cv.notify_all();
+}
+
+// Device bytes a job holds from admission to completion: catalog staging,
+// D-R weights, cell keys, the grid (sorted points, permutations, cell starts),
+// its primary list, T and the normalisation table.
+size_t footprint(int64_t n, int64_t ncell, int64_t outs, int64_t nB)
+{
+    return (size_t)n * (24 + 8 + 8 + 4 + 32 + 4 + 4 + 4) + (size_t)ncell * 8 + (size_t)outs * 8 +
+           (size_t)nB * 8 + ((size_t)1 << 16);
+}
+
+}  // namespace
+
+extern "C" {
+
+int encore_server_create(encore_ctx* ctx, size_t hbm_budget, int n_lanes, int max_active,
+                         int64_t slice_rows, encore_server** out)
+{
+    if (!ctx || !out) return fail(ENCORE_EINVAL, "NULL ctx or out");
+    if (hbm_budget == 0) return fail(ENCORE_EINVAL, "hbm_budget must be > 0");
+    if (n_lanes < 1 || n_lanes > 8) return fail(ENCORE_EINVAL, "n_lanes must be 1..8");
+    if (max_active < 1) return fail(ENCORE_EINVAL, "max_active must be >= 1");
+    if (slice_rows < 1) return fail(ENCORE_EINVAL, "slice_rows must be >= 1");
+    HIPTRY(hipSetDevice(ctx->device));
+    auto* S = new encore_server(hbm_budget, max_active);
+    S->ctx = ctx;
+    S->slice_rows = slice_rows;
+    S->t0 = Clock::now();
+    S->lanes.resize(n_lanes);
+    for (int i = 0; i < n_lanes; ++i) {
+        const int rc = exec_init(S->lanes[i]);
+        if (rc) {
+            for (Exec& x : S->lanes) exec_release(x);
+            delete S;
+            return rc;
+        }
+    }
+    for (int i = 0; i < n_lanes; ++i) S->threads.emplace_back(lane_main, S, i);
+    *out = S;
+    return ENCORE_OK;
+}
+
+int encore_server_submit(encore_server* S, const double* pos, const double* w, int64_t n, int64_t n_data,
+                         const double* box, int npcf, int lmax, int nbins, const double* edges,
+                         uint32_t flags, int64_t* job_id)
+{
+    if (!S || !job_id) return fail(ENCORE_EINVAL, "NULL server or job_id");
+    if (!pos || !w) return fail(ENCORE_EINVAL, "NULL pos or w");
+    if (n < 1) return fail(ENCORE_EINVAL, "n must be >= 1");
+    if (n >= ((int64_t)1 << 26)) return fail(ENCORE_EINVAL, "catalog exceeds the 2^26-point limit of one grid");
+    auto j = std::make_unique<SrvJob>();
+    int rc;
+    if ((rc = plan_call(npcf, lmax, nbins, edges, flags, &j->pl))) return rc;
+    const double r_max = edges[nbins];
+    j->periodic = flags & ENCORE_PERIODIC;
+    if (j->periodic) {
+        if (!box) return fail(ENCORE_EINVAL, "ENCORE_PERIODIC needs box");
+        for (int a = 0; a < 3; ++a) {
+            if (!(box[a] > 0.0) || !std::isfinite(box[a])) return fail(ENCORE_EINVAL, "box must be > 0");
+            if (2.0 * r_max > box[a]) return fail(ENCORE_EINVAL, "periodic box: edges[nbins] must be <= box/2");
+            j->box[a] = box[a];
+        }
+    } else if (flags & ENCORE_NORMALIZE) {
+        return fail(ENCORE_EINVAL, "ENCORE_NORMALIZE in a served job needs a periodic box");
+    }
+    if ((flags & ENCORE_DMR) && (n_data < 1 || n_data >= n)) return fail(ENCORE_EINVAL, "ENCORE_DMR needs 1 <= n_data < n");
+    // cells of the grid the job will build (an upper bound for open boxes)
+    const double cs = r_max / cell_divisor();
+    int64_t ncell = 1;
+    if (j->periodic) {
+        for (int a = 0; a < 3; ++a) ncell *= std::max<int64_t>(1, (int64_t)std::floor(box[a] / cs));
+    } else {
+        double lo[3] = {pos[0], pos[1], pos[2]}, hi[3] = {pos[0], pos[1], pos[2]};
+        for (int64_t i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a) {
+                const double v = pos[3 * i + a];
+                if (v < lo[a]) lo[a] = v;
+                if (v > hi[a]) hi[a] = v;
+            }
+        for (int a = 0; a < 3; ++a) {
+            const double ext = hi[a] - lo[a];
+            ncell *= std::isfinite(ext) ? (int64_t)std::floor(ext / cs) + 1 : 1;
+        }
+    }
+    const TermTable& tt = term_table(npcf, lmax, j->pl.allparity);
+    const int64_t outs = tt.ntuple * j->pl.nB;
+    j->n = n;
+    j->n_data = n_data;
+    j->flags = flags;
+    j->edges.assign(edges, edges + nbins + 1);
+    j->pos.assign(pos, pos + 3 * n);
+    j->w.assign(w, w + n);
+    j->sj.footprint = footprint(n, ncell, outs, j->pl.nB);
+    j->sj.nrows = n;
+    j->sj.user = j.get();
+    std::lock_guard<std::mutex> lock(S->mu);
+    if (S->stop) return fail(ENCORE_EINVAL, "server is shutting down");
+    // class: jobs with the same kernels, tables and bins can share a slice
+    std::vector<double> key{(double)npcf, (double)lmax, (double)nbins,
+                            (double)(flags & (ENCORE_PREC_MASK | ENCORE_ALLPARITY))};
+    key.insert(key.end(), edges, edges + nbins + 1);
+    auto it = S->classes.find(key);
+    if (it == S->classes.end()) it = S->classes.emplace(key, (uint64_t)S->classes.size()).first;
+    j->sj.cls = it->second;
+    j->sj.id = S->next_id++;
+    j->t_submit = S->now();
+    if (!S->sch.submit(&j->sj))
+        return fail(ENCORE_ESIZE, "job needs " + std::to_string(j->sj.footprint) +
+                                      " device bytes, more than the server budget");
+    *job_id = j->sj.id;
+    S->jobs.emplace(j->sj.id, std::move(j));
+    S->n_submitted++;
+    S->cv.notify_all();
+    return ENCORE_OK;
+}
+
+int encore_server_wait(encore_server* S, int64_t job_id, double timeout_s, double* zeta, size_t zeta_len,
+                       double* times)
+{
+    if (!S) return fail(ENCORE_EINVAL, "NULL server");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->jobs.find(job_id);
+    if (it == S->jobs.end()) return fail(ENCORE_EINVAL, "unknown job id (or already collected)");
+    SrvJob* j = it->second.get();
+    auto finished = [&]() { return j->sj.state == SchedJob::DONE || j->sj.state == SchedJob::FAILED; };
+    if (timeout_s < 0) S->cv.wait(lk, finished);
+    else if (!S->cv.wait_for(lk, std::chrono::duration<double>(timeout_s), finished))
+        return fail(ENCORE_EAGAIN, "job not finished");
+    if (times) {
+        times[0] = j->t_submit; times[1] = j->t_admit; times[2] = j->t_start; times[3] = j->t_done;
+    }
+    if (j->sj.state == SchedJob::FAILED) {
+        const int rc = j->rc ? j->rc : ENCORE_EDEVICE;
+        const std::string msg = "job " + std::to_string(job_id) + " failed: " + j->err;
+        S->jobs.erase(it);
+        return fail(rc, msg);
+    }
+    if (zeta_len < j->zeta.size() || (!zeta && !j->zeta.empty()))
+        return fail(ENCORE_ESIZE, "zeta needs " + std::to_string(j->zeta.size()) + " elements");
+    std::copy(j->zeta.begin(), j->zeta.end(), zeta);
+    S->jobs.erase(it);
+    return ENCORE_OK;
+}
+
+int encore_server_stats(encore_server* S, double* out, size_t out_len)
+{
+    if (!S || !out) return fail(ENCORE_EINVAL, "NULL server or out");
+    if (out_len < 12) return fail(ENCORE_ESIZE, "stats need 12 entries");
+    std::lock_guard<std::mutex> lock(S->mu);
+    size_t ws = 0;
+    for (const Exec& x : S->lanes) ws += exec_bytes(x);
+    const double v[12] = {(double)S->n_submitted, (double)S->n_done, (double)S->n_failed,
+                          (double)S->sch.queued(), (double)S->sch.active(), (double)S->sch.used(),
+                          (double)S->sch.peak(), (double)S->rows_done, (double)S->slices,
+                          S->ms_gather, S->ms_couple, (double)ws};
+    std::copy(v, v + 12, out);
+    return ENCORE_OK;
+}
+
+int encore_server_destroy(encore_server* S)
+{
+    if (!S) return ENCORE_OK;
+    {
+        std::lock_guard<std::mutex> lock(S->mu);
+        S->stop = true;
+        S->cv.notify_all();
+    }
+    for (std::thread& t : S->threads) t.join();
+    (void)hipSetDevice(S->ctx->device);
+    for (auto& kv : S->jobs) release_job(kv.second.get());
+    for (Exec& x : S->lanes) exec_release(x);
+    delete S;
+    return ENCORE_OK;
+}
+
+}  // extern "C"

@@ -18,6 +18,7 @@ ESIZE = -2
 ENOMEM = -3
 EDEVICE = -4
 EUNSUPPORTED = -5
+EAGAIN = -6
 
 PERIODIC = 0x1
 ALLPARITY = 0x2
@@ -46,6 +47,7 @@ SIGNATURES = {
     "encore_free_grid": (_I, [_P]),
     "encore_grid_size": (_I64, [_P]),
     "encore_npcf": (_I, [_P, _P, _I, _I, _I, _P, _U32, _D, _P, _SZ, _P, _I64, _P]),
+    "encore_npcf_batch": (_I, [_P, _P, _I, _I, _I, _I, _P, _U32, _P, _SZ, _P]),
     "encore_npcf_simple": (_I, [_P, _P, _I64, _I, _I, _I, _P, _P, _U32, _P, _SZ]),
     "encore_num_multiplets": (_I64, [_I, _I, _U32]),
     "encore_num_bin_tuples": (_I64, [_I, _I]),
@@ -54,6 +56,11 @@ SIGNATURES = {
     "encore_wigner3j": (_D, [_I, _I, _I, _I, _I, _I]),
     "encore_debug_alm": (_I, [_P, _P, _I, _I, _P, _U32, _P, _I64, _P]),
     "encore_last_timings": (_I, [_P, _P, _SZ]),
+    "encore_server_create": (_I, [_P, _SZ, _I, _I, _I64, ctypes.POINTER(_P)]),
+    "encore_server_submit": (_I, [_P, _P, _P, _I64, _I64, _P, _I, _I, _I, _P, _U32, ctypes.POINTER(_I64)]),
+    "encore_server_wait": (_I, [_P, _I64, _D, _P, _SZ, _P]),
+    "encore_server_stats": (_I, [_P, _P, _SZ]),
+    "encore_server_destroy": (_I, [_P]),
 }
 
 _lib = None
@@ -253,6 +260,22 @@ def npcf(ctx, grid, N, lmax, edges, precision="fp32", allparity=False, normalize
     return out[:nlam * nB].reshape(nlam, nB)
 
 
+def npcf_batch(ctx, grids, N, lmax, edges, precision="fp32", allparity=False, normalize=False,
+               stream=None):
+    """encore_npcf_batch: Z for several catalogs, float64 [n_jobs, n_multiplets, n_bin_tuples]."""
+    edges = _f64(edges, (-1,))
+    nbins = len(edges) - 1
+    flags = PRECISIONS[precision] | (ALLPARITY if allparity else 0) | (NORMALIZE if normalize else 0)
+    nlam = num_multiplets(N, lmax, allparity)
+    nB = num_bin_tuples(N, nbins)
+    nj = len(grids)
+    handles = (_P * nj)(*[g.handle.value for g in grids])
+    out = np.zeros(max(nj * nlam * nB, 1))
+    _check(lib().encore_npcf_batch(ctx.handle, ctypes.cast(handles, _P), nj, int(N), int(lmax), nbins,
+                                   _ptr(edges), flags, _ptr(out), out.size, stream))
+    return out[:nj * nlam * nB].reshape(nj, nlam, nB)
+
+
 def debug_alm(ctx, grid, lmax, edges, primaries, precision="fp64", full_launch=False):
     """encore_debug_alm: complex a~ [k, nbins, (lmax+1)(lmax+2)/2] of the given primaries
     (full_launch: gather every point in one launch, as encore_npcf does)."""
@@ -280,3 +303,63 @@ def npcf_simple(pos, w, N, lmax, edges, box=None, precision="fp32", allparity=Fa
     _check(lib().encore_npcf_simple(_ptr(pos), _ptr(w), len(w), int(N), int(lmax), nbins, _ptr(edges),
                                     _ptr(_box3(box)), flags, _ptr(out), out.size))
     return out[:nlam * nB].reshape(nlam, nB)
+
+
+class Server:
+    """encore_server: catalog jobs admitted by device-memory footprint and run with
+    continuous batching on n_lanes concurrent streams."""
+
+    STATS = ("submitted", "done", "failed", "queued", "admitted", "bytes_held", "peak_bytes_held",
+             "primaries_run", "slices", "gather_ms", "couple_ms", "workspace_bytes")
+
+    def __init__(self, ctx, hbm_budget, n_lanes=2, max_active=64, slice_rows=262144):
+        self.ctx = ctx
+        h = _P()
+        _check(lib().encore_server_create(ctx.handle, int(hbm_budget), int(n_lanes), int(max_active),
+                                          int(slice_rows), ctypes.byref(h)))
+        self.handle = h
+        self._shape = {}
+
+    def submit(self, pos, w, N, lmax, edges, box=None, n_data=None, precision="fp32",
+               allparity=False, normalize=False):
+        pos = _f64(pos, (-1, 3))
+        w = _f64(w, (-1,))
+        edges = _f64(edges, (-1,))
+        flags = (PRECISIONS[precision] | (ALLPARITY if allparity else 0) | (NORMALIZE if normalize else 0)
+                 | (PERIODIC if box is not None else 0) | (DMR if n_data is not None else 0))
+        b = _box3(box)
+        jid = _I64(0)
+        _check(lib().encore_server_submit(self.handle, _ptr(pos), _ptr(w), len(w), int(n_data or 0), _ptr(b),
+                                          int(N), int(lmax), len(edges) - 1, _ptr(edges), flags,
+                                          ctypes.byref(jid)))
+        self._shape[jid.value] = (num_multiplets(N, lmax, allparity), num_bin_tuples(N, len(edges) - 1))
+        return jid.value
+
+    def wait(self, job_id, timeout=None):
+        """(zeta [n_multiplets, n_bin_tuples], times {submit, admit, start, done} in s).
+        Raises EncoreError (code EAGAIN when the timeout passes first)."""
+        nlam, nB = self._shape[job_id]
+        out = np.zeros(max(nlam * nB, 1))
+        t = np.zeros(4)
+        rc = lib().encore_server_wait(self.handle, int(job_id), -1.0 if timeout is None else float(timeout),
+                                      _ptr(out), out.size, _ptr(t))
+        if rc != EAGAIN:
+            self._shape.pop(job_id, None)
+        _check(rc)
+        return out[:nlam * nB].reshape(nlam, nB), dict(zip(("submit", "admit", "start", "done"), t.tolist()))
+
+    def stats(self):
+        out = np.zeros(12)
+        _check(lib().encore_server_stats(self.handle, _ptr(out), 12))
+        return dict(zip(self.STATS, out.tolist()))
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            _check(lib().encore_server_destroy(self.handle))
+        self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
