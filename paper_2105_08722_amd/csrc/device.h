@@ -29,6 +29,7 @@ struct DevGrid {
 // ------------------------------------------------------------------ grid build
 int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, int64_t n_data,
                bool dmr, bool periodic, const double box[3], double r_max, double cell_size,
+               double cell_size_x,
                hipStream_t stream, char* errbuf, size_t errlen);
 void grid_free(DevGrid& g);
 // small utility kernels

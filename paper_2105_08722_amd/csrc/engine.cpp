@@ -354,6 +354,19 @@ double cell_divisor()
     return 6.0;   // cell side r_max / 6: measured best of {4, 6, 8, 10}
 }
 
+double cell_x_subdiv()
+{
+    // Cells are split further along x, the axis along which a cell row is one
+    // contiguous particle range: this trims the x extent of each row piece to
+    // the shell's chord more tightly at no extra row set-up cost.
+    const char* s = getenv("ENCORE_CELL_XSUB");
+    if (s) {
+        const int v = atoi(s);
+        if (v >= 1 && v <= 8) return v;
+    }
+    return 4.0;
+}
+
 int build_grid_dev(int device, const double* d_pos, const double* d_w, int64_t n, int64_t n_data,
                    bool dmr, const double* box, double r_max, hipStream_t s, DevGrid& out)
 {
@@ -363,7 +376,8 @@ int build_grid_dev(int device, const double* d_pos, const double* d_w, int64_t n
         for (int a = 0; a < 3; ++a) bx[a] = box[a];
     char err[256] = {0};
     const int rc = grid_build(out, d_pos, d_w, n, n_data, dmr, box != nullptr, bx, r_max,
-                              r_max / cell_divisor(), s, err, sizeof(err));
+                              r_max / cell_divisor(), r_max / (cell_divisor() * cell_x_subdiv()), s,
+                              err, sizeof(err));
     if (rc != 0) return fail(rc == -1 ? ENCORE_EINVAL : (rc == -3 ? ENCORE_ENOMEM : ENCORE_EDEVICE), err);
     return ENCORE_OK;
 }

@@ -111,6 +111,7 @@ std::vector<double> bin_scale(const NpcfPlan& pl, const double* edges, double V)
 int build_grid_dev(int device, const double* d_pos, const double* d_w, int64_t n, int64_t n_data,
                    bool dmr, const double* box, double r_max, hipStream_t s, DevGrid& out);
 double cell_divisor();
+double cell_x_subdiv();   // x cell side = yz side / this
 
 }  // namespace encore
 

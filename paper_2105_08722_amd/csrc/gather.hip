@@ -166,6 +166,19 @@ __device__ __forceinline__ PT* uni(PT* v)
     return (PT*)(((unsigned long long)hi << 32) | lo);
 }
 
+// Catalog and cell-table pointers come from a descriptor in memory, so the
+// compiler cannot tell their address space and would emit flat loads; flat loads
+// count against the LDS wait counter too, which would make every LDS wait in the
+// candidate loop also wait for the next chunk's prefetch.  Loads through these
+// pointers are global loads.
+template <typename T> using gptr = const __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gptr<T> as_global(const T* p) { return (gptr<T>)p; }
+__device__ __forceinline__ double4 load_point(gptr<double4> p, int j)
+{
+    const gptr<double> d = (gptr<double>)p + 4 * (int64_t)j;
+    return make_double4(d[0], d[1], d[2], d[3]);
+}
+
 // a segment descriptor with every field made wave-uniform (SGPRs)
 __device__ __forceinline__ GatherSeg load_seg(const GatherSeg* segs, int s)
 {
@@ -261,6 +274,8 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         if (uni(a.segs[mid].row0) <= row) slo = mid; else shi = mid - 1;
     }
     const GatherSeg g = load_seg(a.segs, uni(slo));
+    const gptr<double4> gP = as_global(g.P);
+    const gptr<int32_t> gcs = as_global(g.cell_start);
     const int ip = uni(g.prim[row - g.row0]);
     const double4 Pi = g.P[ip];
     const double xi = uni(Pi.x), yi = uni(Pi.y), zi = uni(Pi.z);
@@ -352,8 +367,8 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
                         for (int sx = sxa; sx <= sxb && ns < kSegPerRow; ++sx) {
                             const int plo = max(lo, sx * g.ncx) - sx * g.ncx;
                             const int phi = min(hi, sx * g.ncx + g.ncx - 1) - sx * g.ncx;
-                            const int st = g.cell_start[rowbase + plo];
-                            const int en = g.cell_start[rowbase + phi + 1];
+                            const int st = gcs[rowbase + plo];
+                            const int en = gcs[rowbase + phi + 1];
                             if (en > st) {
                                 const int slot = lane * kSegPerRow + ns;
                                 slot_stc[slot] = st | (((sx + 1) | code_yz) << kCodeShift);
@@ -410,7 +425,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         double4 q_nx = make_double4(0.0, 0.0, 0.0, 0.0);
         if (total > 0) {
             lookup(0, j_nx, code_nx);
-            if (lane < total) q_nx = g.P[j_nx];
+            if (lane < total) q_nx = load_point(gP, j_nx);
         }
         for (int f0 = 0; f0 < total; f0 += kWave) {
             const double4 q = q_nx;
@@ -418,7 +433,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
             const bool valid = f0 + lane < total;
             if (f0 + kWave < total) {
                 lookup(f0 + kWave, j_nx, code_nx);
-                if (f0 + kWave + lane < total) q_nx = g.P[j_nx];
+                if (f0 + kWave + lane < total) q_nx = load_point(gP, j_nx);
             }
             bool ok = false;
             int k = 0;

@@ -297,7 +297,7 @@ void grid_free(DevGrid& g)
 // Returns 0 on success, -1 invalid input (errbuf says why), -3 no memory, -4 HIP error.
 int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, int64_t n_data,
                bool dmr, bool periodic, const double box[3], double r_max, double cell_size,
-               hipStream_t stream, char* errbuf, size_t errlen)
+               double cell_size_x, hipStream_t stream, char* errbuf, size_t errlen)
 {
     int rc = -4;
     int* d_flags = nullptr;
@@ -369,11 +369,13 @@ int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, in
     if (periodic) {
         g.Lx = box[0]; g.Ly = box[1]; g.Lz = box[2];
         g.ox = g.oy = g.oz = 0.0;
-        auto ncell_axis = [&](double L) {
-            int nc = (int)floor(L / cell_size);
+        auto ncell_axis = [&](double L, double c) {
+            int nc = (int)floor(L / c);
             return nc < 1 ? 1 : nc;
         };
-        g.ncx = ncell_axis(box[0]); g.ncy = ncell_axis(box[1]); g.ncz = ncell_axis(box[2]);
+        g.ncx = ncell_axis(box[0], cell_size_x);
+        g.ncy = ncell_axis(box[1], cell_size);
+        g.ncz = ncell_axis(box[2], cell_size);
         g.csx = box[0] / g.ncx; g.csy = box[1] / g.ncy; g.csz = box[2] / g.ncz;
     } else {
         HIPCHK(hipMalloc(&d_mm, sizeof(double) * 6));
@@ -384,8 +386,9 @@ int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, in
         HIPCHK(hipStreamSynchronize(stream));
         g.Lx = g.Ly = g.Lz = 0.0;
         g.ox = mm[0]; g.oy = mm[1]; g.oz = mm[2];
-        g.csx = g.csy = g.csz = cell_size;
-        g.ncx = (int)floor((mm[3] - mm[0]) / cell_size) + 1;
+        g.csx = cell_size_x;
+        g.csy = g.csz = cell_size;
+        g.ncx = (int)floor((mm[3] - mm[0]) / cell_size_x) + 1;
         g.ncy = (int)floor((mm[4] - mm[1]) / cell_size) + 1;
         g.ncz = (int)floor((mm[5] - mm[2]) / cell_size) + 1;
     }

@@ -306,10 +306,11 @@ int encore_server_submit(encore_server* S, const double* pos, const double* w, i
     }
     if ((flags & ENCORE_DMR) && (n_data < 1 || n_data >= n)) return fail(ENCORE_EINVAL, "ENCORE_DMR needs 1 <= n_data < n");
     // cells of the grid the job will build (an upper bound for open boxes)
-    const double cs = r_max / cell_divisor();
+    const double cs_yz = r_max / cell_divisor();
+    const double cs_axis[3] = {cs_yz / cell_x_subdiv(), cs_yz, cs_yz};
     int64_t ncell = 1;
     if (j->periodic) {
-        for (int a = 0; a < 3; ++a) ncell *= std::max<int64_t>(1, (int64_t)std::floor(box[a] / cs));
+        for (int a = 0; a < 3; ++a) ncell *= std::max<int64_t>(1, (int64_t)std::floor(box[a] / cs_axis[a]));
     } else {
         double lo[3] = {pos[0], pos[1], pos[2]}, hi[3] = {pos[0], pos[1], pos[2]};
         for (int64_t i = 0; i < n; ++i)
@@ -320,7 +321,7 @@ int encore_server_submit(encore_server* S, const double* pos, const double* w, i
             }
         for (int a = 0; a < 3; ++a) {
             const double ext = hi[a] - lo[a];
-            ncell *= std::isfinite(ext) ? (int64_t)std::floor(ext / cs) + 1 : 1;
+            ncell *= std::isfinite(ext) ? (int64_t)std::floor(ext / cs_axis[a]) + 1 : 1;
         }
     }
     const TermTable& tt = term_table(npcf, lmax, j->pl.allparity);
