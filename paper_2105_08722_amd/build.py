@@ -16,7 +16,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libencore.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["gather.hip", "couple.hip", "grid.hip", "engine.cpp", "api.cpp", "server.cpp", "tables.cpp"]
+SOURCES = ["gather.hip", "couple.hip", "couple_mfma.hip", "grid.hip", "engine.cpp", "api.cpp", "server.cpp",
+           "tables.cpp", "mfma_plan.cpp"]
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include")]

@@ -131,8 +131,8 @@ int run_jobs(encore_ctx* ctx, const std::vector<JobRows>& jobs, const NpcfPlan& 
     const size_t need = (size_t)(pl.nlam * pl.nB);
     int rc;
     DevTables* tb = nullptr;
-    if ((rc = get_tables(ctx, pl.N, pl.lmax, pl.allparity, pl.nbins, &tb))) return rc;
-    const int64_t outs = tb->ntuple * tb->nB;
+    if ((rc = get_tables_for(ctx, pl, &tb))) return rc;
+    const int64_t outs = acc_len(pl, tb);
     const int64_t cap = cap_rows(pl);
     if ((rc = ensure(x.Tjob, sizeof(double) * (size_t)(njobs * outs)))) return rc;
     if ((rc = ensure(x.zeta, sizeof(double) * (size_t)njobs * std::max<size_t>(need, 1)))) return rc;

@@ -198,7 +198,13 @@ __global__ void __launch_bounds__(kBlock) k_contract(ContractArgs a)
     for (int q = a.term_start[l]; q < a.term_start[l + 1]; ++q) {
         const int t = a.term_tuple[q];
         double s = 0.0;
-        for (int sp = 0; sp < a.nsplit; ++sp) s += a.T[((size_t)sp * a.ntuple + t) * a.nB + b];
+        if (a.tmap) {
+            const int32_t mv = a.tmap[(size_t)t * a.nB + b];
+            s = a.T[mv & 0x7fffffff];
+            if (mv < 0) s = -s;
+        } else {
+            for (int sp = 0; sp < a.nsplit; ++sp) s += a.T[((size_t)sp * a.ntuple + t) * a.nB + b];
+        }
         z += a.term_coef[q] * s;
     }
     if (a.bscale) z *= a.bscale[b];

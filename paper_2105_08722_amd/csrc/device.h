@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "mfma_plan.h"
+
 namespace encore {
 
 constexpr int kMaxBins = 16;     // radial bins per call
@@ -96,6 +98,25 @@ struct CoupleArgs {
     double* T;                // [nsplit][ntuple][nB]
 };
 int launch_couple(const CoupleArgs& a, int precision, hipStream_t stream);
+
+// Split-BF16 MFMA coupling (couple_mfma.hip): per split y, D[y][tile][16][16] of
+// the wave jobs of one shape (RT row tiles x NC column tiles per wave).
+struct MfmaArgs {
+    const float2* alm;        // [nrows][nent] FP32 complex coefficients
+    const double* wprim;      // [nrows]
+    int nent;
+    const int32_t* rows;      // [.][KF + 1]: factor entries, flags
+    const int32_t* cols;      // [.]: entry of the last factor (-1: padding)
+    const int32_t* jobs;      // [njobs][kMfmaJobWidth] of this shape
+    int njobs;
+    int nsplit;
+    const int32_t* split_lo;  // [nsplit]
+    const int32_t* split_hi;  // [nsplit]
+    double* D;                // [nsplit][dense]
+    int64_t dense;            // ntiles * 256
+};
+int launch_couple_mfma(const MfmaArgs& a, int KF, int shape, hipStream_t stream);
+int mfma_stage_bytes(int nent);
 // rows per split that keep the coupling kernels' blocks busy
 int couple_split_rows(int nk, int nbins, int64_t ntuple, int64_t nB, int64_t nrows);
 int couple_ptile(int nbins, int nlm, int precision);
@@ -119,6 +140,7 @@ struct ContractArgs {
     const int32_t* term_tuple;  // [nterm]
     const double* term_coef;    // [nterm]
     const double* bscale;       // [nB] or null
+    const int32_t* tmap;        // null, or [ntuple][nB]: index into T (bit 31: negate); nsplit must be 1
     double* zeta;             // [nlam][nB]
 };
 int launch_contract(const ContractArgs& a, hipStream_t stream);

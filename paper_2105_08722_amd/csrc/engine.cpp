@@ -7,6 +7,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace encore {
 
@@ -105,8 +108,7 @@ int precision_of(uint32_t flags, int* prec)
     switch (flags & ENCORE_PREC_MASK) {
     case ENCORE_PREC_FP64: *prec = 0; return ENCORE_OK;
     case ENCORE_PREC_FP32: *prec = 1; return ENCORE_OK;
-    case ENCORE_PREC_SPLITBF16:
-        return fail(ENCORE_EUNSUPPORTED, "ENCORE_PREC_SPLITBF16 coupling is not built in this version");
+    case ENCORE_PREC_SPLITBF16: *prec = 2; return ENCORE_OK;
     }
     return fail(ENCORE_EINVAL, "unknown precision flag");
 }
@@ -191,6 +193,63 @@ int get_tables(encore_ctx* ctx, int N, int lmax, bool allparity, int nbins, DevT
     return ENCORE_OK;
 }
 
+int get_tables_for(encore_ctx* ctx, const NpcfPlan& pl, DevTables** out)
+{
+    int rc = get_tables(ctx, pl.N, pl.lmax, pl.allparity, pl.nbins, out);
+    if (rc || pl.prec != 2) return rc;
+    DevTables* d = *out;
+    std::lock_guard<std::mutex> lock(ctx->tab_mu);
+    if (d->mf_ready) return ENCORE_OK;
+    const int nent = pl.nbins * (pl.lmax + 1) * (pl.lmax + 2) / 2;
+    if (nent > kMfmaMaxEntries)
+        return fail(ENCORE_EUNSUPPORTED, "ENCORE_PREC_SPLITBF16 needs nbins * (lmax+1)(lmax+2)/2 <= " +
+                                             std::to_string(kMfmaMaxEntries) + " (got " +
+                                             std::to_string(nent) + ")");
+    MfmaPlan P;
+    if ((rc = build_mfma_plan(pl.N, pl.lmax, pl.allparity, pl.nbins, P))) return rc;
+    if ((rc = upload(d->mf_rows, P.rows)) || (rc = upload(d->mf_cols, P.cols)) ||
+        (rc = upload(d->mf_tmap, P.tmap)))
+        return rc;
+    for (int sh = 0; sh < kNumMfmaShapes; ++sh) {
+        if ((rc = upload(d->mf_jobs[sh], P.jobs[sh]))) return rc;
+        d->mf_njobs[sh] = (int)(P.jobs[sh].size() / kMfmaJobWidth);
+    }
+    d->mf_KF = P.KF;
+    d->mf_nent = P.nent;
+    d->mf_dense = P.ntiles * 256;
+    d->mf_ready = true;
+    return ENCORE_OK;
+}
+
+int acc_len_host(const NpcfPlan& pl, int64_t* out)
+{
+    if (pl.prec != 2) {
+        *out = (int64_t)term_table(pl.N, pl.lmax, pl.allparity).ntuple * pl.nB;
+        return ENCORE_OK;
+    }
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, bool, int>, int64_t> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_tuple(pl.N, pl.lmax, pl.allparity, pl.nbins);
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+        if (pl.nbins * (pl.lmax + 1) * (pl.lmax + 2) / 2 > kMfmaMaxEntries)
+            return fail(ENCORE_EUNSUPPORTED, "ENCORE_PREC_SPLITBF16 needs nbins * (lmax+1)(lmax+2)/2 <= " +
+                                                 std::to_string(kMfmaMaxEntries));
+        MfmaPlan P;
+        const int rc = build_mfma_plan(pl.N, pl.lmax, pl.allparity, pl.nbins, P);
+        if (rc) return rc;
+        it = cache.emplace(key, P.ntiles * 256).first;
+    }
+    *out = it->second;
+    return ENCORE_OK;
+}
+
+int64_t acc_len(const NpcfPlan& pl, const DevTables* tb)
+{
+    return pl.prec == 2 ? tb->mf_dense : tb->ntuple * tb->nB;
+}
+
 size_t alm_row_bytes(const NpcfPlan& pl)
 {
     const int nlm = (pl.lmax + 1) * (pl.lmax + 2) / 2;
@@ -209,6 +268,14 @@ int64_t cap_rows(const NpcfPlan& pl)
 
 int64_t job_split_rows(const NpcfPlan& pl, const DevTables* tb, int64_t nprim, int64_t cap)
 {
+    if (pl.prec == 2) {
+        // MFMA coupling: one block per (split, 16 wave jobs); aim at ~2048 blocks
+        int64_t nbj = 0;
+        for (int sh = 0; sh < kNumMfmaShapes; ++sh) nbj += (tb->mf_njobs[sh] + 15) / 16;
+        const int64_t ns = std::max<int64_t>(1, std::min<int64_t>(1024, 2048 / std::max<int64_t>(nbj, 1)));
+        const int64_t rows = std::max<int64_t>(256, (std::max<int64_t>(nprim, 1) + ns - 1) / ns);
+        return std::min<int64_t>(cap, rows);
+    }
     return std::min<int64_t>(
         cap, couple_split_rows(pl.N - 1, pl.nbins, tb->ntuple, tb->nB, std::max<int64_t>(nprim, 1)));
 }
@@ -218,7 +285,7 @@ int run_slice(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double* ed
 {
     const hipStream_t s = x.s;
     const int nlm = (pl.lmax + 1) * (pl.lmax + 2) / 2;
-    const int64_t outs = tb->ntuple * tb->nB;
+    const int64_t outs = acc_len(pl, tb);
     std::vector<GatherSeg> hsegs;
     std::vector<int32_t> slo, shi, rlo, rhi;
     std::vector<double*> rdst;
@@ -301,9 +368,28 @@ int run_slice(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double* ed
     ra.dst = (double* const*)x.redp.p;
 
     HIPTRY(hipEventRecord(x.ev[1], s));
-    HIPTRY((hipError_t)launch_gather(ga, pl.lmax, pl.prec, hsegs.size() > 1, s));
+    HIPTRY((hipError_t)launch_gather(ga, pl.lmax, pl.prec == 0 ? 0 : 1, hsegs.size() > 1, s));
     HIPTRY(hipEventRecord(x.ev[2], s));
-    HIPTRY((hipError_t)launch_couple(ca, pl.prec, s));
+    if (pl.prec == 2) {
+        MfmaArgs ma;
+        ma.alm = (const float2*)x.alm.p;
+        ma.wprim = (const double*)x.wprim.p;
+        ma.nent = tb->mf_nent;
+        ma.rows = tb->mf_rows;
+        ma.cols = tb->mf_cols;
+        ma.nsplit = nsplit;
+        ma.split_lo = dsp;
+        ma.split_hi = dsp + nsplit;
+        ma.D = (double*)x.T.p;
+        ma.dense = tb->mf_dense;
+        for (int sh = 0; sh < kNumMfmaShapes; ++sh) {
+            ma.jobs = tb->mf_jobs[sh];
+            ma.njobs = tb->mf_njobs[sh];
+            HIPTRY((hipError_t)launch_couple_mfma(ma, tb->mf_KF, sh, s));
+        }
+    } else {
+        HIPTRY((hipError_t)launch_couple(ca, pl.prec, s));
+    }
     HIPTRY((hipError_t)launch_reduce(ra, s));
     HIPTRY(hipEventRecord(x.ev[3], s));
     HIPTRY(hipEventSynchronize(x.ev[3]));   // the host tables above are reused by the next slice
@@ -323,6 +409,7 @@ int contract_job(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double*
     xa.term_start = tb->term_start; xa.term_tuple = tb->term_tuple; xa.term_coef = tb->term_coef;
     xa.T = T;
     xa.bscale = bscale;
+    xa.tmap = pl.prec == 2 ? tb->mf_tmap : nullptr;
     xa.zeta = zeta;
     HIPTRY((hipError_t)launch_contract(xa, x.s));
     return ENCORE_OK;

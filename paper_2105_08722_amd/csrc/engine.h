@@ -36,7 +36,17 @@ struct DevTables {
     double* term_coef = nullptr;
     double* kappa = nullptr;
     double* gamma = nullptr;
+    // split-BF16 MFMA plan (built on first use)
+    bool mf_ready = false;
+    int mf_KF = 0, mf_nent = 0;
+    int64_t mf_dense = 0;
+    int32_t* mf_rows = nullptr;
+    int32_t* mf_cols = nullptr;
+    int32_t* mf_jobs[kNumMfmaShapes] = {nullptr, nullptr, nullptr, nullptr};
+    int mf_njobs[kNumMfmaShapes] = {0, 0, 0, 0};
+    int32_t* mf_tmap = nullptr;
 };
+
 
 struct Buf {
     void* p = nullptr;
@@ -78,6 +88,11 @@ struct NpcfPlan {
     int64_t nlam = 0, nB = 0;
 };
 int plan_call(int npcf, int lmax, int nbins, const double* edges, uint32_t flags, NpcfPlan* pl);
+
+// per-job accumulator length: ntuple * nB (VALU coupling) or the dense MFMA tiles
+int64_t acc_len(const NpcfPlan& pl, const DevTables* tb);
+// the same before any device tables exist (host plan, cached)
+int acc_len_host(const NpcfPlan& pl, int64_t* out);
 
 // bytes of a~ per primary row
 size_t alm_row_bytes(const NpcfPlan& pl);
@@ -133,4 +148,6 @@ struct encore_grid {
 namespace encore {
 // thread-safe; the returned tables live as long as the context
 int get_tables(encore_ctx* ctx, int N, int lmax, bool allparity, int nbins, DevTables** out);
+// tables of the call's precision (the MFMA plan too for split-BF16)
+int get_tables_for(encore_ctx* ctx, const NpcfPlan& pl, DevTables** out);
 }  // namespace encore

@@ -1,0 +1,206 @@
+// Host plan of the split-BF16 MFMA coupling (the reassociated contraction of eq.
+// NPCF-mult-discrete-binned-estimator, Appendix B half sum), N = 3..6.
+//
+// The accumulated tensor T[t][B] = sum_i w_i Q_t[prod_k a~^{b_k}_{l_k m_k}(i)] is
+// computed as a set of real GEMMs over K = (primary, re/im):
+//
+//   rows    (rho, q, b_1 .. b_{K-1}): the product P = prod_{k<K} a~ of the first
+//           K-1 factors of a tuple (rho = their (l_k, m_k)), q = Re or Im part;
+//   columns (l_K, b_K) of the last factor at fixed m_K = mu >= 0;
+//   A[row][(i, c)] = (Re P, -Im P) for q = Re, (Im P, Re P) for q = Im;
+//   B[(i, c)][col] = (Re, Im)(w_i a~^{b_K}_{l_K mu}(i)),
+//
+// so that sum_K A B = sum_i w_i Q[P a~].  Rows and columns are grouped in blocks
+// of fixed (mu, beta = b_{K-1}); a block's columns are the bins b_K > beta, so
+// every computed entry has strictly increasing bins.  The blocks are cut into
+// 16 x 16 output tiles; one wave owns up to four tiles of one block (a "wave
+// job") and forms each of its row operands once per primary.
+#include "mfma_plan.h"
+
+#include "../../include/encore.h"
+#include "internal.h"
+
+#include <algorithm>
+#include <cstdlib>
+#include <map>
+#include <vector>
+
+namespace encore {
+
+namespace {
+
+int lm_of(int l, int m) { return l * (l + 1) / 2 + m; }
+
+// combinations of size k from [0, n), lexicographic
+std::vector<std::vector<int>> combos(int n, int k)
+{
+    std::vector<std::vector<int>> out;
+    if (k < 0 || k > n) return out;
+    std::vector<int> c(k);
+    for (int i = 0; i < k; ++i) c[i] = i;
+    while (true) {
+        out.push_back(c);
+        int i = k - 1;
+        while (i >= 0 && c[i] == n - k + i) --i;
+        if (i < 0) break;
+        ++c[i];
+        for (int j = i + 1; j < k; ++j) c[j] = c[j - 1] + 1;
+    }
+    return out;
+}
+
+}  // namespace
+
+const MfmaShape kMfmaShapes[kNumMfmaShapes] = {{4, 1}, {2, 2}, {1, 3}, {1, 4}};
+
+int build_mfma_plan(int N, int lmax, bool allparity, int nbins, MfmaPlan& P)
+{
+    const TermTable& tt = term_table(N, lmax, allparity);
+    const int K = N - 1, KF = K - 1;
+    const int nlm = (lmax + 1) * (lmax + 2) / 2;
+    P = MfmaPlan();
+    P.K = K; P.KF = KF; P.nlm = nlm; P.nbins = nbins; P.nent = nbins * nlm;
+
+    // row keys (rho, q) and column ells per mu
+    std::map<int, std::map<std::vector<int>, int>> rowkeys;   // mu -> key -> index
+    std::map<int, std::map<int, int>> colells;                // mu -> l_K -> index
+    for (int64_t t = 0; t < tt.ntuple; ++t) {
+        const int mu = tt.tuple_m[t * K + K - 1];
+        std::vector<int> key;
+        for (int k = 0; k < KF; ++k) {
+            key.push_back(tt.tuple_l[t * K + k]);
+            key.push_back(tt.tuple_m[t * K + k]);
+        }
+        key.push_back(tt.tuple_odd[t]);
+        auto& rk = rowkeys[mu];
+        if (!rk.count(key)) { const int id = (int)rk.size(); rk[key] = id; }
+        auto& ce = colells[mu];
+        const int lK = tt.tuple_l[t * K + K - 1];
+        if (!ce.count(lK)) { const int id = (int)ce.size(); ce[lK] = id; }
+    }
+    // index of a prefix bin tuple (b_1 .. b_{K-2}) among those below beta
+    struct BlockInfo {
+        int64_t row0 = 0;     // first row in P.rows
+        int nrow = 0;
+        std::vector<int64_t> cg_job0;   // per column group: first wave job (global list order)
+        std::vector<int> cg_shape, cg_nct;
+        std::map<std::vector<int>, int> pre_index;
+        int nrho = 0, nell = 0;
+    };
+    std::map<std::pair<int, int>, BlockInfo> blocks;
+    const int W = KF + 1;
+    std::vector<std::vector<int32_t>> shape_jobs(kNumMfmaShapes);
+    struct JobRef { int shape; int64_t idx; };
+    std::vector<JobRef> joblist;
+    int64_t ntiles = 0;
+
+    for (auto& kv : rowkeys) {
+        const int mu = kv.first;
+        // row keys in index order
+        std::vector<const std::vector<int>*> keys(kv.second.size());
+        for (auto& e : kv.second) keys[e.second] = &e.first;
+        std::vector<int> ells(colells[mu].size());
+        for (auto& e : colells[mu]) ells[e.second] = e.first;
+        for (int beta = K - 2; beta <= nbins - 2; ++beta) {
+            const std::vector<std::vector<int>> pres = combos(beta, K - 2);
+            const int nrow = (int)(pres.size() * keys.size());
+            const int ncol = (int)(ells.size() * (nbins - 1 - beta));
+            if (nrow == 0 || ncol == 0) continue;
+            BlockInfo bi;
+            bi.nrho = (int)keys.size();
+            bi.nell = (int)ells.size();
+            for (size_t p = 0; p < pres.size(); ++p) bi.pre_index[pres[p]] = (int)p;
+            bi.row0 = (int64_t)P.rows.size() / W;
+            bi.nrow = nrow;
+            // rows: prefix bins outer, (rho, q) inner; padded to a multiple of 64
+            for (const auto& pre : pres)
+                for (const auto* key : keys) {
+                    int flags = 1 << 9;   // valid
+                    for (int k = 0; k < KF; ++k) {
+                        const int l = (*key)[2 * k], m = (*key)[2 * k + 1];
+                        const int bin = (k < KF - 1) ? pre[k] : beta;
+                        P.rows.push_back(bin * nlm + lm_of(l, std::abs(m)));
+                        if (m < 0) flags |= 1 << k;
+                    }
+                    if ((*key)[2 * KF]) flags |= 1 << 8;
+                    P.rows.push_back(flags);
+                }
+            const int nrow_pad = (nrow + 63) / 64 * 64;
+            for (int r = nrow; r < nrow_pad; ++r)
+                for (int c = 0; c < W; ++c) P.rows.push_back(0);   // flags 0: invalid
+            // columns: b_K outer, l_K inner, cut into groups of at most 4 tiles
+            std::vector<int32_t> cvals;
+            for (int bK = beta + 1; bK < nbins; ++bK)
+                for (int l : ells) cvals.push_back(bK * nlm + lm_of(l, mu));
+            const int nct_all = (ncol + 15) / 16;
+            const int nrt = (nrow + 15) / 16;
+            for (int cg = 0; cg * 4 < nct_all; ++cg) {
+                const int nct = std::min(4, nct_all - cg * 4);
+                const int shape = nct - 1;   // {4,1} {2,2} {1,3} {1,4}
+                const int RT = kMfmaShapes[shape].RT;
+                const int64_t col_base = (int64_t)P.cols.size();
+                for (int c = 0; c < 16 * nct; ++c) {
+                    const int ci = cg * 64 + c;
+                    P.cols.push_back(ci < ncol ? cvals[ci] : -1);
+                }
+                bi.cg_job0.push_back((int64_t)joblist.size());
+                bi.cg_shape.push_back(shape);
+                bi.cg_nct.push_back(nct);
+                for (int rt0 = 0; rt0 < nrt; rt0 += RT) {
+                    auto& js = shape_jobs[shape];
+                    const int64_t idx = (int64_t)js.size() / kMfmaJobWidth;
+                    js.push_back((int32_t)(bi.row0 + rt0 * 16));
+                    js.push_back((int32_t)col_base);
+                    js.push_back((int32_t)ntiles);
+                    js.push_back(std::min(RT, nrt - rt0));
+                    joblist.push_back(JobRef{shape, idx});
+                    ntiles += (int64_t)RT * nct;
+                }
+            }
+            blocks[{mu, beta}] = std::move(bi);
+        }
+    }
+    if ((int64_t)P.rows.size() / W > INT32_MAX || ntiles * 256 > INT32_MAX)
+        return fail(ENCORE_EUNSUPPORTED, "split-bf16 coupling plan too large for this (N, lmax, nbins)");
+    P.ntiles = ntiles;
+    for (int s = 0; s < kNumMfmaShapes; ++s) P.jobs[s] = std::move(shape_jobs[s]);
+
+    // map (t, B) -> dense index, sign bit 31 = (-1)^(sum of |m| over factors with m < 0)
+    const std::vector<int32_t> bt = enumerate_bin_tuples(N, nbins);
+    const int64_t nB = (int64_t)bt.size() / K;
+    P.tmap.assign((size_t)(tt.ntuple * nB), 0);
+    for (int64_t t = 0; t < tt.ntuple; ++t) {
+        const int mu = tt.tuple_m[t * K + K - 1];
+        std::vector<int> key;
+        int neg = 0;
+        for (int k = 0; k < KF; ++k) {
+            const int m = tt.tuple_m[t * K + k];
+            key.push_back(tt.tuple_l[t * K + k]);
+            key.push_back(m);
+            if (m < 0 && (std::abs(m) & 1)) neg ^= 1;
+        }
+        key.push_back(tt.tuple_odd[t]);
+        const int rho = rowkeys[mu][key];
+        const int lidx = colells[mu][tt.tuple_l[t * K + K - 1]];
+        for (int64_t b = 0; b < nB; ++b) {
+            const int32_t* B = &bt[b * K];
+            const int beta = B[K - 2], bK = B[K - 1];
+            const BlockInfo& bi = blocks.at({mu, beta});
+            const std::vector<int> pre(B, B + K - 2);
+            const int row = bi.pre_index.at(pre) * bi.nrho + rho;
+            const int col = (bK - beta - 1) * bi.nell + lidx;
+            const int cg = col / 64, cc = col % 64;
+            const int shape = bi.cg_shape[cg];
+            const int RT = kMfmaShapes[shape].RT, nct = bi.cg_nct[cg];
+            const int rtg = row / 16;
+            const JobRef jr = joblist[bi.cg_job0[cg] + rtg / RT];
+            const int32_t* job = &P.jobs[jr.shape][jr.idx * kMfmaJobWidth];
+            const int64_t tile = job[2] + (int64_t)(rtg % RT) * nct + cc / 16;
+            const int64_t dense = tile * 256 + (row % 16) * 16 + (cc % 16);
+            P.tmap[(size_t)(t * nB + b)] = (int32_t)dense | (neg ? (int32_t)0x80000000 : 0);
+        }
+    }
+    return ENCORE_OK;
+}
+
+}  // namespace encore

@@ -90,7 +90,7 @@ int setup_job(encore_server* S, SrvJob* j, Exec& x)
 {
     const hipStream_t s = x.s;
     int rc;
-    if ((rc = get_tables(S->ctx, j->pl.N, j->pl.lmax, j->pl.allparity, j->pl.nbins, &j->tb))) return rc;
+    if ((rc = get_tables_for(S->ctx, j->pl, &j->tb))) return rc;
     double* d_pos = nullptr;
     double* d_w = nullptr;
     HIPTRY(hipMalloc(&d_pos, sizeof(double) * 3 * j->n));
@@ -108,7 +108,7 @@ int setup_job(encore_server* S, SrvJob* j, Exec& x)
     if (rc) return rc;
     std::vector<double>().swap(j->pos);
     std::vector<double>().swap(j->w);
-    const int64_t outs = j->tb->ntuple * j->tb->nB;
+    const int64_t outs = acc_len(j->pl, j->tb);
     HIPTRY(hipMalloc(&j->prim, sizeof(int32_t) * j->n));
     HIPTRY(hipMalloc(&j->T, sizeof(double) * std::max<int64_t>(outs, 1)));
     HIPTRY((hipError_t)launch_iota(j->prim, j->n, s));
@@ -324,8 +324,8 @@ int encore_server_submit(encore_server* S, const double* pos, const double* w, i
             ncell *= std::isfinite(ext) ? (int64_t)std::floor(ext / cs_axis[a]) + 1 : 1;
         }
     }
-    const TermTable& tt = term_table(npcf, lmax, j->pl.allparity);
-    const int64_t outs = tt.ntuple * j->pl.nB;
+    int64_t outs = 0;
+    if ((rc = acc_len_host(j->pl, &outs))) return rc;
     j->n = n;
     j->n_data = n_data;
     j->flags = flags;

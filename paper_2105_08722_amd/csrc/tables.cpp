@@ -9,9 +9,11 @@
 // * The half-sum terms of Appendix B: only M with m_{N-1} >= 0 are kept, each with
 //   weight 2 S(m_{N-1}) E(L) C^L_M, S(0) = 1/2, applied to Re (even L) or Im (odd L)
 //   of the product of harmonic coefficients.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <tuple>
 
@@ -237,14 +239,15 @@ static TermTable build_terms(int N, int lmax, bool allparity)
 const TermTable& term_table(int N, int lmax, bool allparity)
 {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, bool>, TermTable*> cache;
+    static std::map<std::tuple<int, int, bool>, std::unique_ptr<TermTable>> cache;
     std::lock_guard<std::mutex> lock(mu);
     auto key = std::make_tuple(N, lmax, allparity);
     auto it = cache.find(key);
     if (it != cache.end()) return *it->second;
-    TermTable* t = new TermTable(build_terms(N, lmax, allparity));
-    cache.emplace(key, t);
-    return *t;
+    auto t = std::make_unique<TermTable>(build_terms(N, lmax, allparity));
+    const TermTable& ref = *t;
+    cache.emplace(key, std::move(t));
+    return ref;
 }
 
 }  // namespace encore

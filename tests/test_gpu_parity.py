@@ -10,6 +10,14 @@ Tolerances
     of a few 1e-7 for catalogs with positive weights; a product of N-1 of them
     carries (N-1) times that.  Bound used: 2e-5 normwise per multiplet and 1e-5
     of max|a~| per harmonic coefficient.
+  * Split-BF16 path: the FP32 gather, then coupling products on the matrix cores
+    with both operands split into bf16 hi + lo and hi*hi + hi*lo + lo*hi summed in
+    FP32 (flushed into FP64 every 256 primaries).  Each product carries at most
+    3 * 2^-18 = 1.1e-5 of its magnitude (two representation errors and the dropped
+    lo*lo term), with random signs across primaries, so the error of a multiplet
+    scales with its conditioning kappa_L = ||sum_i |w_i H_i||| / ||Z_L|| (the oracle
+    returns the sum of magnitudes).  Bound used: 5e-5 of max|Z| and
+    e_L <= 1e-5 max(kappa_L, 1) + 1e-5 for every multiplet.
 """
 import math
 import os
@@ -110,7 +118,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("N,lmax,npts,nbins,periodic,allp", CASES)
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "splitbf16"])
 def test_zeta_matches_oracle(ctx, N, lmax, npts, nbins, periodic, allp, precision):
     _say("zeta N=%d lmax=%d n=%d nb=%d periodic=%s allparity=%s %s"
          % (N, lmax, npts, nbins, periodic, allp, precision))
@@ -120,15 +128,22 @@ def test_zeta_matches_oracle(ctx, N, lmax, npts, nbins, periodic, allp, precisio
     box = L if periodic else None
     with encore.build_grid(ctx, pos, w, r_max=edges[-1], box=box) as g:
         zg = encore.npcf(ctx, g, N, lmax, edges, precision=precision, allparity=allp)
-    zo = oracle.zeta(pos, w, N, lmax, edges, box=box, parity="all" if allp else "even")
+    zo, za = oracle.zeta(pos, w, N, lmax, edges, box=box, parity="all" if allp else "even",
+                         return_abs=True)
     assert zg.shape == zo.shape
     scale = np.max(np.abs(zo))
+    _say("  max|dZ|/max|Z| = %.2e, max e_L = %.2e" % (np.max(np.abs(zg - zo)) / scale,
+                                                       np.max(_normwise(zg, zo))))
     if precision == "fp64":
         assert np.max(np.abs(zg - zo)) <= 1e-10 * scale
         assert np.max(_normwise(zg, zo)) <= 1e-9
-    else:
+    elif precision == "fp32":
         assert np.max(np.abs(zg - zo)) <= 2e-5 * scale
         assert np.max(_normwise(zg, zo)) <= 5e-4
+    else:
+        kappa = np.linalg.norm(za, axis=1) / np.maximum(np.linalg.norm(zo, axis=1), 1e-300)
+        assert np.max(np.abs(zg - zo)) <= 5e-5 * scale
+        assert np.all(_normwise(zg, zo) <= 1e-5 * np.maximum(kappa, 1.0) + 1e-5)
 
 
 def test_dmr_weights_and_subset(ctx):
@@ -177,8 +192,9 @@ def test_degenerate_inputs(ctx):
             encore.npcf(ctx, g, 3, 2, np.array([2.0, 20.0]))     # beyond r_max
         with pytest.raises(encore.EncoreError):
             encore.npcf(ctx, g, 3, 2, edges, primaries=np.array([5, 200]))  # index out of range
+        # split-bf16 stages at most 256 coefficients per primary in LDS
         with pytest.raises(encore.EncoreError) as e:
-            encore.npcf(ctx, g, 4, 2, edges, precision="splitbf16")
+            encore.npcf(ctx, g, 3, 10, np.linspace(1.0, 10.0, 11), precision="splitbf16")
         assert e.value.code == encore.EUNSUPPORTED
     # one point: no pairs at all
     with encore.build_grid(ctx, np.array([[1.0, 2.0, 3.0]]), np.array([2.0]), r_max=10.0) as g:
@@ -249,7 +265,7 @@ def test_config2_alm_full_launch_sampled(ctx, cfg2, precision):
         assert err <= (1e-12 if precision == "fp64" else 1e-5), (i, err)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "splitbf16"])
 def test_config2_zeta_sampled_primaries(ctx, cfg2, precision):
     """4PCF lmax = 5 on the full 800k-point D-R catalog, summed over 48 sampled
     primaries (all 800k are secondaries), vs the oracle on the same primaries."""
@@ -267,14 +283,16 @@ def test_config2_zeta_sampled_primaries(ctx, cfg2, precision):
     _say("  max e_L = %.3e, median kappa = %.1f" % (e.max(), np.median(kappa)))
     if precision == "fp64":
         assert np.max(np.abs(zg - zo)) <= 1e-10 * np.max(np.abs(zo))
-    else:
+    elif precision == "fp32":
         # FP32 error grows with the D-R cancellation: e_L <~ few u32 * kappa_L
         assert np.all(e <= 1e-6 * np.maximum(kappa, 1.0) + 1e-6)
+    else:
+        assert np.all(e <= 1e-5 * np.maximum(kappa, 1.0) + 1e-5)
 
 
 # ------------------------------------------------------------------ batched jobs
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "splitbf16"])
 def test_batch_each_job_matches_alone_and_oracle(ctx, precision):
     """Uneven catalogs (periodic and not, one point, one repeated) in one batched
     call: each job's zeta equals its single-job result and the oracle."""
@@ -304,7 +322,7 @@ def test_batch_each_job_matches_alone_and_oracle(ctx, precision):
         scale = max(np.max(np.abs(zo)), 1e-300)
         # Per-job coupling splits and an in-order reduction: bit-identical to alone.
         assert np.array_equal(zb[j], za), j
-        tol = 1e-10 if precision == "fp64" else 2e-5
+        tol = {"fp64": 1e-10, "fp32": 2e-5, "splitbf16": 5e-5}[precision]
         assert np.max(np.abs(zb[j] - zo)) <= tol * scale
     assert np.array_equal(zb[0], zb[-1])
 

@@ -28,7 +28,8 @@ def ctx():
 def _jobs(seed):
     rng = np.random.default_rng(seed)
     specs = []
-    kinds = [(3, 6, "fp64"), (4, 3, "fp32"), (5, 2, "fp32"), (4, 3, "fp64"), (3, 6, "fp32")]
+    kinds = [(3, 6, "fp64"), (4, 3, "fp32"), (5, 2, "fp32"), (4, 3, "fp64"), (3, 6, "fp32"),
+             (4, 3, "splitbf16")]
     for k in range(10):
         N, lmax, prec = kinds[k % len(kinds)]
         n = int(rng.integers(150, 1500))
