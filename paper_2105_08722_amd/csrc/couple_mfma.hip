@@ -36,7 +36,11 @@ constexpr int kStageP = 16;          // primaries per K block (K = 32 = 16 x (re
 constexpr int kAStride = 18;         // float2 per entry of the FP32 plane (16 + 2 pad)
 constexpr int kBStride = 20;         // bf16x2 words per entry of a bf16 plane (16 + 4 pad)
 constexpr int kStageBytesPerEntry = kAStride * 8 + 2 * kBStride * 4;
-constexpr int kMaxStageVals = (kStageP * kMfmaMaxEntries + kMfThreads - 1) / kMfThreads;
+// staging: each thread moves (entry, pair of primaries) items; consecutive threads
+// take consecutive entries, so the global reads are coalesced along a primary's
+// row and the 16-byte LDS writes of 16 consecutive lanes land in 16 distinct bank
+// slots (the entry stride is 9 slots of 16 bytes)
+constexpr int kMaxStagePairs = (kStageP / 2 * kMfmaMaxEntries + kMfThreads - 1) / kMfThreads;
 constexpr int kFlushSteps = 16;      // FP32 MFMA accumulation over 16 K blocks (256 primaries)
 
 __device__ __forceinline__ unsigned pack_bf16(float x0, float x1)
@@ -61,7 +65,9 @@ __device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c)
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-template <int KF, int RT, int NC>
+// ODD: some rows take the Im part (all-parity multiplets); otherwise every row
+// takes the Re part and no per-row select is needed.
+template <int KF, int RT, int NC, bool ODD>
 __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -88,18 +94,22 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
         nrt = a.jobs[job * kMfmaJobWidth + 3];
     }
     nrt = __builtin_amdgcn_readfirstlane(nrt);
-    // this lane's row of each row tile: factor entries (8 bits each, entries are
-    // below kMfmaMaxEntries) and flags (conjugate bits 0..3, bit 4 = Im part), 5 flag
-    // bits per row tile; padded rows and columns read entry 0, their outputs are
-    // never mapped to T
-    unsigned rent[RT], rfl = 0;
+    // this lane's row of each row tile: byte offsets of its factor entries in the
+    // FP32 plane (entries are below kMfmaMaxEntries, offsets fit 16 bits, two per
+    // word) and flags (conjugate bits 0..3, bit 4 = Im part), 5 flag bits per row
+    // tile; padded rows and columns read entry 0, their outputs are never mapped
+    constexpr int KW = (KF + 1) / 2;
+    unsigned roff[RT][KW], rfl = 0;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const int r = row_base + rt * 16 + c16;
-        unsigned e = 0;
 #pragma unroll
-        for (int k = 0; k < KF; ++k) e |= (active ? (unsigned)a.rows[r * (KF + 1) + k] : 0u) << (8 * k);
-        rent[rt] = e;
+        for (int k = 0; k < KW; ++k) roff[rt][k] = 0;
+#pragma unroll
+        for (int k = 0; k < KF; ++k) {
+            const unsigned e = active ? (unsigned)a.rows[r * (KF + 1) + k] : 0u;
+            roff[rt][k / 2] |= (e * kAStride * 8 + 32 * g) << (16 * (k & 1));
+        }
         const unsigned f = active ? (unsigned)a.rows[r * (KF + 1) + KF] : 0u;
         rfl |= ((f & 15u) | (((f >> 8) & 1u) << 4)) << (5 * rt);
     }
@@ -123,22 +133,29 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
 
     const int p_lo = a.split_lo[split], p_hi = a.split_hi[split];
     const int nstep = (p_hi - p_lo + kStageP - 1) / kStageP;
-    const int nval = kStageP * a.nent;      // (primary, entry) values per K block
 
-    float2 sv[kMaxStageVals];
-    float sw[kMaxStageVals];
+    const int npair = kStageP / 2 * a.nent;   // (entry, primary pair) items per K block
+    float4 sv[kMaxStagePairs];
+    float2 sw[kMaxStagePairs];
     auto gload = [&](int st) {
         const int p0 = p_lo + st * kStageP;
 #pragma unroll
-        for (int q = 0; q < kMaxStageVals; ++q) {
+        for (int q = 0; q < kMaxStagePairs; ++q) {
             const int idx = threadIdx.x + q * kMfThreads;
-            sv[q] = make_float2(0.f, 0.f);
-            sw[q] = 0.f;
-            if (idx < nval) {
-                const int p = idx / a.nent, e = idx - p * a.nent;
-                if (p0 + p < p_hi) {
-                    sv[q] = a.alm[(size_t)(p0 + p) * a.nent + e];
-                    sw[q] = (float)a.wprim[p0 + p];
+            sv[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            sw[q] = make_float2(0.f, 0.f);
+            if (idx < npair) {
+                const int pp = idx / a.nent, e = idx - pp * a.nent;
+                const int p = p0 + 2 * pp;
+                if (p < p_hi) {
+                    const float2 v = a.alm[(size_t)p * a.nent + e];
+                    sv[q].x = v.x; sv[q].y = v.y;
+                    sw[q].x = (float)a.wprim[p];
+                }
+                if (p + 1 < p_hi) {
+                    const float2 v = a.alm[(size_t)(p + 1) * a.nent + e];
+                    sv[q].z = v.x; sv[q].w = v.y;
+                    sw[q].y = (float)a.wprim[p + 1];
                 }
             }
         }
@@ -148,15 +165,16 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
         unsigned* Bh = reinterpret_cast<unsigned*>(buf + (size_t)a.nent * kAStride * 8);
         unsigned* Bl = Bh + (size_t)a.nent * kBStride;
 #pragma unroll
-        for (int q = 0; q < kMaxStageVals; ++q) {
+        for (int q = 0; q < kMaxStagePairs; ++q) {
             const int idx = threadIdx.x + q * kMfThreads;
-            if (idx < nval) {
-                const int p = idx / a.nent, e = idx - p * a.nent;
-                A[e * kAStride + p] = sv[q];
-                unsigned hi, lo;
-                split2(sw[q] * sv[q].x, sw[q] * sv[q].y, hi, lo);
-                Bh[e * kBStride + p] = hi;
-                Bl[e * kBStride + p] = lo;
+            if (idx < npair) {
+                const int pp = idx / a.nent, e = idx - pp * a.nent;
+                *reinterpret_cast<float4*>(A + e * kAStride + 2 * pp) = sv[q];
+                unsigned h0, l0, h1, l1;
+                split2(sw[q].x * sv[q].x, sw[q].x * sv[q].y, h0, l0);
+                split2(sw[q].y * sv[q].z, sw[q].y * sv[q].w, h1, l1);
+                *reinterpret_cast<uint2*>(Bh + e * kBStride + 2 * pp) = make_uint2(h0, h1);
+                *reinterpret_cast<uint2*>(Bl + e * kBStride + 2 * pp) = make_uint2(l0, l1);
             }
         }
     };
@@ -186,7 +204,8 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
                     float pr[4], pi[4];
                     const unsigned fl = rfl >> (5 * rt);
                     {
-                        const float2* src = A + (rent[rt] & 255u) * kAStride + 4 * g;
+                        const float2* src = reinterpret_cast<const float2*>(
+                            reinterpret_cast<const unsigned char*>(A) + (roff[rt][0] & 0xffffu));
                         const float4 v0 = *reinterpret_cast<const float4*>(src);
                         const float4 v1 = *reinterpret_cast<const float4*>(src + 2);
                         const float s = (fl & 1u) ? -1.f : 1.f;
@@ -195,7 +214,8 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
                     }
 #pragma unroll
                     for (int k = 1; k < KF; ++k) {
-                        const float2* src = A + ((rent[rt] >> (8 * k)) & 255u) * kAStride + 4 * g;
+                        const float2* src = reinterpret_cast<const float2*>(
+                            reinterpret_cast<const unsigned char*>(A) + ((roff[rt][k / 2] >> (16 * (k & 1))) & 0xffffu));
                         const float4 v0 = *reinterpret_cast<const float4*>(src);
                         const float4 v1 = *reinterpret_cast<const float4*>(src + 2);
                         const float s = ((fl >> k) & 1u) ? -1.f : 1.f;
@@ -208,12 +228,12 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
                             pr[q] = nr; pi[q] = ni;
                         }
                     }
-                    const bool im = (fl >> 4) & 1u;
+                    const bool im = ODD && ((fl >> 4) & 1u);
                     u32x4 ah, al;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const float x0 = im ? pi[q] : pr[q];
-                        const float x1 = im ? pr[q] : -pi[q];
+                        const float x0 = ODD ? (im ? pi[q] : pr[q]) : pr[q];
+                        const float x1 = ODD ? (im ? pr[q] : -pi[q]) : -pi[q];
                         unsigned h, l;
                         split2(x0, x1, h, l);
                         ah[q] = h;
@@ -254,7 +274,7 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
         }
 }
 
-template <int KF, int RT, int NC>
+template <int KF, int RT, int NC, bool ODD>
 int launch_shape(const MfmaArgs& a, hipStream_t stream)
 {
     const int nbj = (a.njobs + kMfWaves - 1) / kMfWaves;
@@ -262,7 +282,7 @@ int launch_shape(const MfmaArgs& a, hipStream_t stream)
     const int64_t blocks = groups * 8 * nbj;
     if (blocks > INT32_MAX) return (int)hipErrorInvalidValue;
     const size_t lds = 2 * (size_t)a.nent * kStageBytesPerEntry;
-    auto fn = k_couple_mfma<KF, RT, NC>;
+    auto fn = k_couple_mfma<KF, RT, NC, ODD>;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
@@ -275,14 +295,14 @@ int launch_shape(const MfmaArgs& a, hipStream_t stream)
     return (int)hipGetLastError();
 }
 
-template <int KF>
+template <int KF, bool ODD>
 int launch_kf(const MfmaArgs& a, int shape, hipStream_t stream)
 {
     switch (shape) {
-    case 0: return launch_shape<KF, 4, 1>(a, stream);
-    case 1: return launch_shape<KF, 2, 2>(a, stream);
-    case 2: return launch_shape<KF, 1, 3>(a, stream);
-    case 3: return launch_shape<KF, 1, 4>(a, stream);
+    case 0: return launch_shape<KF, 4, 1, ODD>(a, stream);
+    case 1: return launch_shape<KF, 2, 2, ODD>(a, stream);
+    case 2: return launch_shape<KF, 1, 3, ODD>(a, stream);
+    case 3: return launch_shape<KF, 1, 4, ODD>(a, stream);
     }
     return (int)hipErrorInvalidValue;
 }
@@ -295,11 +315,15 @@ int launch_couple_mfma(const MfmaArgs& a, int KF, int shape, hipStream_t stream)
 {
     if (a.njobs == 0 || a.nsplit == 0) return (int)hipSuccess;
     if (a.nent < 1 || a.nent > kMfmaMaxEntries) return (int)hipErrorInvalidValue;
-    switch (KF) {
-    case 1: return launch_kf<1>(a, shape, stream);
-    case 2: return launch_kf<2>(a, shape, stream);
-    case 3: return launch_kf<3>(a, shape, stream);
-    case 4: return launch_kf<4>(a, shape, stream);
+    switch (KF * 2 + (a.any_odd ? 1 : 0)) {
+    case 2: return launch_kf<1, false>(a, shape, stream);
+    case 3: return launch_kf<1, true>(a, shape, stream);
+    case 4: return launch_kf<2, false>(a, shape, stream);
+    case 5: return launch_kf<2, true>(a, shape, stream);
+    case 6: return launch_kf<3, false>(a, shape, stream);
+    case 7: return launch_kf<3, true>(a, shape, stream);
+    case 8: return launch_kf<4, false>(a, shape, stream);
+    case 9: return launch_kf<4, true>(a, shape, stream);
     }
     return (int)hipErrorInvalidValue;
 }

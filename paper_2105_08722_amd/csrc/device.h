@@ -114,6 +114,7 @@ struct MfmaArgs {
     const int32_t* split_hi;  // [nsplit]
     double* D;                // [nsplit][dense]
     int64_t dense;            // ntiles * 256
+    int any_odd;              // some rows take the Im part (all-parity multiplets)
 };
 int launch_couple_mfma(const MfmaArgs& a, int KF, int shape, hipStream_t stream);
 int mfma_stage_bytes(int nent);

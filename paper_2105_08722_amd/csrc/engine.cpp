@@ -382,6 +382,7 @@ int run_slice(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double* ed
         ma.split_hi = dsp + nsplit;
         ma.D = (double*)x.T.p;
         ma.dense = tb->mf_dense;
+        ma.any_odd = pl.allparity ? 1 : 0;
         for (int sh = 0; sh < kNumMfmaShapes; ++sh) {
             ma.jobs = tb->mf_jobs[sh];
             ma.njobs = tb->mf_njobs[sh];

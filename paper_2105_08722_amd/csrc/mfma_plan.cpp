@@ -96,9 +96,18 @@ int build_mfma_plan(int N, int lmax, bool allparity, int nbins, MfmaPlan& P)
 
     for (auto& kv : rowkeys) {
         const int mu = kv.first;
-        // row keys in index order
-        std::vector<const std::vector<int>*> keys(kv.second.size());
-        for (auto& e : kv.second) keys[e.second] = &e.first;
+        // Row keys ordered by the factor that takes bin beta (the last row factor),
+        // then the rest: consecutive rows of a tile then share that factor, whose
+        // LDS read is a broadcast.  The key index is the row key's position here.
+        std::vector<const std::vector<int>*> keys;
+        for (auto& e : kv.second) keys.push_back(&e.first);
+        std::stable_sort(keys.begin(), keys.end(), [&](const std::vector<int>* x, const std::vector<int>* y) {
+            const int o = 2 * (KF - 1);
+            if ((*x)[o] != (*y)[o]) return (*x)[o] < (*y)[o];
+            if ((*x)[o + 1] != (*y)[o + 1]) return (*x)[o + 1] < (*y)[o + 1];
+            return *x < *y;
+        });
+        for (size_t i = 0; i < keys.size(); ++i) kv.second[*keys[i]] = (int)i;
         std::vector<int> ells(colells[mu].size());
         for (auto& e : colells[mu]) ells[e.second] = e.first;
         for (int beta = K - 2; beta <= nbins - 2; ++beta) {
@@ -112,9 +121,9 @@ int build_mfma_plan(int N, int lmax, bool allparity, int nbins, MfmaPlan& P)
             for (size_t p = 0; p < pres.size(); ++p) bi.pre_index[pres[p]] = (int)p;
             bi.row0 = (int64_t)P.rows.size() / W;
             bi.nrow = nrow;
-            // rows: prefix bins outer, (rho, q) inner; padded to a multiple of 64
-            for (const auto& pre : pres)
-                for (const auto* key : keys) {
+            // rows: (rho, q) outer, prefix bins inner; padded to a multiple of 64
+            for (const auto* key : keys)
+                for (const auto& pre : pres) {
                     int flags = 1 << 9;   // valid
                     for (int k = 0; k < KF; ++k) {
                         const int l = (*key)[2 * k], m = (*key)[2 * k + 1];
@@ -187,7 +196,7 @@ int build_mfma_plan(int N, int lmax, bool allparity, int nbins, MfmaPlan& P)
             const int beta = B[K - 2], bK = B[K - 1];
             const BlockInfo& bi = blocks.at({mu, beta});
             const std::vector<int> pre(B, B + K - 2);
-            const int row = bi.pre_index.at(pre) * bi.nrho + rho;
+            const int row = rho * (int)bi.pre_index.size() + bi.pre_index.at(pre);
             const int col = (bK - beta - 1) * bi.nell + lidx;
             const int cg = col / 64, cc = col % 64;
             const int shape = bi.cg_shape[cg];
