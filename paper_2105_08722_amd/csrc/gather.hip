@@ -40,6 +40,7 @@ constexpr int kRowsPerBatch = 64;  // rows set up per lane-parallel pass
 constexpr int kSegPerRow = 6;      // <= 2 x-ranges x 3 periodic images
 constexpr int kSegCap = kRowsPerBatch * kSegPerRow;
 constexpr int kWavesPerBlock = 1;  // waves are independent; no block barriers
+constexpr int kRedCh = 16;         // accumulator values per pass of the lane reduction
 
 __host__ __device__ constexpr int nlm_of(int L) { return (L + 1) * (L + 2) / 2; }
 __host__ __device__ constexpr int lm_index(int l, int m) { return l * (l + 1) / 2 + m; }
@@ -63,9 +64,9 @@ template <> __device__ __forceinline__ double rsqrt_t<double>(double v) { return
 template <typename T, int NBG>
 __host__ __device__ constexpr int ring_bytes()
 {
-    return (NBG * kCap * (int)sizeof(typename Entry<T>::type) > 32 * 65 * (int)sizeof(T))
+    return (NBG * kCap * (int)sizeof(typename Entry<T>::type) > kRedCh * 65 * (int)sizeof(T))
                ? NBG * kCap * (int)sizeof(typename Entry<T>::type)
-               : 32 * 65 * (int)sizeof(T);
+               : kRedCh * 65 * (int)sizeof(T);
 }
 template <typename T, int NBG>
 __host__ __device__ constexpr int wave_lds_bytes()
@@ -134,6 +135,11 @@ __device__ __forceinline__ double sep(double xj, double xi, double shift)
 {
 #pragma clang fp contract(off)
     return (xj - xi) + shift;
+}
+__device__ __forceinline__ double diff(double xj, double xi)
+{
+#pragma clang fp contract(off)
+    return xj - xi;
 }
 __device__ __forceinline__ double dist2(double dx, double dy, double dz)
 {
@@ -208,6 +214,8 @@ __device__ __forceinline__ int wave_excl_scan(int v, int lane, int* total)
 
 constexpr int kCodeShift = 26;               // segment start | (image code << 26)
 constexpr int kStartMask = (1 << kCodeShift) - 1;
+constexpr int kCenterCode = 1 | (1 << 2) | (1 << 4);   // no periodic image on any axis
+constexpr int kMapCap = 2 * kSegCap;         // candidate entries per window (the slot area)
 
 // waves per SIMD the kernel is compiled for, from its accumulator registers
 template <typename T, int L, int NBG, int M0, int M1>
@@ -222,7 +230,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
 {
     using E = typename Entry<T>::type;
     constexpr int NLM = nlm_of(L);
-    constexpr int CH = 32;
+    constexpr int CH = kRedCh;
     extern __shared__ __align__(16) unsigned char smem[];
 
     const int lane = threadIdx.x & (kWave - 1);
@@ -394,102 +402,123 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         if (lane == 0) seg_flat[nseg] = total;
         wave_sync();
 
-        // ---- 2./3. dense 64-candidate chunks across segments; pushes and drains.
-        // Software pipeline: the segment lookup and the global load of chunk c+1
-        // are issued before chunk c is processed.
-        int s_cur = 0;
-        int cur_stc = uni(seg_stc[0]), cur_fl = 0, nxt_fl = uni(seg_flat[1]);
-        // lane -> (candidate index, image code) of the chunk starting at f0
-        auto lookup = [&](int f0, int& jout, int& cout) {
-            while (nxt_fl <= f0) {
-                ++s_cur;
-                cur_stc = uni(seg_stc[s_cur]);
-                cur_fl = nxt_fl;
-                nxt_fl = uni(seg_flat[s_cur + 1]);
+        // ---- 2./3. candidates in windows of kMapCap: the window's (particle index |
+        //      image code) entries are written to LDS once (reusing the slot area),
+        //      padded to whole chunks with the primary itself (r = 0 < R_in, always
+        //      rejected); each 64-candidate chunk then reads one entry per lane.
+        //      The entry read and the global load of chunk c+1 are issued before
+        //      chunk c is processed.
+        unsigned* map = reinterpret_cast<unsigned*>(slot_stc);
+        const unsigned self_entry = (unsigned)ip | ((unsigned)kCenterCode << kCodeShift);
+        int s_lo = 0;
+        for (int w0 = 0; w0 < total; w0 += kMapCap) {
+            const int w1 = min(total, w0 + kMapCap);
+            const int wn = w1 - w0;
+            const int wpad = (wn + kWave - 1) & ~(kWave - 1);
+            wave_sync();                       // previous window's entries are consumed
+            int sg = s_lo;
+            while (sg < nseg) {
+                const int f_s = uni(seg_flat[sg]);
+                if (f_s >= w1) break;
+                const int f_e = uni(seg_flat[sg + 1]);
+                const unsigned stc = (unsigned)uni(seg_stc[sg]);
+                const int a1 = min(f_e, w1);
+                for (int f = max(f_s, w0) + lane; f < a1; f += kWave) map[f - w0] = stc + (unsigned)(f - f_s);
+                if (f_e > w1) break;           // continues into the next window
+                ++sg;
             }
-            const int f = f0 + lane;
-            int my_stc = cur_stc, my_fl = cur_fl;
-            int sn = s_cur + 1;
-            int fn = nxt_fl;
-            while (sn < nseg && fn < f0 + kWave) {
-                const int stc_n = uni(seg_stc[sn]);
-                const int fnext = uni(seg_flat[sn + 1]);
-                if (f >= fn) { my_stc = stc_n; my_fl = fn; }
-                ++sn;
-                fn = fnext;
-            }
-            jout = (my_stc & kStartMask) + (f - my_fl);
-            cout = (int)((unsigned)my_stc >> kCodeShift);
-        };
-        int j_nx = 0, code_nx = 0;
-        double4 q_nx = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (total > 0) {
-            lookup(0, j_nx, code_nx);
-            if (lane < total) q_nx = load_point(gP, j_nx);
-        }
-        for (int f0 = 0; f0 < total; f0 += kWave) {
-            const double4 q = q_nx;
-            const int code = code_nx;
-            const bool valid = f0 + lane < total;
-            if (f0 + kWave < total) {
-                lookup(f0 + kWave, j_nx, code_nx);
-                if (f0 + kWave + lane < total) q_nx = load_point(gP, j_nx);
-            }
-            bool ok = false;
-            int k = 0;
-            double dx = 0.0, dy = 0.0, dz = 0.0;
-            if (valid) {
-                // x_j - x_i first, then the periodic image (+/- L or exactly 0)
-                const double shx = (double)((code & 3) - 1) * Lx;
-                const double shy = (double)(((code >> 2) & 3) - 1) * Ly;
-                const double shz = (double)(((code >> 4) & 3) - 1) * Lz;
-                dx = sep(q.x, xi, shx);
-                dy = sep(q.y, yi, shy);
-                dz = sep(q.z, zi, shz);
+            s_lo = sg;
+            for (int f = wn + lane; f < wpad; f += kWave) map[f] = self_entry;
+            wave_sync();
+
+            // one chunk of 64 candidates: exact FP64 bin, ring push, drains
+            auto chunk = [&](const unsigned me, const double4& q) {
+                // x_j - x_i, then the periodic image (+/- L; chunks without images
+                // skip the shift, which would add exactly 0)
+                double dx = diff(q.x, xi), dy = diff(q.y, yi), dz = diff(q.z, zi);
+                const int code = (int)(me >> kCodeShift);
+                if (__builtin_amdgcn_ballot_w64(code != kCenterCode)) {
+                    dx = sep(dx, 0.0, (double)((code & 3) - 1) * Lx);
+                    dy = sep(dy, 0.0, (double)(((code >> 2) & 3) - 1) * Ly);
+                    dz = sep(dz, 0.0, (double)(((code >> 4) & 3) - 1) * Lz);
+                }
                 const double r2 = dist2(dx, dy, dz);
-                ok = (r2 >= R2in) && (r2 < R2out);
+                const bool ok = (r2 >= R2in) && (r2 < R2out);
+                int k = 0;
+                int slot;
+                if constexpr (NBG == 2) {
+                    // bins of the pair: k = 1 past the interior edge; rank among the
+                    // lanes of the same bin from one ballot per bin
+                    const bool k1 = r2 >= e2k[1];
+                    k = k1 ? 1 : 0;
+                    const unsigned long long m1 = __builtin_amdgcn_ballot_w64(ok && k1);
+                    const unsigned long long m0 = __builtin_amdgcn_ballot_w64(ok && !k1);
+                    const int r0 = tail[0] + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m0 >> 32),
+                                                                           __builtin_amdgcn_mbcnt_lo((unsigned)m0, 0u));
+                    const int r1 = tail[1] + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m1 >> 32),
+                                                                           __builtin_amdgcn_mbcnt_lo((unsigned)m1, 0u));
+                    slot = k1 ? (kCap + (r1 & (kCap - 1))) : (r0 & (kCap - 1));
+                    tail[0] += __popcll(m0);
+                    tail[1] += __popcll(m1);
+                } else {
 #pragma unroll
-                for (int q2 = 1; q2 < NBG; ++q2) k += (r2 >= e2k[q2]) ? 1 : 0;
-            }
-            // ring slots: one ballot per bit of the bin index; the lanes of the
-            // same bin are those agreeing on every bit; tails stay wave-uniform
-            constexpr int NBITS = (NBG <= 1) ? 0 : (NBG <= 2) ? 1 : (NBG <= 4) ? 2 : (NBG <= 8) ? 3 : 4;
-            const unsigned long long okm = __builtin_amdgcn_ballot_w64(ok);
-            unsigned long long bm[NBITS > 0 ? NBITS : 1];
-            unsigned long long same = okm;
+                    for (int q2 = 1; q2 < NBG; ++q2) k += (r2 >= e2k[q2]) ? 1 : 0;
+                    // ring slots: one ballot per bit of the bin index; the lanes of
+                    // the same bin are those agreeing on every bit
+                    constexpr int NBITS = (NBG <= 1) ? 0 : (NBG <= 4) ? 2 : (NBG <= 8) ? 3 : 4;
+                    const unsigned long long okm = __builtin_amdgcn_ballot_w64(ok);
+                    unsigned long long bm[NBITS > 0 ? NBITS : 1];
+                    unsigned long long same = okm;
 #pragma unroll
-            for (int bb = 0; bb < NBITS; ++bb) {
-                bm[bb] = __builtin_amdgcn_ballot_w64(ok && ((k >> bb) & 1));
-                same &= ((k >> bb) & 1) ? bm[bb] : ~bm[bb];
-            }
-            const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(same >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((unsigned)same, 0u));
-            int tk = tail[0];
-#pragma unroll
-            for (int q2 = 1; q2 < NBG; ++q2) tk = (k == q2) ? tail[q2] : tk;
-            const int slot = tk + rank;
-#pragma unroll
-            for (int q2 = 0; q2 < NBG; ++q2) {
-                unsigned long long mq = okm;
-#pragma unroll
-                for (int bb = 0; bb < NBITS; ++bb) mq &= ((q2 >> bb) & 1) ? bm[bb] : ~bm[bb];
-                tail[q2] += __popcll(mq);
-            }
-            if (ok) {
-                E ev;
-                ev.x = (T)dx; ev.y = (T)dy; ev.z = (T)dz; ev.w = (T)q.w;
-                ring[k * kCap + (slot & (kCap - 1))] = ev;
-            }
-            [&]<int... K>(std::integer_sequence<int, K...>) {
-                ([&] {
-                    if (tail[K] - head[K] >= kWave) {
-                        wave_sync();
-                        const E e = ring[K * kCap + ((head[K] + lane) & (kCap - 1))];
-                        accum_pair<T, L, M0, M1>(e.x, e.y, e.z, e.w, acc[K], gam);
-                        head[K] += kWave;
+                    for (int bb = 0; bb < NBITS; ++bb) {
+                        bm[bb] = __builtin_amdgcn_ballot_w64(ok && ((k >> bb) & 1));
+                        same &= ((k >> bb) & 1) ? bm[bb] : ~bm[bb];
                     }
-                }(), ...);
-            }(std::make_integer_sequence<int, NBG>{});
+                    const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(same >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((unsigned)same, 0u));
+                    int tk = tail[0];
+#pragma unroll
+                    for (int q2 = 1; q2 < NBG; ++q2) tk = (k == q2) ? tail[q2] : tk;
+#pragma unroll
+                    for (int q2 = 0; q2 < NBG; ++q2) {
+                        unsigned long long mq = okm;
+#pragma unroll
+                        for (int bb = 0; bb < NBITS; ++bb) mq &= ((q2 >> bb) & 1) ? bm[bb] : ~bm[bb];
+                        tail[q2] += __popcll(mq);
+                    }
+                    slot = k * kCap + ((tk + rank) & (kCap - 1));
+                }
+                if (ok) {
+                    E ev;
+                    ev.x = (T)dx; ev.y = (T)dy; ev.z = (T)dz; ev.w = (T)q.w;
+                    ring[slot] = ev;
+                }
+                [&]<int... K>(std::integer_sequence<int, K...>) {
+                    ([&] {
+                        if (tail[K] - head[K] >= kWave) {
+                            wave_sync();
+                            const E e = ring[K * kCap + ((head[K] + lane) & (kCap - 1))];
+                            accum_pair<T, L, M0, M1>(e.x, e.y, e.z, e.w, acc[K], gam);
+                            head[K] += kWave;
+                        }
+                    }(), ...);
+                }(std::make_integer_sequence<int, NBG>{});
+            };
+            // two chunks per iteration, alternating prefetch registers; the
+            // prefetch is unconditional (past the last chunk it re-reads the last
+            // one) so that waiting for a chunk's loads never waits for the next's
+            const int last = wpad - kWave;
+            unsigned me_a = map[lane];
+            double4 q_a = load_point(gP, (int)(me_a & kStartMask));
+            for (int c0 = 0; c0 < wpad; c0 += 2 * kWave) {
+                const unsigned me_b = map[min(c0 + kWave, last) + lane];
+                const double4 q_b = load_point(gP, (int)(me_b & kStartMask));
+                chunk(me_a, q_a);
+                if (c0 + kWave >= wpad) break;
+                me_a = map[min(c0 + 2 * kWave, last) + lane];
+                q_a = load_point(gP, (int)(me_a & kStartMask));
+                chunk(me_b, q_b);
+            }
         }
         wave_sync();
     }
