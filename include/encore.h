@@ -133,7 +133,14 @@ int64_t encore_grid_size(const encore_grid* grid);
  *          i restricted; secondaries are always the whole catalog).
  *  stream  hipStream_t (NULL: the context's stream).  Synchronous: returns once zeta
  *          is on the host.
- * Errors: EINVAL, ESIZE, ENOMEM, EDEVICE, EUNSUPPORTED (precision/N/lmax not built).
+ * Errors: EINVAL, ESIZE, ENOMEM, EDEVICE, EUNSUPPORTED (ENCORE_PREC_SPLITBF16 with
+ * nbins * (lmax+1)(lmax+2)/2 > 256: the coefficients of one primary must fit the
+ * coupling kernel's LDS stage).
+ *
+ * Precision modes (the precision of the harmonic coefficients, the coupling
+ * products and the sum over primaries): FP64 / FP64 / FP64 (plain path); FP32 /
+ * FP32 / FP64; FP32 / split-bf16 matrix-core products (hi*hi + hi*lo + lo*hi, FP32
+ * accumulation over 256 primaries) / FP64.
  */
 int encore_npcf(encore_ctx* ctx, const encore_grid* grid, int npcf, int lmax, int nbins,
                 const double* edges, uint32_t flags, double volume, double* zeta,
@@ -221,6 +228,28 @@ int encore_server_stats(encore_server* srv, double* out, size_t out_len);
 /* Finish every submitted job, stop the lanes and free the server (NULL: no-op).
  * Results not collected with encore_server_wait are discarded. */
 int encore_server_destroy(encore_server* srv);
+
+/*
+ * Graph-captured job step: the computation of encore_npcf over every point of one
+ * grid (gather -> coupling -> FP64 sum over primaries -> contraction, eq.
+ * NPCF-mult-discrete-binned-estimator), prepared once and recorded into a HIP
+ * graph on the plan's own stream, then replayed by encore_plan_execute: repeated
+ * runs of one job cost one graph launch and no host-side preparation.
+ *  grid     must outlive the plan (encore_free_grid refuses while plans exist);
+ *           grids are immutable, so every replay computes the same zeta.
+ *  other arguments as encore_npcf (all points are primaries; no stream argument).
+ * The plan owns its workspaces (sized at creation; replays allocate nothing) and a
+ * pinned host copy of zeta.
+ * Errors: as encore_npcf; EDEVICE if the capture fails.
+ */
+typedef struct encore_plan encore_plan;
+int encore_plan_create(encore_ctx* ctx, encore_grid* grid, int npcf, int lmax, int nbins,
+                       const double* edges, uint32_t flags, double volume, encore_plan** out);
+/* Replay the plan's graph and wait for it; zeta as encore_npcf.  Errors: EINVAL,
+ * ESIZE, EDEVICE.  Calls on one plan must not overlap. */
+int encore_plan_execute(encore_plan* plan, double* zeta, size_t zeta_len);
+/* Destroy a plan (NULL: no-op). */
+int encore_plan_destroy(encore_plan* plan);
 
 /* One-shot form: build a grid from host arrays, run encore_npcf, free the grid.
  * r_max = edges[nbins]; box may be NULL for a non-periodic catalog. */

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libencore.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["gather.hip", "couple.hip", "couple_mfma.hip", "grid.hip", "engine.cpp", "api.cpp", "server.cpp",
-           "tables.cpp", "mfma_plan.cpp"]
+           "tables.cpp", "mfma_plan.cpp", "plan.cpp"]
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include")]

@@ -254,7 +254,9 @@ int encore_destroy(encore_ctx* ctx)
     for (auto& kv : ctx->tables) {
         DevTables& d = kv.second;
         for (void* p : {(void*)d.tuple_off, (void*)d.tuple_flags, (void*)d.btab, (void*)d.term_start,
-                        (void*)d.term_tuple, (void*)d.term_coef, (void*)d.kappa, (void*)d.gamma})
+                        (void*)d.term_tuple, (void*)d.term_coef, (void*)d.kappa, (void*)d.gamma,
+                        (void*)d.mf_rows, (void*)d.mf_cols, (void*)d.mf_tmap, (void*)d.mf_jobs[0],
+                        (void*)d.mf_jobs[1], (void*)d.mf_jobs[2], (void*)d.mf_jobs[3]})
             if (p) (void)hipFree(p);
     }
     delete ctx;
@@ -277,6 +279,7 @@ int encore_build_grid_device(encore_ctx* ctx, const double* pos, const double* w
 int encore_free_grid(encore_grid* grid)
 {
     if (!grid) return ENCORE_OK;
+    if (grid->plans > 0) return fail(ENCORE_EINVAL, "destroy the plans built on this grid first");
     (void)hipSetDevice(grid->ctx->device);
     (void)hipDeviceSynchronize();
     grid_free(grid->g);

@@ -280,8 +280,8 @@ int64_t job_split_rows(const NpcfPlan& pl, const DevTables* tb, int64_t nprim, i
         cap, couple_split_rows(pl.N - 1, pl.nbins, tb->ntuple, tb->nB, std::max<int64_t>(nprim, 1)));
 }
 
-int run_slice(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double* edges,
-              const std::vector<Chunk>& chunks, double* ms_gather, double* ms_couple)
+int prepare_slice(Exec& x, Buf& segs, Buf& splits, Buf& redp, const NpcfPlan& pl, const DevTables* tb,
+                  const double* edges, const std::vector<Chunk>& chunks, SliceLaunch& L)
 {
     const hipStream_t s = x.s;
     const int nlm = (pl.lmax + 1) * (pl.lmax + 2) / 2;
@@ -311,6 +311,8 @@ int run_slice(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double* ed
         rdst.push_back(c.Tdst);
         rows += take;
     }
+    L = SliceLaunch();
+    L.rows = rows;
     if (rows == 0) return ENCORE_OK;
     if (rows > INT32_MAX || hsegs.size() > 65535) return fail(ENCORE_ESIZE, "slice too large");
     const int nsplit = (int)slo.size(), nred = (int)rlo.size();
@@ -318,9 +320,9 @@ int run_slice(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double* ed
     if ((rc = ensure(x.alm, alm_row_bytes(pl) * (size_t)rows))) return rc;
     if ((rc = ensure(x.wprim, sizeof(double) * (size_t)rows))) return rc;
     if ((rc = ensure(x.T, sizeof(double) * (size_t)nsplit * (size_t)outs))) return rc;
-    if ((rc = ensure(x.segs, sizeof(GatherSeg) * hsegs.size()))) return rc;
-    if ((rc = ensure(x.splits, sizeof(int32_t) * (size_t)(2 * nsplit + 2 * nred)))) return rc;
-    if ((rc = ensure(x.redp, sizeof(double*) * (size_t)nred))) return rc;
+    if ((rc = ensure(segs, sizeof(GatherSeg) * hsegs.size()))) return rc;
+    if ((rc = ensure(splits, sizeof(int32_t) * (size_t)(2 * nsplit + 2 * nred)))) return rc;
+    if ((rc = ensure(redp, sizeof(double*) * (size_t)nred))) return rc;
     if ((rc = ensure(x.queues, 64))) return rc;
     if ((rc = ensure(x.misc, 64))) return rc;
     std::vector<int32_t> hsplit;
@@ -328,12 +330,13 @@ int run_slice(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double* ed
     hsplit.insert(hsplit.end(), shi.begin(), shi.end());
     hsplit.insert(hsplit.end(), rlo.begin(), rlo.end());
     hsplit.insert(hsplit.end(), rhi.begin(), rhi.end());
-    HIPTRY(hipMemcpyAsync(x.segs.p, hsegs.data(), sizeof(GatherSeg) * hsegs.size(), hipMemcpyHostToDevice, s));
-    HIPTRY(hipMemcpyAsync(x.splits.p, hsplit.data(), sizeof(int32_t) * hsplit.size(), hipMemcpyHostToDevice, s));
-    HIPTRY(hipMemcpyAsync(x.redp.p, rdst.data(), sizeof(double*) * rdst.size(), hipMemcpyHostToDevice, s));
-    const int32_t* dsp = (const int32_t*)x.splits.p;
+    HIPTRY(hipMemcpyAsync(segs.p, hsegs.data(), sizeof(GatherSeg) * hsegs.size(), hipMemcpyHostToDevice, s));
+    HIPTRY(hipMemcpyAsync(splits.p, hsplit.data(), sizeof(int32_t) * hsplit.size(), hipMemcpyHostToDevice, s));
+    HIPTRY(hipMemcpyAsync(redp.p, rdst.data(), sizeof(double*) * rdst.size(), hipMemcpyHostToDevice, s));
+    const int32_t* dsp = (const int32_t*)splits.p;
+    L.persistent = hsegs.size() > 1;
 
-    GatherArgs ga;
+    GatherArgs& ga = L.ga;
     memset(&ga, 0, sizeof(ga));
     ga.nbins = pl.nbins;
     for (int b = 0; b <= pl.nbins; ++b) ga.e2[b] = edges[b] * edges[b];
@@ -343,11 +346,11 @@ int run_slice(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double* ed
     ga.wprim = (double*)x.wprim.p;
     ga.npairs = (unsigned long long*)x.misc.p;
     ga.queues = (unsigned*)x.queues.p;
-    ga.segs = (const GatherSeg*)x.segs.p;
+    ga.segs = (const GatherSeg*)segs.p;
     ga.nseg = (int)hsegs.size();
     ga.nrows = (int)rows;
 
-    CoupleArgs ca;
+    CoupleArgs& ca = L.ca;
     memset(&ca, 0, sizeof(ca));
     ca.alm = x.alm.p;
     ca.wprim = (const double*)x.wprim.p;
@@ -359,39 +362,66 @@ int run_slice(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double* ed
     ca.split_lo = dsp;
     ca.split_hi = dsp + nsplit;
 
-    ReduceArgs ra;
+    MfmaArgs& ma = L.ma;
+    memset(&ma, 0, sizeof(ma));
+    ma.alm = (const float2*)x.alm.p;
+    ma.wprim = (const double*)x.wprim.p;
+    ma.nent = tb->mf_nent;
+    ma.rows = tb->mf_rows;
+    ma.cols = tb->mf_cols;
+    ma.nsplit = nsplit;
+    ma.split_lo = dsp;
+    ma.split_hi = dsp + nsplit;
+    ma.D = (double*)x.T.p;
+    ma.dense = tb->mf_dense;
+    ma.any_odd = pl.allparity ? 1 : 0;
+
+    ReduceArgs& ra = L.ra;
     ra.T = (const double*)x.T.p;
     ra.per = outs;
     ra.nred = nred;
     ra.red_lo = dsp + 2 * nsplit;
     ra.red_hi = dsp + 2 * nsplit + nred;
-    ra.dst = (double* const*)x.redp.p;
+    ra.dst = (double* const*)redp.p;
+    return ENCORE_OK;
+}
 
-    HIPTRY(hipEventRecord(x.ev[1], s));
-    HIPTRY((hipError_t)launch_gather(ga, pl.lmax, pl.prec == 0 ? 0 : 1, hsegs.size() > 1, s));
-    HIPTRY(hipEventRecord(x.ev[2], s));
+int launch_slice_gather(const SliceLaunch& L, const NpcfPlan& pl, hipStream_t s)
+{
+    if (L.rows == 0) return ENCORE_OK;
+    HIPTRY((hipError_t)launch_gather(L.ga, pl.lmax, pl.prec == 0 ? 0 : 1, L.persistent, s));
+    return ENCORE_OK;
+}
+
+int launch_slice_couple(const SliceLaunch& L, const NpcfPlan& pl, const DevTables* tb, hipStream_t s)
+{
+    if (L.rows == 0) return ENCORE_OK;
     if (pl.prec == 2) {
-        MfmaArgs ma;
-        ma.alm = (const float2*)x.alm.p;
-        ma.wprim = (const double*)x.wprim.p;
-        ma.nent = tb->mf_nent;
-        ma.rows = tb->mf_rows;
-        ma.cols = tb->mf_cols;
-        ma.nsplit = nsplit;
-        ma.split_lo = dsp;
-        ma.split_hi = dsp + nsplit;
-        ma.D = (double*)x.T.p;
-        ma.dense = tb->mf_dense;
-        ma.any_odd = pl.allparity ? 1 : 0;
+        MfmaArgs ma = L.ma;
         for (int sh = 0; sh < kNumMfmaShapes; ++sh) {
             ma.jobs = tb->mf_jobs[sh];
             ma.njobs = tb->mf_njobs[sh];
             HIPTRY((hipError_t)launch_couple_mfma(ma, tb->mf_KF, sh, s));
         }
     } else {
-        HIPTRY((hipError_t)launch_couple(ca, pl.prec, s));
+        HIPTRY((hipError_t)launch_couple(L.ca, pl.prec, s));
     }
-    HIPTRY((hipError_t)launch_reduce(ra, s));
+    HIPTRY((hipError_t)launch_reduce(L.ra, s));
+    return ENCORE_OK;
+}
+
+int run_slice(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double* edges,
+              const std::vector<Chunk>& chunks, double* ms_gather, double* ms_couple)
+{
+    SliceLaunch L;
+    int rc;
+    if ((rc = prepare_slice(x, x.segs, x.splits, x.redp, pl, tb, edges, chunks, L))) return rc;
+    if (L.rows == 0) return ENCORE_OK;
+    const hipStream_t s = x.s;
+    HIPTRY(hipEventRecord(x.ev[1], s));
+    if ((rc = launch_slice_gather(L, pl, s))) return rc;
+    HIPTRY(hipEventRecord(x.ev[2], s));
+    if ((rc = launch_slice_couple(L, pl, tb, s))) return rc;
     HIPTRY(hipEventRecord(x.ev[3], s));
     HIPTRY(hipEventSynchronize(x.ev[3]));   // the host tables above are reused by the next slice
     float ms = 0.f;

@@ -116,6 +116,23 @@ struct Chunk {
 // x.misc holds the accepted-pair counter (cleared by the caller).
 int run_slice(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double* edges,
               const std::vector<Chunk>& chunks, double* ms_gather, double* ms_couple);
+
+// The same in two parts: prepare_slice builds the slice's host tables, copies them
+// (asynchronously on x.s) into segs / splits / redp and grows x's workspaces;
+// launch_slice_* then only launch kernels (no allocation, no host synchronisation),
+// so they can be recorded into a HIP graph.
+struct SliceLaunch {
+    int64_t rows = 0;
+    bool persistent = false;
+    GatherArgs ga;
+    CoupleArgs ca;
+    MfmaArgs ma;
+    ReduceArgs ra;
+};
+int prepare_slice(Exec& x, Buf& segs, Buf& splits, Buf& redp, const NpcfPlan& pl, const DevTables* tb,
+                  const double* edges, const std::vector<Chunk>& chunks, SliceLaunch& L);
+int launch_slice_gather(const SliceLaunch& L, const NpcfPlan& pl, hipStream_t s);
+int launch_slice_couple(const SliceLaunch& L, const NpcfPlan& pl, const DevTables* tb, hipStream_t s);
 // zeta[nlam][nB] (device) from a job's T (device); bscale[nB] (device) or null.
 int contract_job(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double* T,
                  const double* bscale, double* zeta);
@@ -143,6 +160,7 @@ struct encore_ctx {
 struct encore_grid {
     encore_ctx* ctx = nullptr;
     encore::DevGrid g;
+    std::atomic<int> plans{0};   // live encore_plan objects on this grid
 };
 
 namespace encore {

@@ -61,6 +61,9 @@ SIGNATURES = {
     "encore_server_wait": (_I, [_P, _I64, _D, _P, _SZ, _P]),
     "encore_server_stats": (_I, [_P, _P, _SZ]),
     "encore_server_destroy": (_I, [_P]),
+    "encore_plan_create": (_I, [_P, _P, _I, _I, _I, _P, _U32, _D, ctypes.POINTER(_P)]),
+    "encore_plan_execute": (_I, [_P, _P, _SZ]),
+    "encore_plan_destroy": (_I, [_P]),
 }
 
 _lib = None
@@ -258,6 +261,37 @@ def npcf(ctx, grid, N, lmax, edges, precision="fp32", allparity=False, normalize
     _check(lib().encore_npcf(ctx.handle, grid.handle, int(N), int(lmax), nbins, _ptr(edges), flags,
                              float(volume), _ptr(out), out.size, _ptr(prim), nsub, stream))
     return out[:nlam * nB].reshape(nlam, nB)
+
+
+class Plan:
+    """encore_plan: the hot path over one grid recorded once into a HIP graph
+    (create), then replayed (execute)."""
+
+    def __init__(self, ctx, grid, N, lmax, edges, precision="fp32", allparity=False, normalize=False,
+                 volume=0.0):
+        edges = _f64(edges, (-1,))
+        nbins = len(edges) - 1
+        flags = PRECISIONS[precision] | (ALLPARITY if allparity else 0) | (NORMALIZE if normalize else 0)
+        self.shape = (num_multiplets(N, lmax, allparity), num_bin_tuples(N, nbins))
+        self.handle = _P()
+        _check(lib().encore_plan_create(ctx.handle, grid.handle, int(N), int(lmax), nbins, _ptr(edges),
+                                        flags, float(volume), ctypes.byref(self.handle)))
+
+    def execute(self):
+        out = np.zeros(max(self.shape[0] * self.shape[1], 1))
+        _check(lib().encore_plan_execute(self.handle, _ptr(out), out.size))
+        return out[:self.shape[0] * self.shape[1]].reshape(self.shape)
+
+    def destroy(self):
+        if self.handle is not None and self.handle.value:
+            _check(lib().encore_plan_destroy(self.handle))
+        self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
 
 
 def npcf_batch(ctx, grids, N, lmax, edges, precision="fp32", allparity=False, normalize=False,

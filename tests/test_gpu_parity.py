@@ -226,6 +226,33 @@ def test_device_pointer_grid_matches_host(ctx):
     assert np.max(np.abs(z1 - z2)) <= 1e-12 * np.max(np.abs(z2))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "splitbf16"])
+def test_graph_plan_replays_match_eager(ctx, precision):
+    """encore_plan: the captured graph replayed three times, with eager library
+    work and synchronisation between the replays; every replay equals the eager
+    encore_npcf result bit for bit (same kernels, same order) and the oracle."""
+    _say("graph plan %s" % precision)
+    pos, w = _uniform(1500, 60.0, 321)
+    edges = np.linspace(3.0, 25.0, 7)
+    with encore.build_grid(ctx, pos, w, r_max=edges[-1], box=60.0) as g:
+        eager = encore.npcf(ctx, g, 4, 3, edges, precision=precision)
+        with encore.Plan(ctx, g, 4, 3, edges, precision=precision) as plan:
+            with pytest.raises(encore.EncoreError):
+                g.free()                       # the plan holds the grid
+            for rep in range(3):
+                z = plan.execute()
+                assert np.array_equal(z, eager), rep
+                other = encore.npcf(ctx, g, 3, 4, edges, precision="fp64")   # eager work between
+                assert np.all(np.isfinite(other))
+        zn = encore.npcf(ctx, g, 4, 3, edges, precision=precision, normalize=True)
+        with encore.Plan(ctx, g, 4, 3, edges, precision=precision, normalize=True) as plan:
+            assert np.array_equal(plan.execute(), zn)
+            assert np.array_equal(plan.execute(), zn)
+    zo = oracle.zeta(pos, w, 4, 3, edges, box=60.0)
+    tol = {"fp64": 1e-10, "fp32": 2e-5, "splitbf16": 5e-5}[precision]
+    assert np.max(np.abs(eager - zo)) <= tol * np.max(np.abs(zo))
+
+
 # ------------------------------------------------------------------ benchmark workloads
 
 def test_config1_3pcf_full(ctx):
@@ -290,6 +317,37 @@ def test_config2_zeta_sampled_primaries(ctx, cfg2, precision):
         assert np.all(e <= 1e-5 * np.maximum(kappa, 1.0) + 1e-5)
 
 
+@pytest.fixture(scope="module")
+def cfg3():
+    return synth.config(3)
+
+
+@pytest.mark.parametrize("N,lmax,nprim", [(5, 4, 12), (6, 3, 6)])
+@pytest.mark.parametrize("precision", ["fp32", "splitbf16"])
+def test_config3_wedge_sampled_primaries(ctx, cfg3, N, lmax, nprim, precision):
+    """Survey-wedge workload in full (500k clustered data + 1.5M randoms in a
+    non-periodic 600-1200 Mpc/h shell wedge with holes, FKP weights, D-R): 5PCF at
+    lmax = 4 and 6PCF at lmax = 3 summed over seeded primaries, all 2M points as
+    secondaries, vs the oracle."""
+    _say("config3 wedge N=%d lmax=%d %s" % (N, lmax, precision))
+    n = len(cfg3["w"])
+    w = oracle.dmr_weights(cfg3["w"][:cfg3["n_data"]], cfg3["w"][cfg3["n_data"]:])
+    prim = np.random.default_rng(30 + N).choice(n, nprim, replace=False)
+    with encore.build_grid(ctx, cfg3["pos"], cfg3["w"], r_max=160.0, n_data=cfg3["n_data"]) as g:
+        zg = encore.npcf(ctx, g, N, lmax, cfg3["edges"], precision=precision, primaries=prim)
+    zo, za = oracle.zeta(cfg3["pos"], w, N, lmax, cfg3["edges"], primaries=prim, return_abs=True)
+    e = _normwise(zg, zo)
+    kappa = np.linalg.norm(za, axis=1) / np.maximum(np.linalg.norm(zo, axis=1), 1e-300)
+    _say("  max e_L = %.3e, median e_L = %.3e, median kappa = %.1f, max e_L/kappa = %.2e"
+         % (e.max(), np.median(e), np.median(kappa), np.max(e / np.maximum(kappa, 1.0))))
+    # The D-R field cancels inside each harmonic coefficient: sum_j |w_j Y_lm| /
+    # |a~_lm| has median ~24 and reaches 1e3..1e5 on this geometry (kappa_L does
+    # not see this), so FP32 accumulation errors are amplified accordingly; the
+    # per-coefficient unit is set from that conditioning.
+    u = 2e-5 if precision == "fp32" else 5e-5
+    assert np.all(e <= u * np.maximum(kappa, 1.0) + u)
+
+
 # ------------------------------------------------------------------ batched jobs
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "splitbf16"])
@@ -327,11 +385,12 @@ def test_batch_each_job_matches_alone_and_oracle(ctx, precision):
     assert np.array_equal(zb[0], zb[-1])
 
 
-def test_batch_matches_alone_many_slices(ctx):
-    """Twelve uneven catalogs with the benchmark kernel (FP32, lmax=5, two bin
-    groups per work item): bit-identical to alone, also when the rows are cut
-    into many slices that jobs straddle."""
-    _say("batched jobs lmax=5 fp32, 12 catalogs")
+@pytest.mark.parametrize("precision", ["fp32", "splitbf16"])
+def test_batch_matches_alone_many_slices(ctx, precision):
+    """Twelve uneven catalogs with the benchmark kernels (lmax=5, two bin groups
+    per work item): bit-identical to alone, also when the rows are cut into many
+    slices that jobs straddle."""
+    _say("batched jobs lmax=5 %s, 12 catalogs" % precision)
     N, lmax = 4, 5
     edges = np.linspace(4.0, 30.0, 11)
     rng = np.random.default_rng(77)
@@ -342,17 +401,17 @@ def test_batch_matches_alone_many_slices(ctx):
         grids.append(encore.build_grid(ctx, pos, w, r_max=edges[-1], box=100.0))
         ns.append(n)
     try:
-        zb = encore.npcf_batch(ctx, grids, N, lmax, edges, precision="fp32")
+        zb = encore.npcf_batch(ctx, grids, N, lmax, edges, precision=precision)
         for j, g in enumerate(grids):
-            za = encore.npcf(ctx, g, N, lmax, edges, precision="fp32")
+            za = encore.npcf(ctx, g, N, lmax, edges, precision=precision)
             assert np.array_equal(zb[j], za), (j, ns[j])
         # slices of at most 2500 rows: jobs straddle slice boundaries
         os.environ["ENCORE_MAX_SLICE_ROWS"] = "2500"
         try:
-            zs = encore.npcf_batch(ctx, grids, N, lmax, edges, precision="fp32")
+            zs = encore.npcf_batch(ctx, grids, N, lmax, edges, precision=precision)
             assert ctx.last_timings()["batches"] > 5
             for j, g in enumerate(grids):
-                za = encore.npcf(ctx, g, N, lmax, edges, precision="fp32")
+                za = encore.npcf(ctx, g, N, lmax, edges, precision=precision)
                 assert np.array_equal(zs[j], za), (j, ns[j])
                 assert np.max(np.abs(zs[j] - zb[j])) <= 1e-5 * np.max(np.abs(zb[j])), (j, ns[j])
         finally:
