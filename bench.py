@@ -8,22 +8,30 @@ plus 600,000 uniform randoms weighted -N_D/N_R -- in a periodic 1000 Mpc/h box:
 
 One step = the whole hot path on device-resident inputs: cell-grid build (with
 the D-R weighting) + harmonic-coefficient gather + coupling + FP64 sum over
-primaries + contraction to zeta, ending with zeta on the host.
+primaries + contraction to zeta, ending with zeta on the host.  The default path
+is FP32 harmonic coefficients with the split-bf16 matrix-core coupling; the plain
+FP64 path is timed in the same run and the two results are compared.
+
+Besides the JSON fields of the step, the line carries: the roofline of the
+dominant kernel (the gather, ALU-bound), the matrix-core figures of the coupling,
+the FP64 oracle on the host cores, a batched leg (uneven catalogs in one
+persistent launch) and a served leg (Poisson arrivals, p50/p99 latency).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import json
-import math
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "4PCF primaries/s (ℓmax=5, 10 bins) vs plain FP64 path; p50/p99 job latency"
-PEAK_ALU_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, non-packed VALU (FP32 or FP64)
+PEAK_ALU_TFLOPS = 78.6    # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, non-packed VALU (FP32 or FP64)
+PEAK_BF16_TFLOPS = 2500.0  # dense bf16 matrix cores
 
 
 def log(msg):
@@ -82,15 +90,100 @@ def cpu_baseline(cfg, target_s):
                       "secondaries, FP64 C oracle (full M sum), %.1f s" % (k, dt)}
 
 
+def ns_dmr_catalog(nd, box, seed):
+    """Neyman-Scott data (parents Poisson, ~10 children, sigma 5) thinned to nd, plus
+    3 nd uniform randoms; D-R weights are applied by the library."""
+    import numpy as np
+    from paper_2105_08722_amd import synth
+    dpos, dw = synth.neyman_scott(nd, box, seed)
+    rpos, rw = synth.uniform_box(3 * nd, box, seed + 7919)
+    return np.concatenate([dpos, rpos]), np.concatenate([dw, rw])
+
+
+def batched_leg(ctx, edges, precision, njobs, seed=4000):
+    """Uneven mock catalogs (N_D ~ U[50k, 400k] Neyman-Scott data + 3 N_D randoms each,
+    periodic 1000 Mpc/h) in one encore_npcf_batch call (one persistent gather launch
+    per slice over all catalogs)."""
+    import numpy as np
+    from paper_2105_08722_amd import encore
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(50_000, 400_001, size=njobs)
+    grids = []
+    tot = 0
+    try:
+        for k, nd in enumerate(sizes):
+            pos, w = ns_dmr_catalog(int(nd), 1000.0, seed + k)
+            grids.append(encore.build_grid(ctx, pos, w, r_max=edges[-1], box=1000.0, n_data=int(nd)))
+            tot += len(w)
+        encore.npcf_batch(ctx, grids[:2], 4, 5, edges, precision=precision)   # warm
+        t0 = time.perf_counter()
+        encore.npcf_batch(ctx, grids, 4, 5, edges, precision=precision)
+        dt = time.perf_counter() - t0
+    finally:
+        for g in grids:
+            g.free()
+    return {"value": tot / dt, "unit": "primaries/s", "jobs": njobs, "primaries": int(tot),
+            "seconds": dt, "precision": precision,
+            "workload": "%d Neyman-Scott D-R catalogs, N_D ~ U[50k, 400k] + 3 N_D randoms, periodic "
+                        "1000 Mpc/h, 4PCF lmax=5, 10 bins, one batched call (grids prebuilt)" % njobs}
+
+
+def served_leg(ctx, edges, njobs, rate, seed=5000):
+    """Poisson request stream (mean `rate` jobs/s) mixing 3PCF lmax=10 (FP32), 4PCF
+    lmax=5 and 5PCF lmax=4 (split-bf16) jobs on Neyman-Scott D-R catalogs of
+    log-uniform size; latency = arrival (submit) to result ready."""
+    import numpy as np
+    from paper_2105_08722_amd import encore
+    rng = np.random.default_rng(seed)
+    kinds = [(3, 10, "fp32"), (4, 5, "splitbf16"), (5, 4, "splitbf16")]
+    jobs = []
+    for k in range(njobs):
+        N, L, prec = kinds[int(rng.integers(0, 3))]
+        ntot = int(np.exp(rng.uniform(np.log(1e4), np.log(1e6))))
+        nd = max(ntot // 4, 1)
+        pos, w = ns_dmr_catalog(nd, 1000.0, seed + 13 * k)
+        jobs.append((N, L, prec, pos, w, nd))
+    gaps = rng.exponential(1.0 / rate, size=njobs)
+    ids = [None] * njobs
+    with encore.Server(ctx, hbm_budget=64 << 30, n_lanes=3, max_active=16, slice_rows=262144) as srv:
+        def feed():
+            for k, (N, L, prec, pos, w, nd) in enumerate(jobs):
+                time.sleep(float(gaps[k]))
+                ids[k] = srv.submit(pos, w, N, L, edges, box=1000.0, n_data=nd, precision=prec)
+
+        t0 = time.perf_counter()
+        th = threading.Thread(target=feed)
+        th.start()
+        th.join()
+        lat = []
+        for k in range(njobs):
+            _, t = srv.wait(ids[k])
+            lat.append(t["done"] - t["submit"])
+        dt = time.perf_counter() - t0
+        st = srv.stats()
+    lat = np.array(lat)
+    return {"jobs": njobs, "rate_jobs_per_s": rate, "jobs_per_s": njobs / dt,
+            "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+            "mean_latency_s": float(lat.mean()), "primaries_run": st["primaries_run"],
+            "peak_bytes_held": st["peak_bytes_held"],
+            "workload": "Poisson arrivals (mean %.1f jobs/s), jobs uniform over {3PCF lmax=10 fp32, "
+                        "4PCF lmax=5 split-bf16, 5PCF lmax=4 split-bf16}, 1e4-1e6 points "
+                        "(log-uniform, 1:3 data:randoms, Neyman-Scott D-R, periodic 1000 Mpc/h), "
+                        "10 bins [20,160]; 3 lanes" % rate}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "splitbf16"])
+    ap.add_argument("--precision", default="splitbf16", choices=["fp32", "fp64", "splitbf16"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--batched-jobs", type=int, default=8, help="0: skip the batched leg")
+    ap.add_argument("--served-jobs", type=int, default=24, help="0: skip the served leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (the reference "
                          "dispatch for scaling FETCH_SIZE/WRITE_SIZE counters)")
@@ -123,6 +216,13 @@ def main():
         log("copy calibration: %d MiB read + %d MiB written" % (args.calibrate_copy, args.calibrate_copy))
         del src, dst
     ctx = encore.Context(0)
+    tuned = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        tuned = encore.autotune(ctx, cfg["pos"], cfg["w"], N, L, edges, box=cfg["box"],
+                                n_data=cfg["n_data"], precision=args.precision, n_sample=16384)
+        tuned["tuning_s"] = time.perf_counter() - t0
+        log("autotune: %s" % tuned)
 
     def step(prec):
         g = encore.build_grid_device(ctx, tp, tw, r_max=edges[-1], box=cfg["box"], n_data=cfg["n_data"])
@@ -153,13 +253,24 @@ def main():
     c_ms = couple_ms / args.steps
     flops = gather_flops_per_pair(L) * pairs
     achieved = flops / (g_ms * 1e-3) / 1e12
+    nbg = tuned["bins_per_item"] if tuned else 2
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_ALU_TFLOPS, "traffic": gather_traffic(pairs),
-                "kernel": "k_gather<float,5,2,0,5> (harmonic-coefficient gather)",
+                "kernel": "k_gather<float,5,%d,0,5> (harmonic-coefficient gather)" % nbg,
                 "launch_ms": g_ms, "pairs_per_launch": pairs,
                 "flops_per_pair": gather_flops_per_pair(L)}
 
     extra = {}
+    if args.precision == "splitbf16":
+        ms_ = encore.mfma_plan_stats(N, L, len(edges) - 1)
+        raw = ms_["tiles_per_16"] * 3 * 16 * 16 * 32 * 2 / 16.0 * n      # MFMA flops issued per step
+        useful = 4.0 * ms_["t_entries"] * n                               # real triple products x (re, im) x FMA
+        extra["coupling_mfma"] = {
+            "bound": "mfma", "unit": "TFLOP/s", "peak": PEAK_BF16_TFLOPS, "coupling_ms": c_ms,
+            "issued": raw / (c_ms * 1e-3) / 1e12, "issued_frac": raw / (c_ms * 1e-3) / 1e12 / PEAK_BF16_TFLOPS,
+            "useful": useful / (c_ms * 1e-3) / 1e12,
+            "useful_frac_of_split_peak": useful / (c_ms * 1e-3) / 1e12 / (PEAK_BF16_TFLOPS / 3.0),
+            "tiles_per_16_primaries": ms_["tiles_per_16"], "t_entries_per_primary": ms_["t_entries"]}
     if not args.no_fp64 and args.precision != "fp64":
         log("plain FP64 path, one step")
         step("fp64")
@@ -174,6 +285,15 @@ def main():
         extra["speedup_vs_fp64_path"] = extra["fp64_path"]["ms_per_step"] / ms
         extra["accuracy_vs_fp64_path"] = {"max_e_lambda": float(np.max(num[keep] / den[keep])),
                                           "median_e_lambda": float(np.median(num[keep] / den[keep]))}
+    if args.batched_jobs > 0:
+        log("batched leg: %d catalogs" % args.batched_jobs)
+        extra["batched"] = batched_leg(ctx, edges, args.precision, args.batched_jobs)
+        log("batched: %.3g primaries/s" % extra["batched"]["value"])
+    if args.served_jobs > 0:
+        log("served leg: %d jobs" % args.served_jobs)
+        extra["served"] = served_leg(ctx, edges, args.served_jobs, 4.0)
+        log("served: p50 %.2f s, p99 %.2f s" % (extra["served"]["p50_latency_s"],
+                                                 extra["served"]["p99_latency_s"]))
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, args.cpu_seconds)
@@ -188,7 +308,7 @@ def main():
         "config": {"workload": "4PCF lmax=5, 10 bins [20,160] Mpc/h, Neyman-Scott 200k data + "
                                "600k uniform randoms (D-R), periodic 1000 Mpc/h box",
                    "N": N, "lmax": L, "nbins": 10, "primaries": n, "precision": args.precision,
-                   "gather_ms": g_ms, "couple_ms": c_ms, "pairs": pairs},
+                   "gather_ms": g_ms, "couple_ms": c_ms, "pairs": pairs, "autotune": tuned},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

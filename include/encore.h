@@ -251,6 +251,32 @@ int encore_plan_execute(encore_plan* plan, double* zeta, size_t zeta_len);
 /* Destroy a plan (NULL: no-op). */
 int encore_plan_destroy(encore_plan* plan);
 
+/*
+ * Work of the split-BF16 MFMA coupling for (npcf, lmax, nbins, ENCORE_ALLPARITY in
+ * flags), host only: out[0] = 16x16 output tiles computed per 16 primaries (three
+ * 16x16x32 bf16 MFMAs each), out[1] = 16-row operand tiles formed per 16
+ * primaries, out[2] = entries of T used (tuples x bin tuples), out[3] = dense
+ * entries accumulated.  Errors: EINVAL, ESIZE (out_len < 4), EUNSUPPORTED.
+ */
+int encore_mfma_plan_stats(int npcf, int lmax, int nbins, uint32_t flags, int64_t* out, size_t out_len);
+
+/*
+ * Autotuner of the launch shapes: builds trial grids of the catalog (host arrays,
+ * as encore_build_grid) with several cell shapes (cell side r_max/d on y and z,
+ * r_max/(d*s) on x, where one cell row is a contiguous particle range) and times,
+ * for each, the gather + coupling of this job (as encore_npcf) over a sample of
+ * n_sample primaries spread over the input order, for every compiled
+ * bins-per-work-item value of the gather.  The fastest (d, s) becomes the cell
+ * shape of later grids built on ctx; the fastest bins-per-item value is used by
+ * later calls with the same lmax, gather precision and nbins.  The choice changes
+ * only the order of floating-point operations, never what is computed.
+ *  report  NULL or [5]: d, s, bins per item, best ms, ms of the default shape.
+ * Errors: as encore_build_grid and encore_npcf; ESIZE if report_len < 5.
+ */
+int encore_autotune(encore_ctx* ctx, const double* pos, const double* w, int64_t n, int64_t n_data,
+                    const double* box, int npcf, int lmax, int nbins, const double* edges, uint32_t flags,
+                    int64_t n_sample, double* report, size_t report_len);
+
 /* One-shot form: build a grid from host arrays, run encore_npcf, free the grid.
  * r_max = edges[nbins]; box may be NULL for a non-periodic catalog. */
 int encore_npcf_simple(const double* pos, const double* w, int64_t n, int npcf, int lmax,

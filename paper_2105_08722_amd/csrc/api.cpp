@@ -85,8 +85,10 @@ int build_grid_impl(encore_ctx* ctx, const double* pos, const double* w, int64_t
     }
     auto* gr = new encore_grid();
     gr->ctx = ctx;
+    double div = 0.0, xsub = 0.0;
+    ctx_cells(ctx, &div, &xsub);
     const int rc = build_grid_dev(ctx->device, d_pos, d_w, n, n_data, (flags & ENCORE_DMR) != 0,
-                                  periodic ? box : nullptr, r_max, s, gr->g);
+                                  periodic ? box : nullptr, r_max, div, xsub, s, gr->g);
     if (tmp_pos) (void)hipFree(tmp_pos);
     if (tmp_w) (void)hipFree(tmp_w);
     if (rc != 0) {
@@ -353,6 +355,7 @@ int encore_npcf(encore_ctx* ctx, const encore_grid* grid, int npcf, int lmax, in
     NpcfPlan pl;
     int rc;
     if ((rc = plan_call(npcf, lmax, nbins, edges, flags, &pl))) return rc;
+    pl.nbg = ctx_nbg(ctx, pl);
     if ((rc = check_grids(&grid, 1, ctx, edges, nbins, flags, volume))) return rc;
     const size_t need = (size_t)(pl.nlam * pl.nB);
     if (!zeta && need > 0) return fail(ENCORE_EINVAL, "zeta is NULL");
@@ -381,6 +384,7 @@ int encore_npcf_batch(encore_ctx* ctx, const encore_grid* const* grids, int njob
     NpcfPlan pl;
     int rc;
     if ((rc = plan_call(npcf, lmax, nbins, edges, flags, &pl))) return rc;
+    pl.nbg = ctx_nbg(ctx, pl);
     if ((rc = check_grids(grids, njobs, ctx, edges, nbins, flags, 0.0))) return rc;
     const size_t need = (size_t)(pl.nlam * pl.nB);
     if (!zeta && need > 0) return fail(ENCORE_EINVAL, "zeta is NULL");
@@ -407,6 +411,117 @@ int encore_npcf_batch(encore_ctx* ctx, const encore_grid* const* grids, int njob
         }
         return run_jobs(ctx, jobs, pl, flags, edges, 0.0, zeta);
     });
+}
+
+int encore_mfma_plan_stats(int npcf, int lmax, int nbins, uint32_t flags, int64_t* out, size_t out_len)
+{
+    if (!out || out_len < 4) return fail(ENCORE_ESIZE, "out needs 4 elements");
+    if (npcf < 3 || npcf > 6) return fail(ENCORE_EINVAL, "npcf must be 3..6");
+    if (!valid_lmax(npcf, lmax)) return fail(ENCORE_EINVAL, "lmax out of range for this N");
+    if (nbins < 1 || nbins > kMaxBins) return fail(ENCORE_EINVAL, "nbins out of range");
+    if (nbins * (lmax + 1) * (lmax + 2) / 2 > kMfmaMaxEntries)
+        return fail(ENCORE_EUNSUPPORTED, "too many coefficients per primary for the MFMA coupling");
+    MfmaPlan P;
+    int rc;
+    if ((rc = build_mfma_plan(npcf, lmax, flags & ENCORE_ALLPARITY, nbins, P))) return rc;
+    int64_t tiles = 0, rts = 0;
+    for (int sh = 0; sh < kNumMfmaShapes; ++sh)
+        for (size_t j = 0; j < P.jobs[sh].size() / kMfmaJobWidth; ++j) {
+            const int nrt = P.jobs[sh][j * kMfmaJobWidth + 3];
+            rts += nrt;
+            tiles += (int64_t)nrt * kMfmaShapes[sh].NC;
+        }
+    out[0] = tiles;
+    out[1] = rts;
+    out[2] = (int64_t)P.tmap.size();
+    out[3] = P.ntiles * 256;
+    return ENCORE_OK;
+}
+
+int encore_autotune(encore_ctx* ctx, const double* pos, const double* w, int64_t n, int64_t n_data,
+                    const double* box, int npcf, int lmax, int nbins, const double* edges, uint32_t flags,
+                    int64_t n_sample, double* report, size_t report_len)
+{
+    if (!ctx || !pos || !w) return fail(ENCORE_EINVAL, "NULL ctx, pos or w");
+    if (n < 1) return fail(ENCORE_EINVAL, "n must be >= 1");
+    if (report && report_len < 5) return fail(ENCORE_ESIZE, "report needs 5 elements");
+    NpcfPlan pl;
+    int rc;
+    if ((rc = plan_call(npcf, lmax, nbins, edges, flags, &pl))) return rc;
+    const bool periodic = flags & ENCORE_PERIODIC;
+    if (periodic && !box) return fail(ENCORE_EINVAL, "ENCORE_PERIODIC needs box");
+    const double r_max = edges[nbins];
+    const int gprec = pl.prec == 0 ? 0 : 1;
+    const std::vector<int> nbgs = gather_nbg_options(lmax, gprec);
+    // cell shapes tried: (y/z divisor of r_max, extra x subdivision); the default first
+    static const double kCells[][2] = {{6, 4}, {6, 8}, {8, 4}, {8, 2}, {5, 4}, {4, 6}};
+    const int64_t k = std::min<int64_t>(n, std::max<int64_t>(1, n_sample));
+    std::vector<int64_t> sample(k);
+    for (int64_t i = 0; i < k; ++i) sample[i] = i * n / k;   // spread over the input order
+    const size_t need = (size_t)std::max<int64_t>(pl.nlam * pl.nB, 1);
+    std::vector<double> ztmp(need);
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    HIPTRY(hipSetDevice(ctx->device));
+    Exec& x = ctx->main;
+    const hipStream_t s = x.s;
+    double* d_pos = nullptr;
+    double* d_w = nullptr;
+    HIPTRY(hipMalloc(&d_pos, sizeof(double) * 3 * n));
+    hipError_t e = hipMalloc(&d_w, sizeof(double) * n);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_pos, pos, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_w, w, sizeof(double) * n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+        if (d_pos) (void)hipFree(d_pos);
+        if (d_w) (void)hipFree(d_w);
+        return hip_fail(e, "encore_autotune: catalog upload");
+    }
+    double best = 1e300, best_div = 0, best_xsub = 0, dflt = 0;
+    int best_nbg = 0;
+    rc = ENCORE_OK;
+    for (const auto& cell : kCells) {
+        encore_grid tg;
+        tg.ctx = ctx;
+        rc = build_grid_dev(ctx->device, d_pos, d_w, n, n_data, (flags & ENCORE_DMR) != 0,
+                            periodic ? box : nullptr, r_max, cell[0], cell[1], s, tg.g);
+        if (rc) break;
+        int64_t np = 0;
+        if ((rc = make_primaries(x, &tg, sample.data(), k, &np)) == ENCORE_OK) {
+            for (size_t q = 0; q < nbgs.size() && rc == ENCORE_OK; ++q) {
+                pl.nbg = nbgs[q];
+                double t = 1e300;
+                for (int rep = 0; rep < 3 && rc == ENCORE_OK; ++rep) {
+                    std::vector<JobRows> jobs{JobRows{&tg, (const int32_t*)x.prim.p, np}};
+                    HIPTRY(hipEventRecord(x.ev[0], s));
+                    rc = run_jobs(ctx, jobs, pl, flags & ~ENCORE_NORMALIZE, edges, 0.0, ztmp.data());
+                    t = std::min(t, ctx->timings[1] + ctx->timings[2]);
+                }
+                if (&cell == &kCells[0] && q == 0) dflt = t;
+                if (rc == ENCORE_OK && t < best) {
+                    best = t; best_div = cell[0]; best_xsub = cell[1]; best_nbg = nbgs[q];
+                }
+            }
+        }
+        (void)hipStreamSynchronize(s);
+        grid_free(tg.g);
+        if (rc) break;
+    }
+    (void)hipFree(d_pos);
+    (void)hipFree(d_w);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> tl(ctx->tab_mu);
+        ctx->cell_div = best_div;
+        ctx->cell_xsub = best_xsub;
+        ctx->tuned_nbg[std::make_tuple(lmax, gprec, nbins)] = best_nbg;
+    }
+    if (report) {
+        report[0] = best_div;
+        report[1] = best_xsub;
+        report[2] = best_nbg;
+        report[3] = best;
+        report[4] = dflt;
+    }
+    return ENCORE_OK;
 }
 
 int encore_npcf_simple(const double* pos, const double* w, int64_t n, int npcf, int lmax, int nbins,
@@ -487,7 +602,10 @@ int encore_debug_alm(encore_ctx* ctx, const encore_grid* grid, int lmax, int nbi
     ga.segs = (const GatherSeg*)x.segs.p;
     ga.nseg = 1;
     ga.nrows = (int)nlaunch;
-    if (e == hipSuccess) e = (hipError_t)launch_gather(ga, lmax, prec, false, s);
+    NpcfPlan gpl;
+    gpl.lmax = lmax; gpl.prec = prec; gpl.nbins = nbins;
+    const int nbg = ctx_nbg(ctx, gpl);   // the configuration encore_npcf launches
+    if (e == hipSuccess) e = (hipError_t)launch_gather(ga, lmax, prec, nbg, false, s);
     if (e == hipSuccess) e = (hipError_t)launch_to_double(x.alm.p, prec, nlaunch * per, (double*)x.zeta.p, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     for (int64_t r = 0; r < k && e == hipSuccess; ++r) {

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <vector>
 
 #include "mfma_plan.h"
 
@@ -75,9 +76,12 @@ struct GatherArgs {
     // XCD, contiguous item ranges) and steal from the others when theirs is empty
     unsigned* queues;        // [8] counters, zero at launch
 };
-// precision: 0 = FP64, 1 = FP32.  persistent: grid sized to the resident waves.
-int launch_gather(const GatherArgs& a, int lmax, int precision, bool persistent, hipStream_t stream);
-int gather_group_bins(int lmax, int precision);
+// precision: 0 = FP64, 1 = FP32.  nbg: bins per work item (0 or a value without
+// a compiled variant: the default).  persistent: grid sized to the resident waves.
+int launch_gather(const GatherArgs& a, int lmax, int precision, int nbg, bool persistent, hipStream_t stream);
+int gather_group_bins(int lmax, int precision, int nbg);
+// compiled bins-per-item values for (lmax, precision), the default first
+std::vector<int> gather_nbg_options(int lmax, int precision);
 void gather_tables(int lmax, double* kappa, double* gamma);
 
 // ------------------------------------------------------------------ coupling

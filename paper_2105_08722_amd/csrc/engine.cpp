@@ -389,7 +389,7 @@ int prepare_slice(Exec& x, Buf& segs, Buf& splits, Buf& redp, const NpcfPlan& pl
 int launch_slice_gather(const SliceLaunch& L, const NpcfPlan& pl, hipStream_t s)
 {
     if (L.rows == 0) return ENCORE_OK;
-    HIPTRY((hipError_t)launch_gather(L.ga, pl.lmax, pl.prec == 0 ? 0 : 1, L.persistent, s));
+    HIPTRY((hipError_t)launch_gather(L.ga, pl.lmax, pl.prec == 0 ? 0 : 1, pl.nbg, L.persistent, s));
     return ENCORE_OK;
 }
 
@@ -462,17 +462,18 @@ std::vector<double> bin_scale(const NpcfPlan& pl, const double* edges, double V)
     return sc;
 }
 
-double cell_divisor()
+double cell_divisor(double tuned)
 {
     const char* s = getenv("ENCORE_CELL_DIVISOR");
     if (s) {
         const double v = atof(s);
         if (v >= 1.0 && v <= 32.0) return v;
     }
-    return 6.0;   // cell side r_max / 6: measured best of {4, 6, 8, 10}
+    if (tuned >= 1.0 && tuned <= 32.0) return tuned;
+    return 6.0;   // cell side r_max / 6
 }
 
-double cell_x_subdiv()
+double cell_x_subdiv(double tuned)
 {
     // Cells are split further along x, the axis along which a cell row is one
     // contiguous particle range: this trims the x extent of each row piece to
@@ -482,11 +483,27 @@ double cell_x_subdiv()
         const int v = atoi(s);
         if (v >= 1 && v <= 8) return v;
     }
+    if (tuned >= 1.0 && tuned <= 8.0) return tuned;
     return 4.0;
 }
 
+int ctx_nbg(encore_ctx* ctx, const NpcfPlan& pl)
+{
+    std::lock_guard<std::mutex> lock(ctx->tab_mu);
+    auto it = ctx->tuned_nbg.find(std::make_tuple(pl.lmax, pl.prec == 0 ? 0 : 1, pl.nbins));
+    return it == ctx->tuned_nbg.end() ? 0 : it->second;
+}
+
+void ctx_cells(encore_ctx* ctx, double* div, double* xsub)
+{
+    std::lock_guard<std::mutex> lock(ctx->tab_mu);
+    *div = cell_divisor(ctx->cell_div);
+    *xsub = cell_x_subdiv(ctx->cell_xsub);
+}
+
 int build_grid_dev(int device, const double* d_pos, const double* d_w, int64_t n, int64_t n_data,
-                   bool dmr, const double* box, double r_max, hipStream_t s, DevGrid& out)
+                   bool dmr, const double* box, double r_max, double div, double xsub, hipStream_t s,
+                   DevGrid& out)
 {
     HIPTRY(hipSetDevice(device));
     double bx[3] = {0, 0, 0};
@@ -494,7 +511,7 @@ int build_grid_dev(int device, const double* d_pos, const double* d_w, int64_t n
         for (int a = 0; a < 3; ++a) bx[a] = box[a];
     char err[256] = {0};
     const int rc = grid_build(out, d_pos, d_w, n, n_data, dmr, box != nullptr, bx, r_max,
-                              r_max / cell_divisor(), r_max / (cell_divisor() * cell_x_subdiv()), s,
+                              r_max / div, r_max / (div * xsub), s,
                               err, sizeof(err));
     if (rc != 0) return fail(rc == -1 ? ENCORE_EINVAL : (rc == -3 ? ENCORE_ENOMEM : ENCORE_EDEVICE), err);
     return ENCORE_OK;

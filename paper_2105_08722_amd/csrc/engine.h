@@ -84,6 +84,7 @@ int check_grid_edges(const DevGrid& g, const double* edges, int nbins);
 // Validated call parameters shared by every entry point that computes zeta.
 struct NpcfPlan {
     int N = 0, lmax = 0, nbins = 0, prec = 0;
+    int nbg = 0;   // gather bins per work item (0: the compiled default)
     bool allparity = false;
     int64_t nlam = 0, nB = 0;
 };
@@ -140,16 +141,23 @@ int contract_job(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double*
 std::vector<double> bin_scale(const NpcfPlan& pl, const double* edges, double V);
 
 // Cell grid of a catalog already on the device (pos [n][3], w [n]).
+// cell sides r_max / div (y, z) and r_max / (div * xsub) (x)
 int build_grid_dev(int device, const double* d_pos, const double* d_w, int64_t n, int64_t n_data,
-                   bool dmr, const double* box, double r_max, hipStream_t s, DevGrid& out);
-double cell_divisor();
-double cell_x_subdiv();   // x cell side = yz side / this
+                   bool dmr, const double* box, double r_max, double div, double xsub, hipStream_t s,
+                   DevGrid& out);
+// cell shape: ENCORE_CELL_DIVISOR / ENCORE_CELL_XSUB, else the tuned value (> 0),
+// else the default
+double cell_divisor(double tuned = 0.0);
+double cell_x_subdiv(double tuned = 0.0);   // x cell side = yz side / this
 
 }  // namespace encore
 
 struct encore_ctx {
     int device = 0;
     encore::Exec main;
+    // autotuned launch shapes (encore_autotune); guarded by tab_mu
+    double cell_div = 0.0, cell_xsub = 0.0;               // 0: defaults
+    std::map<std::tuple<int, int, int>, int> tuned_nbg;  // (lmax, gather precision, nbins) -> bins per item
     std::map<std::tuple<int, int, bool, int>, encore::DevTables> tables;
     std::mutex tab_mu;   // tables
     std::mutex mu;       // main exec, timings
@@ -164,6 +172,9 @@ struct encore_grid {
 };
 
 namespace encore {
+// tuned bins per work item for a call (0: default); thread-safe
+int ctx_nbg(encore_ctx* ctx, const NpcfPlan& pl);
+void ctx_cells(encore_ctx* ctx, double* div, double* xsub);
 // thread-safe; the returned tables live as long as the context
 int get_tables(encore_ctx* ctx, int N, int lmax, bool allparity, int nbins, DevTables** out);
 // tables of the call's precision (the MFMA plan too for split-BF16)

@@ -28,6 +28,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <utility>
+#include <vector>
 
 #include "device.h"
 
@@ -609,37 +610,32 @@ KernelCfg cfg2()
     return c;
 }
 
-// Bins per work item for the FP32 lmax = 5 kernel: an autotune knob
-// (ENCORE_GATHER_NBG in {2, 3, 5}).  Fewer bins per item means more passes over
-// the candidates but fewer accumulator registers, hence more resident waves to
-// hide the LDS and L2 latency of the candidate stream; 2 measured best.
-int nbg_override()
+// Bins per work item: fewer bins per item means more passes over the candidates
+// but fewer accumulator registers, hence more resident waves to hide the LDS and
+// L2 latency of the candidate stream.  Several values are compiled for the common
+// cases; encore_autotune picks one per job shape (ENCORE_GATHER_NBG overrides).
+int nbg_env()
 {
     static int v = [] {
         const char* s = getenv("ENCORE_GATHER_NBG");
-        const int x = s ? atoi(s) : 0;
-        return (x == 2 || x == 3 || x == 5) ? x : 0;
+        return s ? atoi(s) : 0;
     }();
     return v;
 }
 
-KernelCfg config(int lmax, int precision)
+// The compiled variant with `nbg` bins per item, or the default (first) one.
+KernelCfg config(int lmax, int precision, int nbg)
 {
-    if (precision == 1 && lmax == 5) {
-        switch (nbg_override()) {
-        case 3: return cfg1<float, 5, 3>();
-        case 5: return cfg1<float, 5, 5>();
-        default: return cfg1<float, 5, 2>();
-        }
-    }
+    if (nbg_env() > 0) nbg = nbg_env();
     if (precision == 1) {
         switch (lmax) {
         case 0: return cfg1<float, 0, 16>();
         case 1: return cfg1<float, 1, 16>();
-        case 2: return cfg1<float, 2, 6>();
-        case 3: return cfg1<float, 3, 4>();
-        case 4: return cfg1<float, 4, 3>();
-        case 6: return cfg1<float, 6, 2>();
+        case 2: return nbg == 10 ? cfg1<float, 2, 10>() : cfg1<float, 2, 6>();
+        case 3: return nbg == 5 ? cfg1<float, 3, 5>() : (nbg == 2 ? cfg1<float, 3, 2>() : cfg1<float, 3, 4>());
+        case 4: return nbg == 5 ? cfg1<float, 4, 5>() : (nbg == 2 ? cfg1<float, 4, 2>() : cfg1<float, 4, 3>());
+        case 5: return nbg == 3 ? cfg1<float, 5, 3>() : (nbg == 5 ? cfg1<float, 5, 5>() : cfg1<float, 5, 2>());
+        case 6: return nbg == 1 ? cfg1<float, 6, 1>() : cfg1<float, 6, 2>();
         case 7: return cfg1<float, 7, 1>();
         case 8: return cfg1<float, 8, 1>();
         case 9: return cfg1<float, 9, 1>();
@@ -650,9 +646,9 @@ KernelCfg config(int lmax, int precision)
         case 0: return cfg1<double, 0, 8>();
         case 1: return cfg1<double, 1, 8>();
         case 2: return cfg1<double, 2, 8>();
-        case 3: return cfg1<double, 3, 5>();
-        case 4: return cfg1<double, 4, 3>();
-        case 5: return cfg1<double, 5, 2>();
+        case 3: return nbg == 2 ? cfg1<double, 3, 2>() : cfg1<double, 3, 5>();
+        case 4: return nbg == 2 ? cfg1<double, 4, 2>() : cfg1<double, 4, 3>();
+        case 5: return nbg == 3 ? cfg1<double, 5, 3>() : cfg1<double, 5, 2>();
         case 6: return cfg1<double, 6, 1>();
         case 7: return cfg1<double, 7, 1>();
         case 8: return cfg1<double, 8, 1>();
@@ -665,7 +661,16 @@ KernelCfg config(int lmax, int precision)
 
 }  // namespace
 
-int gather_group_bins(int lmax, int precision) { return config(lmax, precision).nbg; }
+int gather_group_bins(int lmax, int precision, int nbg) { return config(lmax, precision, nbg).nbg; }
+
+std::vector<int> gather_nbg_options(int lmax, int precision)
+{
+    static const std::vector<int> f32[11] = {{16}, {16}, {6, 10}, {4, 2, 5}, {3, 2, 5}, {2, 3, 5},
+                                             {2, 1}, {1}, {1}, {1}, {1}};
+    static const std::vector<int> f64[11] = {{8}, {8}, {8}, {5, 2}, {3, 2}, {2, 3}, {1}, {1}, {1}, {1}, {1}};
+    if (lmax < 0 || lmax > 10) return {};
+    return precision == 1 ? f32[lmax] : f64[lmax];
+}
 
 void gather_tables(int lmax, double* kappa, double* gamma)
 {
@@ -693,9 +698,9 @@ void gather_tables(int lmax, double* kappa, double* gamma)
     }
 }
 
-int launch_gather(const GatherArgs& a0, int lmax, int precision, bool persistent, hipStream_t stream)
+int launch_gather(const GatherArgs& a0, int lmax, int precision, int nbg, bool persistent, hipStream_t stream)
 {
-    const KernelCfg c = config(lmax, precision);
+    const KernelCfg c = config(lmax, precision, nbg);
     if (!c.fn[0]) return (int)hipErrorInvalidValue;
     GatherArgs a = a0;
     a.group_bins = c.nbg;

@@ -137,6 +137,7 @@ int encore_plan_create(encore_ctx* ctx, encore_grid* grid, int npcf, int lmax, i
     auto* P = new encore_plan();
     P->ctx = ctx;
     int rc = plan_call(npcf, lmax, nbins, edges, flags, &P->pl);
+    if (!rc) P->pl.nbg = ctx_nbg(ctx, P->pl);
     if (!rc) rc = check_grid_edges(grid->g, edges, nbins);
     if (!rc && (flags & ENCORE_NORMALIZE) && !(volume > 0.0) && !grid->g.periodic)
         rc = fail(ENCORE_EINVAL, "ENCORE_NORMALIZE needs volume > 0 without a periodic box");

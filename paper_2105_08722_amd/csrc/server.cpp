@@ -98,8 +98,10 @@ int setup_job(encore_server* S, SrvJob* j, Exec& x)
     if (e == hipSuccess) e = hipMemcpyAsync(d_pos, j->pos.data(), sizeof(double) * 3 * j->n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_w, j->w.data(), sizeof(double) * j->n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
+        double div = 0.0, xsub = 0.0;
+        ctx_cells(S->ctx, &div, &xsub);
         rc = build_grid_dev(S->ctx->device, d_pos, d_w, j->n, j->n_data, (j->flags & ENCORE_DMR) != 0,
-                            j->periodic ? j->box : nullptr, j->edges[j->pl.nbins], s, j->g);
+                            j->periodic ? j->box : nullptr, j->edges[j->pl.nbins], div, xsub, s, j->g);
         j->has_grid = rc == ENCORE_OK;
     }
     if (d_pos) (void)hipFree(d_pos);
@@ -292,6 +294,7 @@ int encore_server_submit(encore_server* S, const double* pos, const double* w, i
     auto j = std::make_unique<SrvJob>();
     int rc;
     if ((rc = plan_call(npcf, lmax, nbins, edges, flags, &j->pl))) return rc;
+    j->pl.nbg = ctx_nbg(S->ctx, j->pl);
     const double r_max = edges[nbins];
     j->periodic = flags & ENCORE_PERIODIC;
     if (j->periodic) {
@@ -306,8 +309,10 @@ int encore_server_submit(encore_server* S, const double* pos, const double* w, i
     }
     if ((flags & ENCORE_DMR) && (n_data < 1 || n_data >= n)) return fail(ENCORE_EINVAL, "ENCORE_DMR needs 1 <= n_data < n");
     // cells of the grid the job will build (an upper bound for open boxes)
-    const double cs_yz = r_max / cell_divisor();
-    const double cs_axis[3] = {cs_yz / cell_x_subdiv(), cs_yz, cs_yz};
+    double div = 0.0, xsub = 0.0;
+    ctx_cells(S->ctx, &div, &xsub);
+    const double cs_yz = r_max / div;
+    const double cs_axis[3] = {cs_yz / xsub, cs_yz, cs_yz};
     int64_t ncell = 1;
     if (j->periodic) {
         for (int a = 0; a < 3; ++a) ncell *= std::max<int64_t>(1, (int64_t)std::floor(box[a] / cs_axis[a]));

@@ -64,6 +64,8 @@ SIGNATURES = {
     "encore_plan_create": (_I, [_P, _P, _I, _I, _I, _P, _U32, _D, ctypes.POINTER(_P)]),
     "encore_plan_execute": (_I, [_P, _P, _SZ]),
     "encore_plan_destroy": (_I, [_P]),
+    "encore_mfma_plan_stats": (_I, [_I, _I, _I, _U32, _P, _SZ]),
+    "encore_autotune": (_I, [_P, _P, _P, _I64, _I64, _P, _I, _I, _I, _P, _U32, _I64, _P, _SZ]),
 }
 
 _lib = None
@@ -261,6 +263,31 @@ def npcf(ctx, grid, N, lmax, edges, precision="fp32", allparity=False, normalize
     _check(lib().encore_npcf(ctx.handle, grid.handle, int(N), int(lmax), nbins, _ptr(edges), flags,
                              float(volume), _ptr(out), out.size, _ptr(prim), nsub, stream))
     return out[:nlam * nB].reshape(nlam, nB)
+
+
+def mfma_plan_stats(N, lmax, nbins, allparity=False):
+    """encore_mfma_plan_stats as a dict."""
+    out = np.zeros(4, dtype=np.int64)
+    _check(lib().encore_mfma_plan_stats(int(N), int(lmax), int(nbins), ALLPARITY if allparity else 0,
+                                        _ptr(out), 4))
+    return {"tiles_per_16": int(out[0]), "row_tiles_per_16": int(out[1]), "t_entries": int(out[2]),
+            "dense_entries": int(out[3])}
+
+
+def autotune(ctx, pos, w, N, lmax, edges, box=None, n_data=None, precision="fp32", n_sample=8192):
+    """encore_autotune: pick the cell shape and gather bins-per-item for jobs like
+    this one; returns the report as a dict."""
+    pos = _f64(pos, (-1, 3))
+    w = _f64(w, (-1,))
+    edges = _f64(edges, (-1,))
+    flags = (PRECISIONS[precision] | (PERIODIC if box is not None else 0) |
+             (DMR if n_data is not None else 0))
+    rep = np.zeros(5)
+    _check(lib().encore_autotune(ctx.handle, _ptr(pos), _ptr(w), len(w), int(n_data or 0), _ptr(_box3(box)),
+                                 int(N), int(lmax), len(edges) - 1, _ptr(edges), flags, int(n_sample),
+                                 _ptr(rep), 5))
+    return {"cell_divisor": rep[0], "x_subdivision": rep[1], "bins_per_item": int(rep[2]),
+            "best_ms": rep[3], "default_ms": rep[4]}
 
 
 class Plan:

@@ -253,6 +253,34 @@ def test_graph_plan_replays_match_eager(ctx, precision):
     assert np.max(np.abs(eager - zo)) <= tol * np.max(np.abs(zo))
 
 
+def test_autotune_then_parity():
+    """encore_autotune on a D-R catalog picks a cell shape and a gather
+    bins-per-item value among the compiled ones; grids built and calls made
+    afterwards on that context (which use them) still match the oracle."""
+    _say("autotune")
+    rng = np.random.default_rng(5)
+    L = 90.0
+    dpos, _ = synth.neyman_scott(2500, L, 19, nbar_parent=2e-4, sigma=2.0)
+    rpos = rng.uniform(0, L, (5000, 3))
+    pos = np.concatenate([dpos, rpos])
+    w_in = np.ones(len(pos))
+    w = oracle.dmr_weights(w_in[:2500], w_in[2500:])
+    edges = np.linspace(4.0, 30.0, 11)
+    with encore.Context(0) as c:
+        for prec in ["fp32", "splitbf16"]:
+            rep = encore.autotune(c, pos, w_in, 4, 5, edges, box=L, n_data=2500, precision=prec,
+                                  n_sample=1000)
+            _say("  %s: %s" % (prec, rep))
+            assert (rep["cell_divisor"], rep["x_subdivision"]) in [(6, 4), (6, 8), (8, 4), (8, 2), (5, 4), (4, 6)]
+            assert rep["bins_per_item"] in (2, 3, 5)
+            assert 0 < rep["best_ms"] <= rep["default_ms"]
+            prim = rng.choice(len(pos), 200, replace=False)
+            with encore.build_grid(c, pos, w_in, r_max=edges[-1], box=L, n_data=2500) as g:
+                zg = encore.npcf(c, g, 4, 5, edges, precision=prec, primaries=prim)
+            zo = oracle.zeta(pos, w, 4, 5, edges, box=L, primaries=prim)
+            assert np.max(np.abs(zg - zo)) <= 5e-5 * np.max(np.abs(zo))
+
+
 # ------------------------------------------------------------------ benchmark workloads
 
 def test_config1_3pcf_full(ctx):
