@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -223,7 +224,7 @@ template <typename T, int L, int NBG, int M0, int M1>
 __host__ __device__ constexpr int gather_wpe()
 {
     constexpr int acc = NBG * ((L + 1) * (L + 1)) * (int)(sizeof(T) / 4);
-    return acc <= 48 ? 4 : (acc <= 90 ? 3 : 2);
+    return acc <= 48 ? 4 : (acc <= 72 ? 3 : 2);
 }
 
 template <typename T, int L, int NBG, int M0, int M1>
@@ -545,33 +546,81 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
     }(std::make_integer_sequence<int, NBG>{});
     wave_sync();
 
-    // ---- 4. reduce over lanes through LDS (FP64, 8 interleaved partial sums) and write
+    // ---- 4. reduce the 64 lanes' accumulators and write
     constexpr int NV = NBG * NLM * 2;
     T* accf = &acc[0][0][0];
     const int nvalid = (b_hi - b_lo) * NLM * 2;
     T* out = reinterpret_cast<T*>(a.alm) + ((size_t)row * a.nbins + b_lo) * NLM * 2;
     if (grp == 0 && lane == 0) a.wprim[row] = Pi.w;
+    if constexpr (std::is_same_v<T, float>) {
+        // Reduce-scatter across lanes, two values per step: a 32-lane swap packs
+        // values 2p and 2p+1 into one register (lanes 0-31 and 32-63) summed over
+        // lanes i, i+32; a 16-row swap packs four values (one per row of 16 lanes)
+        // summed over 4 lanes; four rotate-adds inside each row finish the sums.
+        // Row r of c[q] then holds value 4q + {0, 2, 1, 3}[r].
+        constexpr int NV4 = (NV + 3) / 4 * 4;
+        unsigned v[NV4];
 #pragma unroll
-    for (int v0 = 0; v0 < NV; v0 += CH) {
+        for (int q = 0; q < NV4; ++q) v[q] = q < NV ? __float_as_uint(accf[q]) : 0u;
+        unsigned b[NV4 / 2];
 #pragma unroll
-        for (int c = 0; c < CH; ++c)
-            if (v0 + c < NV) scratch[c * 65 + lane] = accf[v0 + c];
+        for (int p2 = 0; p2 < NV4 / 2; ++p2) {
+            const auto r = __builtin_amdgcn_permlane32_swap(v[2 * p2], v[2 * p2 + 1], false, false);
+            b[p2] = __float_as_uint(__uint_as_float(r[0]) + __uint_as_float(r[1]));
+        }
+        float c[NV4 / 4];
+#pragma unroll
+        for (int q = 0; q < NV4 / 4; ++q) {
+            const auto r = __builtin_amdgcn_permlane16_swap(b[2 * q], b[2 * q + 1], false, false);
+            float x = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+            x += __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(x), 0x128, 0xf, 0xf, false));
+            x += __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(x), 0x124, 0xf, 0xf, false));
+            x += __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(x), 0x122, 0xf, 0xf, false));
+            x += __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(x), 0x121, 0xf, 0xf, false));
+            c[q] = x;
+        }
+        // the recurrence scales through LDS (the rings are idle now)
+        double* kap = reinterpret_cast<double*>(scratch);
+        for (int q = lane; q < NLM; q += kWave) kap[q] = a.kappa[q];
         wave_sync();
-        const int v = v0 + lane;
-        if (lane < CH && v < nvalid) {
-            const int lm = (v >> 1) % NLM;
-            const int m = m_of_lm(lm);
-            if (m >= M0 && m <= M1) {
-                double s8[8];
+        const int rrow = lane >> 4;
+        const int sub = (rrow == 1) ? 2 : (rrow == 2 ? 1 : rrow);
+        if ((lane & 15) == 0) {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) s8[u] = 0.0;
-#pragma unroll
-                for (int l2 = 0; l2 < kWave; ++l2) s8[l2 & 7] += (double)scratch[lane * 65 + l2];
-                const double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
-                out[v] = (T)(s * a.kappa[lm]);
+            for (int q = 0; q < NV4 / 4; ++q) {
+                const int vi = 4 * q + sub;
+                if (vi < nvalid) {
+                    const int lm = (vi >> 1) % NLM;
+                    const int m = m_of_lm(lm);
+                    if (m >= M0 && m <= M1) out[vi] = (T)((double)c[q] * kap[lm]);
+                }
             }
         }
         wave_sync();
+    } else {
+        // FP64 accumulators: through LDS, 8 interleaved FP64 partial sums per value
+#pragma unroll
+        for (int v0 = 0; v0 < NV; v0 += CH) {
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                if (v0 + c < NV) scratch[c * 65 + lane] = accf[v0 + c];
+            wave_sync();
+            const int v = v0 + lane;
+            if (lane < CH && v < nvalid) {
+                const int lm = (v >> 1) % NLM;
+                const int m = m_of_lm(lm);
+                if (m >= M0 && m <= M1) {
+                    double s8[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) s8[u] = 0.0;
+#pragma unroll
+                    for (int l2 = 0; l2 < kWave; ++l2) s8[l2 & 7] += (double)scratch[lane * 65 + l2];
+                    const double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+                    out[v] = (T)(s * a.kappa[lm]);
+                }
+            }
+            wave_sync();
+        }
     }
     wave_sync();
     item = a.queues ? pop() : -1;
@@ -634,7 +683,7 @@ KernelCfg config(int lmax, int precision, int nbg)
         case 2: return nbg == 10 ? cfg1<float, 2, 10>() : cfg1<float, 2, 6>();
         case 3: return nbg == 5 ? cfg1<float, 3, 5>() : (nbg == 2 ? cfg1<float, 3, 2>() : cfg1<float, 3, 4>());
         case 4: return nbg == 5 ? cfg1<float, 4, 5>() : (nbg == 2 ? cfg1<float, 4, 2>() : cfg1<float, 4, 3>());
-        case 5: return nbg == 3 ? cfg1<float, 5, 3>() : (nbg == 5 ? cfg1<float, 5, 5>() : cfg1<float, 5, 2>());
+        case 5: return nbg == 3 ? cfg1<float, 5, 3>() : cfg1<float, 5, 2>();
         case 6: return nbg == 1 ? cfg1<float, 6, 1>() : cfg1<float, 6, 2>();
         case 7: return cfg1<float, 7, 1>();
         case 8: return cfg1<float, 8, 1>();
@@ -648,7 +697,7 @@ KernelCfg config(int lmax, int precision, int nbg)
         case 2: return cfg1<double, 2, 8>();
         case 3: return nbg == 2 ? cfg1<double, 3, 2>() : cfg1<double, 3, 5>();
         case 4: return nbg == 2 ? cfg1<double, 4, 2>() : cfg1<double, 4, 3>();
-        case 5: return nbg == 3 ? cfg1<double, 5, 3>() : cfg1<double, 5, 2>();
+        case 5: return cfg1<double, 5, 2>();
         case 6: return cfg1<double, 6, 1>();
         case 7: return cfg1<double, 7, 1>();
         case 8: return cfg1<double, 8, 1>();
@@ -665,9 +714,9 @@ int gather_group_bins(int lmax, int precision, int nbg) { return config(lmax, pr
 
 std::vector<int> gather_nbg_options(int lmax, int precision)
 {
-    static const std::vector<int> f32[11] = {{16}, {16}, {6, 10}, {4, 2, 5}, {3, 2, 5}, {2, 3, 5},
+    static const std::vector<int> f32[11] = {{16}, {16}, {6, 10}, {4, 2, 5}, {3, 2, 5}, {2, 3},
                                              {2, 1}, {1}, {1}, {1}, {1}};
-    static const std::vector<int> f64[11] = {{8}, {8}, {8}, {5, 2}, {3, 2}, {2, 3}, {1}, {1}, {1}, {1}, {1}};
+    static const std::vector<int> f64[11] = {{8}, {8}, {8}, {5, 2}, {3, 2}, {2}, {1}, {1}, {1}, {1}, {1}};
     if (lmax < 0 || lmax > 10) return {};
     return precision == 1 ? f32[lmax] : f64[lmax];
 }

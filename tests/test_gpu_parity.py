@@ -272,7 +272,7 @@ def test_autotune_then_parity():
                                   n_sample=1000)
             _say("  %s: %s" % (prec, rep))
             assert (rep["cell_divisor"], rep["x_subdivision"]) in [(6, 4), (6, 8), (8, 4), (8, 2), (5, 4), (4, 6)]
-            assert rep["bins_per_item"] in (2, 3, 5)
+            assert rep["bins_per_item"] in (2, 3)
             assert 0 < rep["best_ms"] <= rep["default_ms"]
             prim = rng.choice(len(pos), 200, replace=False)
             with encore.build_grid(c, pos, w_in, r_max=edges[-1], box=L, n_data=2500) as g:
