@@ -334,7 +334,7 @@ int prepare_slice(Exec& x, Buf& segs, Buf& splits, Buf& redp, const NpcfPlan& pl
     HIPTRY(hipMemcpyAsync(splits.p, hsplit.data(), sizeof(int32_t) * hsplit.size(), hipMemcpyHostToDevice, s));
     HIPTRY(hipMemcpyAsync(redp.p, rdst.data(), sizeof(double*) * rdst.size(), hipMemcpyHostToDevice, s));
     const int32_t* dsp = (const int32_t*)splits.p;
-    L.persistent = hsegs.size() > 1;
+    L.persistent = hsegs.size() > 1 || getenv("ENCORE_GATHER_PERSISTENT") != nullptr;
 
     GatherArgs& ga = L.ga;
     memset(&ga, 0, sizeof(ga));

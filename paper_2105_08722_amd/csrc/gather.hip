@@ -219,6 +219,109 @@ constexpr int kStartMask = (1 << kCodeShift) - 1;
 constexpr int kCenterCode = 1 | (1 << 2) | (1 << 4);   // no periodic image on any axis
 constexpr int kMapCap = 2 * kSegCap;         // candidate entries per window (the slot area)
 
+// Uniform inputs of the row set-up in precision R: primary position relative to
+// the grid origin, cell sizes and their reciprocals, the culling sphere radius and
+// inner-hole radius (widened / shrunk by the margin eps), the row range.
+template <typename R>
+struct RowFrame {
+    R px, py, pz, csx, csy, csz, icsx, eps, Rc2, R2in;
+    int ky0, kz0, nyr;
+    float inv_nyr;
+};
+
+template <typename R>
+__device__ __forceinline__ RowFrame<R> make_frame(const GatherSeg& g, double xi, double yi, double zi,
+                                                 double R2in, double R2out, int ky0, int kz0, int nyr,
+                                                 double margin)
+{
+    RowFrame<R> f;
+    const double eps = margin * fmin(g.csx, fmin(g.csy, g.csz));
+    f.px = (R)(xi - g.ox); f.py = (R)(yi - g.oy); f.pz = (R)(zi - g.oz);
+    f.csx = (R)g.csx; f.csy = (R)g.csy; f.csz = (R)g.csz;
+    f.icsx = (R)(1.0 / g.csx);
+    f.eps = (R)eps;
+    const double rc = sqrt(R2out) + eps;
+    f.Rc2 = (R)(rc * rc);
+    const double rin = fmax(0.0, sqrt(R2in) - eps);
+    f.R2in = (R)(rin * rin);
+    f.ky0 = ky0; f.kz0 = kz0; f.nyr = nyr;
+    f.inv_nyr = 1.0f / (float)max(nyr, 1);
+    return f;
+}
+
+// One cell row (lane's row r of the primary's row range): clip its x extent to the
+// culling sphere's chord, minus the inner hole where the whole row is inside it,
+// split at periodic images, and write its non-empty pieces (start | image code,
+// length) to the lane's slots.  Row, cell and image indices stay within one period
+// of the grid because the largest separation is at most half the box.
+template <typename R>
+__device__ __forceinline__ void setup_row(const RowFrame<R>& f, const GatherSeg& g, gptr<int32_t> gcs, int r,
+                                          int lane, int* slot_stc, int* slot_len, int& ns, int& nlen)
+{
+    // r / nyr: the float product is exact below 2^22 rows
+    const int rz = r < (1 << 22) ? (int)(((float)r + 0.5f) * f.inv_nyr) : r / f.nyr;
+    const int ky = f.ky0 + (r - rz * f.nyr), kz = f.kz0 + rz;
+    int wy = ky, wz = kz, sy = 0, sz = 0;
+    if (g.periodic) {
+        sy = ky < 0 ? -1 : (ky >= g.ncy ? 1 : 0);
+        sz = kz < 0 ? -1 : (kz >= g.ncz ? 1 : 0);
+        wy = ky - sy * g.ncy;
+        wz = kz - sz * g.ncz;
+    }
+    const R ylo = (R)ky * f.csy - f.eps, yhi = (R)(ky + 1) * f.csy + f.eps;
+    const R zlo = (R)kz * f.csz - f.eps, zhi = (R)(kz + 1) * f.csz + f.eps;
+    const R dymin = fmax((R)0, fmax(ylo - f.py, f.py - yhi));
+    const R dzmin = fmax((R)0, fmax(zlo - f.pz, f.pz - zhi));
+    const R rho2 = dymin * dymin + dzmin * dzmin;
+    if (!(rho2 < f.Rc2)) return;
+    const R h = sqrt(f.Rc2 - rho2) + f.eps;
+    int kx0 = (int)floor((f.px - h) * f.icsx), kx1 = (int)floor((f.px + h) * f.icsx);
+    if (!g.periodic) { kx0 = max(kx0, 0); kx1 = min(kx1, g.ncx - 1); }
+    const R dymax = fmax(fabs(ylo - f.py), fabs(yhi - f.py));
+    const R dzmax = fmax(fabs(zlo - f.pz), fabs(zhi - f.pz));
+    const R rhomax2 = dymax * dymax + dzmax * dzmax;
+    int kin0 = 1, kin1 = 0;
+    if (f.R2in > (R)0 && rhomax2 < f.R2in) {
+        const R hin = sqrt(f.R2in - rhomax2) - f.eps;
+        if (hin > (R)0) {
+            kin0 = (int)ceil((f.px - hin) * f.icsx);
+            kin1 = (int)floor((f.px + hin) * f.icsx) - 1;
+        }
+    }
+    const int rowbase = (wz * g.ncy + wy) * g.ncx;
+    const int code_yz = ((sy + 1) << 2) | ((sz + 1) << 4);
+    // at most two x ranges: left of and right of the inner hole
+    for (int q = 0; q < 2; ++q) {
+        int lo, hi;
+        if (kin0 <= kin1) {
+            lo = (q == 0) ? kx0 : max(kx0, kin1 + 1);
+            hi = (q == 0) ? min(kx1, kin0 - 1) : kx1;
+        } else {
+            if (q == 1) break;
+            lo = kx0; hi = kx1;
+        }
+        if (lo > hi) continue;
+        int sxa = 0, sxb = 0;
+        if (g.periodic) {
+            sxa = lo < 0 ? -1 : (lo >= g.ncx ? 1 : 0);
+            sxb = hi < 0 ? -1 : (hi >= g.ncx ? 1 : 0);
+        }
+        for (int sx = sxa; sx <= sxb && ns < kSegPerRow; ++sx) {
+            const int plo = max(lo, sx * g.ncx) - sx * g.ncx;
+            const int phi = min(hi, sx * g.ncx + g.ncx - 1) - sx * g.ncx;
+            const int st = gcs[rowbase + plo];
+            const int en = gcs[rowbase + phi + 1];
+            if (en > st) {
+                const int slot = lane * kSegPerRow + ns;
+                slot_stc[slot] = st | (((sx + 1) | code_yz) << kCodeShift);
+                slot_len[slot] = en - st;
+                nlen += en - st;
+                ++ns;
+            }
+        }
+    }
+}
+
 // waves per SIMD the kernel is compiled for, from its accumulator registers
 template <typename T, int L, int NBG, int M0, int M1>
 __host__ __device__ constexpr int gather_wpe()
@@ -299,10 +402,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
     // periodic images: shift per axis for image codes 0, 1, 2 (-L, 0, +L)
     const double Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
     // culling uses slightly enlarged cells and radius; the bin test below is exact
-    const double eps = 1e-7 * fmin(g.csx, fmin(g.csy, g.csz));
-    const double Rc = sqrt(R2out) + eps;
-    const double Rc2 = Rc * Rc;
-    const double Rin = sqrt(R2in);
+    const double Rc = sqrt(R2out) + 1e-7 * fmin(g.csx, fmin(g.csy, g.csz));
 
     int head[NBG], tail[NBG];
 #pragma unroll
@@ -322,75 +422,20 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
     }
     const int nyr = ky1 - ky0 + 1, nzr = kz1 - kz0 + 1;
     const int nrows = (nyr > 0 && nzr > 0) ? nyr * nzr : 0;
+    // Row set-up frame.  Rows only cull candidates (every candidate is binned
+    // exactly in FP64 below), so the set-up runs in FP32 with a margin, in cell
+    // units, far above the FP32 rounding of coordinates relative to the grid origin
+    // (about n * 2^-23 cells for a grid n cells long).
+    const int nmax = max(g.ncx, max(g.ncy, g.ncz));
+    const RowFrame<float> rf = make_frame<float>(g, xi, yi, zi, R2in, R2out, ky0, kz0, nyr,
+                                                 fmax(1e-3, 1e-6 * (double)nmax));
 
     for (int rb = 0; rb < nrows; rb += kRowsPerBatch) {
         // ---- 1. lane-parallel row set-up: lane r writes its <= kSegPerRow pieces to
         //         slots [lane * kSegPerRow, ...)
         int ns = 0, nlen = 0;
-        {
-            const int r = rb + lane;
-            if (r < nrows) {
-                const int ky = ky0 + r % nyr, kz = kz0 + r / nyr;
-                int wy = ky, wz = kz, sy = 0, sz = 0;
-                if (g.periodic) {
-                    wy = ((ky % g.ncy) + g.ncy) % g.ncy; sy = (ky - wy) / g.ncy;
-                    wz = ((kz % g.ncz) + g.ncz) % g.ncz; sz = (kz - wz) / g.ncz;
-                }
-                const double ylo = g.oy + ky * g.csy - eps, yhi = g.oy + (ky + 1) * g.csy + eps;
-                const double zlo = g.oz + kz * g.csz - eps, zhi = g.oz + (kz + 1) * g.csz + eps;
-                const double dymin = fmax(0.0, fmax(ylo - yi, yi - yhi));
-                const double dzmin = fmax(0.0, fmax(zlo - zi, zi - zhi));
-                const double rho2 = dymin * dymin + dzmin * dzmin;
-                if (rho2 < Rc2) {
-                    const double h = sqrt(Rc2 - rho2) + eps;
-                    int kx0 = (int)floor((xi - h - g.ox) / g.csx), kx1 = (int)floor((xi + h - g.ox) / g.csx);
-                    if (!g.periodic) { kx0 = max(kx0, 0); kx1 = min(kx1, g.ncx - 1); }
-                    const double dymax = fmax(fabs(ylo - yi), fabs(yhi - yi));
-                    const double dzmax = fmax(fabs(zlo - zi), fabs(zhi - zi));
-                    const double rhomax2 = dymax * dymax + dzmax * dzmax;
-                    int kin0 = 1, kin1 = 0;
-                    if (Rin > 0.0 && rhomax2 < R2in) {
-                        const double hin = sqrt(R2in - rhomax2) - eps;
-                        if (hin > 0.0) {
-                            kin0 = (int)ceil((xi - hin - g.ox) / g.csx);
-                            kin1 = (int)floor((xi + hin - g.ox) / g.csx) - 1;
-                        }
-                    }
-                    const int rowbase = (wz * g.ncy + wy) * g.ncx;
-                    const int code_yz = ((sy + 1) << 2) | ((sz + 1) << 4);
-                    // at most two x ranges: left of and right of the inner hole
-                    for (int q = 0; q < 2; ++q) {
-                        int lo, hi;
-                        if (kin0 <= kin1) {
-                            lo = (q == 0) ? kx0 : max(kx0, kin1 + 1);
-                            hi = (q == 0) ? min(kx1, kin0 - 1) : kx1;
-                        } else {
-                            if (q == 1) break;
-                            lo = kx0; hi = kx1;
-                        }
-                        if (lo > hi) continue;
-                        int sxa = 0, sxb = 0;
-                        if (g.periodic) {
-                            sxa = (lo >= 0) ? lo / g.ncx : -((-lo + g.ncx - 1) / g.ncx);
-                            sxb = (hi >= 0) ? hi / g.ncx : -((-hi + g.ncx - 1) / g.ncx);
-                        }
-                        for (int sx = sxa; sx <= sxb && ns < kSegPerRow; ++sx) {
-                            const int plo = max(lo, sx * g.ncx) - sx * g.ncx;
-                            const int phi = min(hi, sx * g.ncx + g.ncx - 1) - sx * g.ncx;
-                            const int st = gcs[rowbase + plo];
-                            const int en = gcs[rowbase + phi + 1];
-                            if (en > st) {
-                                const int slot = lane * kSegPerRow + ns;
-                                slot_stc[slot] = st | (((sx + 1) | code_yz) << kCodeShift);
-                                slot_len[slot] = en - st;
-                                nlen += en - st;
-                                ++ns;
-                            }
-                        }
-                    }
-                }
-            }
-        }
+        const int r = rb + lane;
+        if (r < nrows) setup_row<float>(rf, g, gcs, r, lane, slot_stc, slot_len, ns, nlen);
         // compact the segments in (lane, piece) order with their flat offsets
         int nseg = 0, total = 0;
         const int sbase = wave_excl_scan(ns, lane, &nseg);
@@ -413,6 +458,10 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         unsigned* map = reinterpret_cast<unsigned*>(slot_stc);
         const unsigned self_entry = (unsigned)ip | ((unsigned)kCenterCode << kCodeShift);
         int s_lo = 0;
+        // segment descriptors, 64 at a time: lane l holds segment gbase + l, read
+        // back with readlane (no LDS round trip per segment)
+        int gbase = -kWave, fs_v = 0, fe_v = 0;
+        unsigned stc_v = 0;
         for (int w0 = 0; w0 < total; w0 += kMapCap) {
             const int w1 = min(total, w0 + kMapCap);
             const int wn = w1 - w0;
@@ -420,10 +469,18 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
             wave_sync();                       // previous window's entries are consumed
             int sg = s_lo;
             while (sg < nseg) {
-                const int f_s = uni(seg_flat[sg]);
+                if (sg >= gbase + kWave) {
+                    gbase = sg;
+                    const int sl = gbase + lane;
+                    stc_v = sl < nseg ? (unsigned)seg_stc[sl] : 0u;
+                    fs_v = sl < nseg ? seg_flat[sl] : total;
+                    fe_v = sl < nseg ? seg_flat[sl + 1] : total;
+                }
+                const int i = sg - gbase;
+                const int f_s = __builtin_amdgcn_readlane(fs_v, i);
                 if (f_s >= w1) break;
-                const int f_e = uni(seg_flat[sg + 1]);
-                const unsigned stc = (unsigned)uni(seg_stc[sg]);
+                const int f_e = __builtin_amdgcn_readlane(fe_v, i);
+                const unsigned stc = (unsigned)__builtin_amdgcn_readlane((int)stc_v, i);
                 const int a1 = min(f_e, w1);
                 for (int f = max(f_s, w0) + lane; f < a1; f += kWave) map[f - w0] = stc + (unsigned)(f - f_s);
                 if (f_e > w1) break;           // continues into the next window
