@@ -41,7 +41,10 @@ constexpr int kCap = 128;          // ring capacity per bin (pairs)
 constexpr int kRowsPerBatch = 64;  // rows set up per lane-parallel pass
 constexpr int kSegPerRow = 6;      // <= 2 x-ranges x 3 periodic images
 constexpr int kSegCap = kRowsPerBatch * kSegPerRow;
-constexpr int kWavesPerBlock = 1;  // waves are independent; no block barriers
+// Waves of a block are independent (no block barriers); they take the same bin
+// group of kWavesPerBlock consecutive rows, so nearly the same candidate stream
+// runs on one compute unit and its vector L1 serves the repeats.
+constexpr int kWavesPerBlock = 4;
 constexpr int kRedCh = 16;         // accumulator values per pass of the lane reduction
 
 __host__ __device__ constexpr int nlm_of(int L) { return (L + 1) * (L + 2) / 2; }
@@ -73,7 +76,7 @@ __host__ __device__ constexpr int ring_bytes()
 template <typename T, int NBG>
 __host__ __device__ constexpr int wave_lds_bytes()
 {
-    // ring | slot_stc[kSegCap] slot_len[kSegCap] | seg_stc[kSegCap] seg_flat[kSegCap + 1]
+    // ring | slot_stc[kSegCap] slot_len[kSegCap] | seg_dl[kSegCap] seg_flat[kSegCap + 1]
     return ring_bytes<T, NBG>() + 4 * (4 * kSegCap + 4);
 }
 
@@ -217,7 +220,6 @@ __device__ __forceinline__ int wave_excl_scan(int v, int lane, int* total)
 constexpr int kCodeShift = 26;               // segment start | (image code << 26)
 constexpr int kStartMask = (1 << kCodeShift) - 1;
 constexpr int kCenterCode = 1 | (1 << 2) | (1 << 4);   // no periodic image on any axis
-constexpr int kMapCap = 2 * kSegCap;         // candidate entries per window (the slot area)
 
 // Uniform inputs of the row set-up in precision R: primary position relative to
 // the grid origin, cell sizes and their reciprocals, the culling sphere radius and
@@ -345,18 +347,22 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
     T* scratch = reinterpret_cast<T*>(base);
     int* slot_stc = reinterpret_cast<int*>(base + ring_bytes<T, NBG>());
     int* slot_len = slot_stc + kSegCap;
-    int* seg_stc = slot_len + kSegCap;
-    int* seg_flat = seg_stc + kSegCap;
+    unsigned* seg_dl = reinterpret_cast<unsigned*>(slot_len + kSegCap);
+    int* seg_flat = reinterpret_cast<int*>(seg_dl + kSegCap);
 
     // recurrence coefficients -> registers (uniform)
     T gam[NLM];
 #pragma unroll
     for (int q = 0; q < NLM; ++q) gam[q] = (T)a.gamma[q];
 
-    const int64_t nitems = (int64_t)a.nrows * a.ngroups;
-    // Item order: a static grid gives each XCD (block b runs on XCD b % 8) a
-    // contiguous run of items, so neighbouring primaries (same cells) share that
-    // XCD's L2; the persistent grid pulls items from 8 contiguous queues the same way.
+    // Item j -> quad j / kWavesPerBlock = (row block, bin group), row = block *
+    // kWavesPerBlock + j % kWavesPerBlock.  Rows are cell-sorted primaries, so the
+    // waves of one quad scan almost the same cells.  A static grid gives each XCD
+    // (block b runs on XCD b % 8) a contiguous run of quads, so neighbouring
+    // primaries share that XCD's L2; the persistent grid pulls items from 8
+    // contiguous queues the same way.
+    const int64_t nquads = ((int64_t)a.nrows + kWavesPerBlock - 1) / kWavesPerBlock * a.ngroups;
+    const int64_t nitems = nquads * kWavesPerBlock;
     const int home = blockIdx.x & 7;
     auto pop = [&]() -> int64_t {
         for (int t = 0; t < 8; ++t) {
@@ -378,8 +384,14 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         item = (int64_t)bid * kWavesPerBlock + wib;
     }
     while (item >= 0 && item < nitems) {
-    const int row = uni((int)(item / a.ngroups));
-    const int grp = uni((int)(item - (int64_t)row * a.ngroups));
+    const int64_t quad = item / kWavesPerBlock;
+    const int64_t rblk = quad / a.ngroups;
+    const int grp = uni((int)(quad - rblk * a.ngroups));
+    const int row = uni((int)(rblk * kWavesPerBlock + (item - quad * kWavesPerBlock)));
+    if (row >= a.nrows) {   // ragged last row block
+        item = a.queues ? pop() : -1;
+        continue;
+    }
     // segment (catalog) of this row: binary search over the segments' first rows
     int slo = 0, shi = a.nseg - 1;
     while (slo < shi) {
@@ -436,60 +448,79 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         int ns = 0, nlen = 0;
         const int r = rb + lane;
         if (r < nrows) setup_row<float>(rf, g, gcs, r, lane, slot_stc, slot_len, ns, nlen);
-        // compact the segments in (lane, piece) order with their flat offsets
+        // compact the pieces in (lane, piece) order: flat position of the first
+        // candidate, and entry minus flat position (so a candidate's entry is its
+        // flat position plus its piece's delta; start + length < 2^26 never carries
+        // into the image code)
         int nseg = 0, total = 0;
         const int sbase = wave_excl_scan(ns, lane, &nseg);
         int fbase = wave_excl_scan(nlen, lane, &total);
         wave_sync();
         for (int q = 0; q < ns; ++q) {
-            seg_stc[sbase + q] = slot_stc[lane * kSegPerRow + q];
+            seg_dl[sbase + q] = (unsigned)slot_stc[lane * kSegPerRow + q] - (unsigned)fbase;
             seg_flat[sbase + q] = fbase;
             fbase += slot_len[lane * kSegPerRow + q];
         }
-        if (lane == 0) seg_flat[nseg] = total;
         wave_sync();
 
-        // ---- 2./3. candidates in windows of kMapCap: the window's (particle index |
-        //      image code) entries are written to LDS once (reusing the slot area),
-        //      padded to whole chunks with the primary itself (r = 0 < R_in, always
-        //      rejected); each 64-candidate chunk then reads one entry per lane.
-        //      The entry read and the global load of chunk c+1 are issued before
-        //      chunk c is processed.
-        unsigned* map = reinterpret_cast<unsigned*>(slot_stc);
+        // ---- 2./3. candidates, 64 per chunk: lane l of the chunk at flat position p0
+        //      takes candidate p0 + l, whose entry (particle index | image code) is
+        //      p0 + l plus the delta of the last piece starting at or before it.
+        //      Positions past the batch take the primary itself (r = 0 < R_in, always
+        //      rejected).  Piece descriptors are held 64 at a time in VGPRs (lane l:
+        //      piece gbase + l) and read with readlane.
         const unsigned self_entry = (unsigned)ip | ((unsigned)kCenterCode << kCodeShift);
-        int s_lo = 0;
-        // segment descriptors, 64 at a time: lane l holds segment gbase + l, read
-        // back with readlane (no LDS round trip per segment)
-        int gbase = -kWave, fs_v = 0, fe_v = 0;
-        unsigned stc_v = 0;
-        for (int w0 = 0; w0 < total; w0 += kMapCap) {
-            const int w1 = min(total, w0 + kMapCap);
-            const int wn = w1 - w0;
-            const int wpad = (wn + kWave - 1) & ~(kWave - 1);
-            wave_sync();                       // previous window's entries are consumed
-            int sg = s_lo;
-            while (sg < nseg) {
-                if (sg >= gbase + kWave) {
-                    gbase = sg;
-                    const int sl = gbase + lane;
-                    stc_v = sl < nseg ? (unsigned)seg_stc[sl] : 0u;
-                    fs_v = sl < nseg ? seg_flat[sl] : total;
-                    fe_v = sl < nseg ? seg_flat[sl + 1] : total;
-                }
-                const int i = sg - gbase;
-                const int f_s = __builtin_amdgcn_readlane(fs_v, i);
-                if (f_s >= w1) break;
-                const int f_e = __builtin_amdgcn_readlane(fe_v, i);
-                const unsigned stc = (unsigned)__builtin_amdgcn_readlane((int)stc_v, i);
-                const int a1 = min(f_e, w1);
-                for (int f = max(f_s, w0) + lane; f < a1; f += kWave) map[f - w0] = stc + (unsigned)(f - f_s);
-                if (f_e > w1) break;           // continues into the next window
+        int gbase = 0;
+        unsigned dl_v = 0;
+        int fs_v = 0;
+        auto reload = [&](int base) {
+            gbase = base;
+            const int sl = base + lane;
+            dl_v = sl < nseg ? seg_dl[sl] : 0u;
+            fs_v = sl < nseg ? seg_flat[sl] : INT_MAX;
+        };
+        // descriptor of piece t (uniform); past the last piece: start INT_MAX
+        auto desc = [&](int t, unsigned& dl, int& fs) {
+            if (t >= nseg) { dl = 0u; fs = INT_MAX; return; }
+            if (t < gbase || t >= gbase + kWave) reload(t);
+            dl = (unsigned)__builtin_amdgcn_readlane((int)dl_v, t - gbase);
+            fs = __builtin_amdgcn_readlane(fs_v, t - gbase);
+        };
+        reload(0);
+        // walk state: piece sg holds the next chunk's first position; (dnext, fnext)
+        // describe piece sg + 1
+        int sg = 0;
+        unsigned dcur = 0u, dnext = 0u;
+        int fnext = INT_MAX;
+        if (nseg > 0) {
+            int f0;
+            desc(0, dcur, f0);
+            desc(1, dnext, fnext);
+        }
+        // entries of the chunk at p0 (uniform, increasing from call to call)
+        auto fetch = [&](int p0) -> unsigned {
+            if (p0 >= total) return self_entry;
+            while (fnext <= p0) {
                 ++sg;
+                dcur = dnext;
+                desc(sg + 1, dnext, fnext);
             }
-            s_lo = sg;
-            for (int f = wn + lane; f < wpad; f += kWave) map[f] = self_entry;
-            wave_sync();
-
+            const unsigned pl = (unsigned)(p0 + lane);
+            unsigned me = pl + dcur;
+            if (fnext < p0 + kWave) {
+                // pieces starting inside the chunk; the walk ends on the last of
+                // them, which holds the next chunk's first position
+                do {
+                    if (lane >= fnext - p0) me = pl + dnext;
+                    ++sg;
+                    dcur = dnext;
+                    desc(sg + 1, dnext, fnext);
+                } while (fnext < p0 + kWave);
+            }
+            if (p0 + kWave > total && (int)pl >= total) me = self_entry;
+            return me;
+        };
+        {
             // one chunk of 64 candidates: exact FP64 bin, ring push, drains
             auto chunk = [&](const unsigned me, const double4& q) {
                 // x_j - x_i, then the periodic image (+/- L; chunks without images
@@ -502,24 +533,29 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
                     dz = sep(dz, 0.0, (double)(((code >> 4) & 3) - 1) * Lz);
                 }
                 const double r2 = dist2(dx, dy, dz);
-                const bool ok = (r2 >= R2in) && (r2 < R2out);
+                bool ok;
                 int k = 0;
                 int slot;
                 if constexpr (NBG == 2) {
-                    // bins of the pair: k = 1 past the interior edge; rank among the
-                    // lanes of the same bin from one ballot per bin
-                    const bool k1 = r2 >= e2k[1];
-                    k = k1 ? 1 : 0;
-                    const unsigned long long m1 = __builtin_amdgcn_ballot_w64(ok && k1);
-                    const unsigned long long m0 = __builtin_amdgcn_ballot_w64(ok && !k1);
-                    const int r0 = tail[0] + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m0 >> 32),
-                                                                           __builtin_amdgcn_mbcnt_lo((unsigned)m0, 0u));
-                    const int r1 = tail[1] + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m1 >> 32),
-                                                                           __builtin_amdgcn_mbcnt_lo((unsigned)m1, 0u));
-                    slot = k1 ? (kCap + (r1 & (kCap - 1))) : (r0 & (kCap - 1));
+                    // three compares give the lane masks: inside the shell, and past
+                    // the interior edge (bin 1); each bin's lanes are ranked by one
+                    // mbcnt of that bin's mask, offset by the bin's tail
+                    const bool c_in = r2 >= R2in, c_out = r2 < R2out, c_k = r2 >= e2k[1];
+                    ok = c_in && c_out;
+                    const unsigned long long okm = __builtin_amdgcn_ballot_w64(ok);
+                    const unsigned long long km = __builtin_amdgcn_ballot_w64(c_k);
+                    const unsigned long long m1 = okm & km, m0 = okm & ~km;
+                    const unsigned r0 = __builtin_amdgcn_mbcnt_hi((unsigned)(m0 >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((unsigned)m0, 0u)) +
+                                        (unsigned)tail[0];
+                    const unsigned r1 = __builtin_amdgcn_mbcnt_hi((unsigned)(m1 >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((unsigned)m1, 0u)) +
+                                        (unsigned)tail[1];
+                    slot = (int)(c_k ? ((r1 & (kCap - 1)) | (unsigned)kCap) : (r0 & (kCap - 1)));
                     tail[0] += __popcll(m0);
                     tail[1] += __popcll(m1);
                 } else {
+                    ok = (r2 >= R2in) && (r2 < R2out);
 #pragma unroll
                     for (int q2 = 1; q2 < NBG; ++q2) k += (r2 >= e2k[q2]) ? 1 : 0;
                     // ring slots: one ballot per bit of the bin index; the lanes of
@@ -564,17 +600,16 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
                 }(std::make_integer_sequence<int, NBG>{});
             };
             // two chunks per iteration, alternating prefetch registers; the
-            // prefetch is unconditional (past the last chunk it re-reads the last
-            // one) so that waiting for a chunk's loads never waits for the next's
-            const int last = wpad - kWave;
-            unsigned me_a = map[lane];
+            // prefetch is unconditional (past the last chunk it loads the primary)
+            // so that waiting for a chunk's loads never waits for the next's
+            unsigned me_a = fetch(0);
             double4 q_a = load_point(gP, (int)(me_a & kStartMask));
-            for (int c0 = 0; c0 < wpad; c0 += 2 * kWave) {
-                const unsigned me_b = map[min(c0 + kWave, last) + lane];
+            for (int c0 = 0; c0 < total; c0 += 2 * kWave) {
+                const unsigned me_b = fetch(c0 + kWave);
                 const double4 q_b = load_point(gP, (int)(me_b & kStartMask));
                 chunk(me_a, q_a);
-                if (c0 + kWave >= wpad) break;
-                me_a = map[min(c0 + 2 * kWave, last) + lane];
+                if (c0 + kWave >= total) break;
+                me_a = fetch(c0 + 2 * kWave);
                 q_a = load_point(gP, (int)(me_a & kStartMask));
                 chunk(me_b, q_b);
             }
@@ -643,14 +678,17 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         const int rrow = lane >> 4;
         const int sub = (rrow == 1) ? 2 : (rrow == 2 ? 1 : rrow);
         if ((lane & 15) == 0) {
+            // value 4q + sub is coefficient 2q + (sub >> 1) (mod NLM), part sub & 1;
+            // both candidates and their m are compile-time constants
+            const bool hi = (sub >> 1) != 0;
 #pragma unroll
             for (int q = 0; q < NV4 / 4; ++q) {
                 const int vi = 4 * q + sub;
-                if (vi < nvalid) {
-                    const int lm = (vi >> 1) % NLM;
-                    const int m = m_of_lm(lm);
-                    if (m >= M0 && m <= M1) out[vi] = (T)((double)c[q] * kap[lm]);
-                }
+                const int lmA = (2 * q) % NLM, lmB = (2 * q + 1) % NLM;
+                const bool inA = m_of_lm(lmA) >= M0 && m_of_lm(lmA) <= M1;
+                const bool inB = m_of_lm(lmB) >= M0 && m_of_lm(lmB) <= M1;
+                const int lm = hi ? lmB : lmA;
+                if (vi < nvalid && (hi ? inB : inA)) out[vi] = (T)((double)c[q] * kap[lm]);
             }
         }
         wave_sync();
@@ -665,7 +703,10 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
             const int v = v0 + lane;
             if (lane < CH && v < nvalid) {
                 const int lm = (v >> 1) % NLM;
-                const int m = m_of_lm(lm);
+                int l = 0;   // degree of coefficient lm: the count of t <= L with t(t+1)/2 <= lm
+#pragma unroll
+                for (int t = 1; t <= L; ++t) l += (lm >= t * (t + 1) / 2) ? 1 : 0;
+                const int m = lm - l * (l + 1) / 2;
                 if (m >= M0 && m <= M1) {
                     double s8[8];
 #pragma unroll
@@ -813,12 +854,12 @@ int launch_gather(const GatherArgs& a0, int lmax, int precision, int nbg, bool p
     a.ngroups = (a.nbins + c.nbg - 1) / c.nbg;
     if (!persistent) a.queues = nullptr;
     if (persistent && !a.queues) return (int)hipErrorInvalidValue;
-    const int64_t items = (int64_t)a.nrows * a.ngroups;
-    if (items == 0) return (int)hipSuccess;
+    const int64_t quads = ((int64_t)a.nrows + kWavesPerBlock - 1) / kWavesPerBlock * a.ngroups;
+    if (quads == 0) return (int)hipSuccess;
     for (int g = 0; g < c.nm; ++g) {
         int64_t blocks;
         if (persistent) {
-            // one block per resident wave slot (blocks are one wave each)
+            // one block per resident block slot
             int dev = 0, per_cu = 0;
             hipDeviceProp_t prop;
             hipError_t e = hipGetDevice(&dev);
@@ -828,14 +869,22 @@ int launch_gather(const GatherArgs& a0, int lmax, int precision, int nbg, bool p
                                                                  (size_t)c.lds);
             if (e != hipSuccess) return (int)e;
             blocks = std::max(1, per_cu) * (int64_t)prop.multiProcessorCount;
-            blocks = std::min<int64_t>(blocks, (items + kWavesPerBlock - 1) / kWavesPerBlock);
+            blocks = std::min<int64_t>(blocks, quads);
             const int rc = launch_fill_u32(a.queues, 8, 0u, stream);
             if (rc != 0) return rc;
         } else {
-            blocks = (items + kWavesPerBlock - 1) / kWavesPerBlock;
+            blocks = quads;
         }
         blocks = (blocks + 7) / 8 * 8;
         if (blocks > INT32_MAX) return (int)hipErrorInvalidValue;
+        if (c.lds > 65536) {   // blocks above 64 KiB of LDS need the limit raised once
+            static thread_local std::vector<const void*> raised;
+            if (std::find(raised.begin(), raised.end(), c.fn[g]) == raised.end()) {
+                const hipError_t e = hipFuncSetAttribute(c.fn[g], hipFuncAttributeMaxDynamicSharedMemorySize, c.lds);
+                if (e != hipSuccess) return (int)e;
+                raised.push_back(c.fn[g]);
+            }
+        }
         void* args[] = {&a};
         hipError_t e = hipLaunchKernel(c.fn[g], dim3((unsigned)blocks), dim3(kWave * kWavesPerBlock),
                                        args, (size_t)c.lds, stream);
