@@ -265,7 +265,8 @@ int encore_mfma_plan_stats(int npcf, int lmax, int nbins, uint32_t flags, int64_
  * as encore_build_grid) with several cell shapes (cell side r_max/d on y and z,
  * r_max/(d*s) on x, where one cell row is a contiguous particle range) and times,
  * for each, the gather + coupling of this job (as encore_npcf) over a sample of
- * n_sample primaries spread over the input order, for every compiled
+ * n_sample primaries (16 runs of consecutive cell-sorted primaries spread over the
+ * grid, so that neighbouring work items share cells as in a full pass), for every compiled
  * bins-per-work-item value of the gather.  The fastest (d, s) becomes the cell
  * shape of later grids built on ctx; the fastest bins-per-item value is used by
  * later calls with the same lmax, gather precision and nbins.  The choice changes

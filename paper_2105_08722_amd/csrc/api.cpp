@@ -256,7 +256,7 @@ int encore_destroy(encore_ctx* ctx)
     for (auto& kv : ctx->tables) {
         DevTables& d = kv.second;
         for (void* p : {(void*)d.tuple_off, (void*)d.tuple_flags, (void*)d.btab, (void*)d.term_start,
-                        (void*)d.term_tuple, (void*)d.term_coef, (void*)d.kappa, (void*)d.gamma,
+                        (void*)d.term_tuple, (void*)d.term_coef, (void*)d.kappa,
                         (void*)d.mf_rows, (void*)d.mf_cols, (void*)d.mf_tmap, (void*)d.mf_jobs[0],
                         (void*)d.mf_jobs[1], (void*)d.mf_jobs[2], (void*)d.mf_jobs[3]})
             if (p) (void)hipFree(p);
@@ -454,10 +454,19 @@ int encore_autotune(encore_ctx* ctx, const double* pos, const double* w, int64_t
     const int gprec = pl.prec == 0 ? 0 : 1;
     const std::vector<int> nbgs = gather_nbg_options(lmax, gprec);
     // cell shapes tried: (y/z divisor of r_max, extra x subdivision); the default first
-    static const double kCells[][2] = {{6, 4}, {6, 8}, {8, 4}, {8, 2}, {5, 4}, {4, 6}};
+    static const double kCells[][2] = {{6, 4}, {6, 8}, {8, 4}, {8, 8}, {8, 2}, {5, 4}, {4, 6}, {10, 4}};
+    // The sample: 16 runs of consecutive cell-sorted primaries spread over the grid,
+    // so that neighbouring work items share cells as in a full pass (a scattered
+    // sample would time cache misses that a full pass does not have).
     const int64_t k = std::min<int64_t>(n, std::max<int64_t>(1, n_sample));
-    std::vector<int64_t> sample(k);
-    for (int64_t i = 0; i < k; ++i) sample[i] = i * n / k;   // spread over the input order
+    const int64_t runs = std::min<int64_t>(16, k);
+    std::vector<int32_t> sample;
+    sample.reserve(k);
+    for (int64_t q = 0; q < runs; ++q) {
+        const int64_t len = k / runs + (q < k % runs ? 1 : 0);
+        const int64_t start = runs > 1 ? (n - len) * q / (runs - 1) : 0;
+        for (int64_t j = 0; j < len; ++j) sample.push_back((int32_t)(start + j));
+    }
     const size_t need = (size_t)std::max<int64_t>(pl.nlam * pl.nB, 1);
     std::vector<double> ztmp(need);
     std::lock_guard<std::mutex> lock(ctx->mu);
@@ -484,8 +493,14 @@ int encore_autotune(encore_ctx* ctx, const double* pos, const double* w, int64_t
         rc = build_grid_dev(ctx->device, d_pos, d_w, n, n_data, (flags & ENCORE_DMR) != 0,
                             periodic ? box : nullptr, r_max, cell[0], cell[1], s, tg.g);
         if (rc) break;
-        int64_t np = 0;
-        if ((rc = make_primaries(x, &tg, sample.data(), k, &np)) == ENCORE_OK) {
+        const int64_t np = k;
+        rc = ensure(x.prim, sizeof(int32_t) * (size_t)k);
+        if (rc == ENCORE_OK) {
+            const hipError_t ce = hipMemcpyAsync(x.prim.p, sample.data(), sizeof(int32_t) * (size_t)k,
+                                                 hipMemcpyHostToDevice, s);
+            if (ce != hipSuccess) rc = hip_fail(ce, "encore_autotune: sample upload");
+        }
+        if (rc == ENCORE_OK) {
             for (size_t q = 0; q < nbgs.size() && rc == ENCORE_OK; ++q) {
                 pl.nbg = nbgs[q];
                 double t = 1e300;
@@ -576,12 +591,11 @@ int encore_debug_alm(encore_ctx* ctx, const encore_grid* grid, int lmax, int nbi
     if ((rc = ensure(x.zeta, sizeof(double) * (size_t)(nlaunch * per)))) return rc;
     if ((rc = ensure(x.wprim, sizeof(double) * (size_t)nlaunch))) return rc;
     if ((rc = ensure(x.segs, sizeof(GatherSeg)))) return rc;
-    std::vector<double> kap(nlm), gam(nlm);
-    gather_tables(lmax, kap.data(), gam.data());
+    std::vector<double> kap(nlm);
+    gather_tables(lmax, kap.data());
     double* d_kg = nullptr;
-    HIPTRY(hipMalloc(&d_kg, sizeof(double) * 2 * nlm));
+    HIPTRY(hipMalloc(&d_kg, sizeof(double) * nlm));
     hipError_t e = hipMemcpy(d_kg, kap.data(), sizeof(double) * nlm, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(d_kg + nlm, gam.data(), sizeof(double) * nlm, hipMemcpyHostToDevice);
     const DevGrid& g = grid->g;
     GatherSeg gs;
     gs.P = g.P; gs.cell_start = g.cell_start; gs.prim = (const int32_t*)x.prim.p;
@@ -596,7 +610,6 @@ int encore_debug_alm(encore_ctx* ctx, const encore_grid* grid, int lmax, int nbi
     ga.nbins = nbins;
     for (int b = 0; b <= nbins; ++b) ga.e2[b] = edges[b] * edges[b];
     ga.kappa = d_kg;
-    ga.gamma = d_kg + nlm;
     ga.alm = x.alm.p;
     ga.wprim = (double*)x.wprim.p;
     ga.segs = (const GatherSeg*)x.segs.p;

@@ -70,7 +70,6 @@ struct GatherArgs {
     void* alm;               // output rows
     double* wprim;           // output: weight of each row's primary
     const double* kappa;     // [nlm] final scale of the monic recurrence
-    const double* gamma;     // [nlm] recurrence coefficients
     unsigned long long* npairs;  // optional: += accepted pairs (null: not counted)
     // persistent mode (queues != null): waves pull items from 8 queues (one per
     // XCD, contiguous item ranges) and steal from the others when theirs is empty
@@ -82,7 +81,7 @@ int launch_gather(const GatherArgs& a, int lmax, int precision, int nbg, bool pe
 int gather_group_bins(int lmax, int precision, int nbg);
 // compiled bins-per-item values for (lmax, precision), the default first
 std::vector<int> gather_nbg_options(int lmax, int precision);
-void gather_tables(int lmax, double* kappa, double* gamma);
+void gather_tables(int lmax, double* kappa);
 
 // ------------------------------------------------------------------ coupling
 // For every split y: T[y][t][B] = sum over rows p in [split_lo[y], split_hi[y]) of

@@ -180,13 +180,13 @@ int get_tables(encore_ctx* ctx, int N, int lmax, bool allparity, int nbins, DevT
     for (int32_t l : tt.lam) tstart[l + 1]++;
     for (int64_t l = 0; l < tt.nlam; ++l) tstart[l + 1] += tstart[l];
     const int nlm = (lmax + 1) * (lmax + 2) / 2;
-    std::vector<double> kap(nlm), gam(nlm);
-    gather_tables(lmax, kap.data(), gam.data());
+    std::vector<double> kap(nlm);
+    gather_tables(lmax, kap.data());
     int rc;
     if ((rc = upload(d.tuple_off, toff)) || (rc = upload(d.tuple_flags, tflags)) ||
         (rc = upload(d.btab, bt)) || (rc = upload(d.term_start, tstart)) ||
         (rc = upload(d.term_tuple, tt.term_tuple)) || (rc = upload(d.term_coef, tt.coef)) ||
-        (rc = upload(d.kappa, kap)) || (rc = upload(d.gamma, gam)))
+        (rc = upload(d.kappa, kap)))
         return rc;
     auto res = ctx->tables.emplace(key, d);
     *out = &res.first->second;
@@ -341,7 +341,6 @@ int prepare_slice(Exec& x, Buf& segs, Buf& splits, Buf& redp, const NpcfPlan& pl
     ga.nbins = pl.nbins;
     for (int b = 0; b <= pl.nbins; ++b) ga.e2[b] = edges[b] * edges[b];
     ga.kappa = tb->kappa;
-    ga.gamma = tb->gamma;
     ga.alm = x.alm.p;
     ga.wprim = (double*)x.wprim.p;
     ga.npairs = (unsigned long long*)x.misc.p;

@@ -35,7 +35,6 @@ struct DevTables {
     int32_t* term_tuple = nullptr;
     double* term_coef = nullptr;
     double* kappa = nullptr;
-    double* gamma = nullptr;
     // split-BF16 MFMA plan (built on first use)
     bool mf_ready = false;
     int mf_KF = 0, mf_nent = 0;

@@ -64,8 +64,8 @@ template <typename T> __device__ __forceinline__ T rsqrt_t(T v);
 template <> __device__ __forceinline__ float rsqrt_t<float>(float v) { return __builtin_amdgcn_rsqf(v); }
 template <> __device__ __forceinline__ double rsqrt_t<double>(double v) { return 1.0 / sqrt(v); }
 
-// LDS of one wave: the per-bin rings (reused as the reduction scratch), the
-// per-lane segment slots and the compacted segment list of one row batch.
+// LDS of one wave: the per-bin rings (reused as the reduction scratch) and the
+// piece descriptors of one row batch.
 template <typename T, int NBG>
 __host__ __device__ constexpr int ring_bytes()
 {
@@ -76,14 +76,47 @@ __host__ __device__ constexpr int ring_bytes()
 template <typename T, int NBG>
 __host__ __device__ constexpr int wave_lds_bytes()
 {
-    // ring | slot_stc[kSegCap] slot_len[kSegCap] | seg_dl[kSegCap] seg_flat[kSegCap + 1]
-    return ring_bytes<T, NBG>() + 4 * (4 * kSegCap + 4);
+    // ring | seg_dl[kSegCap] seg_flat[kSegCap + 1]
+    return ring_bytes<T, NBG>() + 4 * (2 * kSegCap + 4);
 }
+
+// Square root by Newton's iteration, for the compile-time tables below.
+constexpr double ce_sqrt(double x)
+{
+    if (!(x > 0.0)) return 0.0;
+    double r = x < 1.0 ? 1.0 : x;
+    for (int i = 0; i < 200; ++i) {
+        const double n = 0.5 * (r + x / r);
+        if (n == r) break;
+        r = n;
+    }
+    return r;
+}
+
+// Recurrence coefficients of the normalised associated Legendre functions,
+// R_lm = z R_{l-1,m} - gamma_lm R_{l-2,m} (l >= m + 2), with
+// gamma_lm = b_lm kappa_{l-2,m} / kappa_{l-1,m} (kappa, a and b as in gather_tables):
+// the ratio is 1 / sqrt(2m + 3) for l = m + 2 and 1 / a_{l-1,m} above.  Zero for l < m + 2.
+template <int L>
+struct GammaTable {
+    double v[nlm_of(L)];
+    constexpr GammaTable() : v{}
+    {
+        for (int m = 0; m <= L; ++m)
+            for (int l = m + 2; l <= L; ++l) {
+                const double l1 = l - 1;
+                const double bl = ce_sqrt((l1 * l1 - (double)m * m) / (4.0 * l1 * l1 - 1.0));
+                const double den = (l == m + 2) ? ce_sqrt(2.0 * m + 3.0)
+                                                : ce_sqrt((4.0 * l1 * l1 - 1.0) / (l1 * l1 - (double)m * m));
+                v[lm_index(l, m)] = bl / den;
+            }
+    }
+};
+template <int L> struct Gamma { static constexpr GammaTable<L> t{}; };
 
 // Add w*Y_lm for m in [M0, M1] of one pair into acc (layout [lm][re, im]).
 template <typename T, int L, int M0, int M1>
-__device__ __forceinline__ void accum_pair(T dx, T dy, T dz, T w, T (&acc)[nlm_of(L)][2],
-                                           const T (&gam)[nlm_of(L)])
+__device__ __forceinline__ void accum_pair(T dx, T dy, T dz, T w, T (&acc)[nlm_of(L)][2])
 {
     const T r2 = dx * dx + dy * dy + dz * dz;
     const T inv = rsqrt_t<T>(r2);
@@ -120,7 +153,7 @@ __device__ __forceinline__ void accum_pair(T dx, T dy, T dz, T w, T (&acc)[nlm_o
         }
 #pragma unroll
         for (int l = m + 2; l <= L; ++l) {
-            const T rn = z * r1 - gam[lm_index(l, m)] * r0;
+            const T rn = z * r1 - (T)Gamma<L>::t.v[lm_index(l, m)] * r0;
             if (m == 0) {
                 acc[lm_index(l, 0)][0] += rn;
             } else {
@@ -251,15 +284,23 @@ __device__ __forceinline__ RowFrame<R> make_frame(const GatherSeg& g, double xi,
     return f;
 }
 
-// One cell row (lane's row r of the primary's row range): clip its x extent to the
-// culling sphere's chord, minus the inner hole where the whole row is inside it,
-// split at periodic images, and write its non-empty pieces (start | image code,
-// length) to the lane's slots.  Row, cell and image indices stay within one period
-// of the grid because the largest separation is at most half the box.
+// One cell row (lane's row r of the primary's row range): its x extent clipped to
+// the culling sphere's chord, minus the inner hole where the whole row is inside
+// it.  Row, cell and image indices stay within one period of the grid because the
+// largest separation is at most half the box.
+struct RowGeom {
+    int rowbase, code_yz;
+    int lo[2], hi[2];   // unwrapped x cell ranges, left and right of the hole (lo > hi: none)
+};
+
 template <typename R>
-__device__ __forceinline__ void setup_row(const RowFrame<R>& f, const GatherSeg& g, gptr<int32_t> gcs, int r,
-                                          int lane, int* slot_stc, int* slot_len, int& ns, int& nlen)
+__device__ __forceinline__ RowGeom row_geom(const RowFrame<R>& f, const GatherSeg& g, int r)
 {
+    RowGeom rg;
+    rg.lo[0] = rg.lo[1] = 1;
+    rg.hi[0] = rg.hi[1] = 0;
+    rg.rowbase = 0;
+    rg.code_yz = 0;
     // r / nyr: the float product is exact below 2^22 rows
     const int rz = r < (1 << 22) ? (int)(((float)r + 0.5f) * f.inv_nyr) : r / f.nyr;
     const int ky = f.ky0 + (r - rz * f.nyr), kz = f.kz0 + rz;
@@ -275,7 +316,7 @@ __device__ __forceinline__ void setup_row(const RowFrame<R>& f, const GatherSeg&
     const R dymin = fmax((R)0, fmax(ylo - f.py, f.py - yhi));
     const R dzmin = fmax((R)0, fmax(zlo - f.pz, f.pz - zhi));
     const R rho2 = dymin * dymin + dzmin * dzmin;
-    if (!(rho2 < f.Rc2)) return;
+    if (!(rho2 < f.Rc2)) return rg;
     const R h = sqrt(f.Rc2 - rho2) + f.eps;
     int kx0 = (int)floor((f.px - h) * f.icsx), kx1 = (int)floor((f.px + h) * f.icsx);
     if (!g.periodic) { kx0 = max(kx0, 0); kx1 = min(kx1, g.ncx - 1); }
@@ -290,38 +331,65 @@ __device__ __forceinline__ void setup_row(const RowFrame<R>& f, const GatherSeg&
             kin1 = (int)floor((f.px + hin) * f.icsx) - 1;
         }
     }
-    const int rowbase = (wz * g.ncy + wy) * g.ncx;
-    const int code_yz = ((sy + 1) << 2) | ((sz + 1) << 4);
-    // at most two x ranges: left of and right of the inner hole
+    rg.rowbase = (wz * g.ncy + wy) * g.ncx;
+    rg.code_yz = ((sy + 1) << 2) | ((sz + 1) << 4);
+    if (kin0 <= kin1) {
+        rg.lo[0] = kx0; rg.hi[0] = min(kx1, kin0 - 1);
+        rg.lo[1] = max(kx0, kin1 + 1); rg.hi[1] = kx1;
+    } else {
+        rg.lo[0] = kx0; rg.hi[0] = kx1;
+    }
+    return rg;
+}
+
+// periodic image range (-1, 0, +1) of the cells [lo, hi]
+__device__ __forceinline__ void image_range(const GatherSeg& g, int lo, int hi, int& sxa, int& sxb)
+{
+    sxa = 0; sxb = 0;
+    if (g.periodic) {
+        sxa = lo < 0 ? -1 : (lo >= g.ncx ? 1 : 0);
+        sxb = hi < 0 ? -1 : (hi >= g.ncx ? 1 : 0);
+    }
+}
+
+// pieces of a row: one per x range and periodic image (<= kSegPerRow), empty ones included
+__device__ __forceinline__ int row_pieces(const RowGeom& rg, const GatherSeg& g)
+{
+    int n = 0;
+#pragma unroll
     for (int q = 0; q < 2; ++q) {
-        int lo, hi;
-        if (kin0 <= kin1) {
-            lo = (q == 0) ? kx0 : max(kx0, kin1 + 1);
-            hi = (q == 0) ? min(kx1, kin0 - 1) : kx1;
-        } else {
-            if (q == 1) break;
-            lo = kx0; hi = kx1;
-        }
-        if (lo > hi) continue;
-        int sxa = 0, sxb = 0;
-        if (g.periodic) {
-            sxa = lo < 0 ? -1 : (lo >= g.ncx ? 1 : 0);
-            sxb = hi < 0 ? -1 : (hi >= g.ncx ? 1 : 0);
-        }
-        for (int sx = sxa; sx <= sxb && ns < kSegPerRow; ++sx) {
-            const int plo = max(lo, sx * g.ncx) - sx * g.ncx;
-            const int phi = min(hi, sx * g.ncx + g.ncx - 1) - sx * g.ncx;
-            const int st = gcs[rowbase + plo];
-            const int en = gcs[rowbase + phi + 1];
-            if (en > st) {
-                const int slot = lane * kSegPerRow + ns;
-                slot_stc[slot] = st | (((sx + 1) | code_yz) << kCodeShift);
-                slot_len[slot] = en - st;
-                nlen += en - st;
-                ++ns;
-            }
+        if (rg.lo[q] > rg.hi[q]) continue;
+        int sxa, sxb;
+        image_range(g, rg.lo[q], rg.hi[q], sxa, sxb);
+        n += sxb - sxa + 1;
+    }
+    return n;
+}
+
+// Write the row's pieces at slots [s0, ...): entry of the first candidate (start |
+// image code) and length.  Because particles are sorted by cell with x fastest,
+// each piece is one contiguous particle range.
+__device__ __forceinline__ int emit_pieces(const RowGeom& rg, const GatherSeg& g, gptr<int32_t> gcs, int s0,
+                                           unsigned* ent, int* len)
+{
+    int k = s0, nlen = 0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        if (rg.lo[q] > rg.hi[q]) continue;
+        int sxa, sxb;
+        image_range(g, rg.lo[q], rg.hi[q], sxa, sxb);
+        for (int sx = sxa; sx <= sxb; ++sx) {
+            const int plo = max(rg.lo[q], sx * g.ncx) - sx * g.ncx;
+            const int phi = min(rg.hi[q], sx * g.ncx + g.ncx - 1) - sx * g.ncx;
+            const int st = gcs[rg.rowbase + plo];
+            const int en = gcs[rg.rowbase + phi + 1];
+            ent[k] = (unsigned)st | ((unsigned)((sx + 1) | rg.code_yz) << kCodeShift);
+            len[k] = en - st;
+            nlen += en - st;
+            ++k;
         }
     }
+    return nlen;
 }
 
 // waves per SIMD the kernel is compiled for, from its accumulator registers
@@ -329,7 +397,7 @@ template <typename T, int L, int NBG, int M0, int M1>
 __host__ __device__ constexpr int gather_wpe()
 {
     constexpr int acc = NBG * ((L + 1) * (L + 1)) * (int)(sizeof(T) / 4);
-    return acc <= 48 ? 4 : (acc <= 72 ? 3 : 2);
+    return acc <= 48 ? 5 : (acc <= 72 ? 4 : 2);
 }
 
 template <typename T, int L, int NBG, int M0, int M1>
@@ -345,15 +413,9 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
     unsigned char* base = smem + wib * wave_lds_bytes<T, NBG>();
     E* ring = reinterpret_cast<E*>(base);
     T* scratch = reinterpret_cast<T*>(base);
-    int* slot_stc = reinterpret_cast<int*>(base + ring_bytes<T, NBG>());
-    int* slot_len = slot_stc + kSegCap;
-    unsigned* seg_dl = reinterpret_cast<unsigned*>(slot_len + kSegCap);
+    unsigned* seg_dl = reinterpret_cast<unsigned*>(base + ring_bytes<T, NBG>());
     int* seg_flat = reinterpret_cast<int*>(seg_dl + kSegCap);
 
-    // recurrence coefficients -> registers (uniform)
-    T gam[NLM];
-#pragma unroll
-    for (int q = 0; q < NLM; ++q) gam[q] = (T)a.gamma[q];
 
     // Item j -> quad j / kWavesPerBlock = (row block, bin group), row = block *
     // kWavesPerBlock + j % kWavesPerBlock.  Rows are cell-sorted primaries, so the
@@ -443,23 +505,29 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
                                                  fmax(1e-3, 1e-6 * (double)nmax));
 
     for (int rb = 0; rb < nrows; rb += kRowsPerBatch) {
-        // ---- 1. lane-parallel row set-up: lane r writes its <= kSegPerRow pieces to
-        //         slots [lane * kSegPerRow, ...)
-        int ns = 0, nlen = 0;
+        // ---- 1. lane-parallel row set-up: lane r counts its row's pieces, which
+        //         are written straight to their slots in (lane, piece) order; then
+        //         each lane turns its lengths into flat positions and its entries
+        //         into deltas (entry minus flat position: a candidate's entry is its
+        //         flat position plus its piece's delta; start + length < 2^26 never
+        //         carries into the image code)
         const int r = rb + lane;
-        if (r < nrows) setup_row<float>(rf, g, gcs, r, lane, slot_stc, slot_len, ns, nlen);
-        // compact the pieces in (lane, piece) order: flat position of the first
-        // candidate, and entry minus flat position (so a candidate's entry is its
-        // flat position plus its piece's delta; start + length < 2^26 never carries
-        // into the image code)
+        RowGeom rg;
+        rg.lo[0] = rg.lo[1] = 1;
+        rg.hi[0] = rg.hi[1] = 0;
+        rg.rowbase = rg.code_yz = 0;
+        if (r < nrows) rg = row_geom<float>(rf, g, r);
+        const int ns = row_pieces(rg, g);
         int nseg = 0, total = 0;
         const int sbase = wave_excl_scan(ns, lane, &nseg);
+        wave_sync();                        // the previous batch's descriptors are consumed
+        const int nlen = emit_pieces(rg, g, gcs, sbase, seg_dl, seg_flat);
         int fbase = wave_excl_scan(nlen, lane, &total);
-        wave_sync();
-        for (int q = 0; q < ns; ++q) {
-            seg_dl[sbase + q] = (unsigned)slot_stc[lane * kSegPerRow + q] - (unsigned)fbase;
+        for (int q = 0; q < ns; ++q) {      // the lane's own slots only
+            const int ln = seg_flat[sbase + q];
             seg_flat[sbase + q] = fbase;
-            fbase += slot_len[lane * kSegPerRow + q];
+            seg_dl[sbase + q] -= (unsigned)fbase;
+            fbase += ln;
         }
         wave_sync();
 
@@ -593,7 +661,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
                         if (tail[K] - head[K] >= kWave) {
                             wave_sync();
                             const E e = ring[K * kCap + ((head[K] + lane) & (kCap - 1))];
-                            accum_pair<T, L, M0, M1>(e.x, e.y, e.z, e.w, acc[K], gam);
+                            accum_pair<T, L, M0, M1>(e.x, e.y, e.z, e.w, acc[K]);
                             head[K] += kWave;
                         }
                     }(), ...);
@@ -632,7 +700,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
             if (rem > 0) {
                 E e = ring[K * kCap + ((head[K] + lane) & (kCap - 1))];
                 if (lane >= rem) { e.x = (T)1; e.y = (T)0; e.z = (T)0; e.w = (T)0; }
-                accum_pair<T, L, M0, M1>(e.x, e.y, e.z, e.w, acc[K], gam);
+                accum_pair<T, L, M0, M1>(e.x, e.y, e.z, e.w, acc[K]);
             }
         }(), ...);
     }(std::make_integer_sequence<int, NBG>{});
@@ -819,28 +887,21 @@ std::vector<int> gather_nbg_options(int lmax, int precision)
     return precision == 1 ? f32[lmax] : f64[lmax];
 }
 
-void gather_tables(int lmax, double* kappa, double* gamma)
+void gather_tables(int lmax, double* kappa)
 {
     // kappa_mm = (-1)^m c_m, c_0 = 1/sqrt(4 pi), c_m = c_{m-1} sqrt((2m+1)/(2m));
     // kappa_{m+1,m} = sqrt(2m+3) kappa_mm; kappa_lm = a_lm kappa_{l-1,m} (l >= m+2),
-    // a_lm = sqrt((4l^2-1)/(l^2-m^2)), b_lm = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1)),
-    // gamma_lm = b_lm kappa_{l-2,m} / kappa_{l-1,m}.
+    // a_lm = sqrt((4l^2-1)/(l^2-m^2)); the recurrence coefficients gamma_lm use
+    // b_lm = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1)) (GammaTable).
     double c = 1.0 / std::sqrt(4.0 * M_PI);
     for (int m = 0; m <= lmax; ++m) {
         if (m > 0) c *= std::sqrt((2.0 * m + 1.0) / (2.0 * m));
         const double kmm = (m % 2) ? -c : c;
         kappa[lm_index(m, m)] = kmm;
-        gamma[lm_index(m, m)] = 0.0;
-        if (m + 1 <= lmax) {
-            kappa[lm_index(m + 1, m)] = std::sqrt(2.0 * m + 3.0) * kmm;
-            gamma[lm_index(m + 1, m)] = 0.0;
-        }
+        if (m + 1 <= lmax) kappa[lm_index(m + 1, m)] = std::sqrt(2.0 * m + 3.0) * kmm;
         for (int l = m + 2; l <= lmax; ++l) {
             const double al = std::sqrt((4.0 * l * l - 1.0) / ((double)l * l - (double)m * m));
-            const double bl = std::sqrt(((double)(l - 1) * (l - 1) - (double)m * m) /
-                                        (4.0 * (l - 1) * (l - 1) - 1.0));
             kappa[lm_index(l, m)] = al * kappa[lm_index(l - 1, m)];
-            gamma[lm_index(l, m)] = bl * kappa[lm_index(l - 2, m)] / kappa[lm_index(l - 1, m)];
         }
     }
 }
