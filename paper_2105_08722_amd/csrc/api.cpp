@@ -604,11 +604,15 @@ int encore_debug_alm(encore_ctx* ctx, const encore_grid* grid, int lmax, int nbi
     gs.csx = g.csx; gs.csy = g.csy; gs.csz = g.csz;
     gs.Lx = g.Lx; gs.Ly = g.Ly; gs.Lz = g.Lz;
     gs.row0 = 0; gs.nprim = (int)nlaunch;
+    finish_seg(gs);
     if (e == hipSuccess) e = hipMemcpy(x.segs.p, &gs, sizeof(gs), hipMemcpyHostToDevice);
     GatherArgs ga;
     memset(&ga, 0, sizeof(ga));
     ga.nbins = nbins;
-    for (int b = 0; b <= nbins; ++b) ga.e2[b] = edges[b] * edges[b];
+    for (int b = 0; b <= nbins; ++b) {
+        ga.e2[b] = edges[b] * edges[b];
+        ga.e1[b] = edges[b];
+    }
     ga.kappa = d_kg;
     ga.alm = x.alm.p;
     ga.wprim = (double*)x.wprim.p;

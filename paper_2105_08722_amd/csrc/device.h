@@ -58,7 +58,23 @@ struct GatherSeg {
     double ox, oy, oz, csx, csy, csz;
     double Lx, Ly, Lz;
     int row0, nprim;
+    // derived by finish_seg: reciprocal cell sizes, the pad of the culling radius
+    // and the FP32 row set-up margin (both in length units)
+    double icsx, icsy, icsz, cull_pad, frame_eps;
 };
+inline void finish_seg(GatherSeg& s)
+{
+    s.icsx = 1.0 / s.csx;
+    s.icsy = 1.0 / s.csy;
+    s.icsz = 1.0 / s.csz;
+    const double cmin = s.csx < s.csy ? (s.csx < s.csz ? s.csx : s.csz) : (s.csy < s.csz ? s.csy : s.csz);
+    const int nmax = s.ncx > s.ncy ? (s.ncx > s.ncz ? s.ncx : s.ncz) : (s.ncy > s.ncz ? s.ncy : s.ncz);
+    s.cull_pad = 1e-7 * cmin;
+    // FP32 rounding of coordinates relative to the grid origin is about
+    // nmax * 2^-23 cells; the margin is far above it
+    const double margin = 1e-6 * nmax > 1e-3 ? 1e-6 * nmax : 1e-3;
+    s.frame_eps = margin * cmin;
+}
 struct GatherArgs {
     const GatherSeg* segs;   // device array
     int nseg;
@@ -67,6 +83,7 @@ struct GatherArgs {
     int ngroups;             // bin groups per primary (work items per primary)
     int group_bins;          // bins per group (last group may have fewer)
     double e2[kMaxBins + 1]; // squared edges
+    double e1[kMaxBins + 1]; // edges
     void* alm;               // output rows
     double* wprim;           // output: weight of each row's primary
     const double* kappa;     // [nlm] final scale of the monic recurrence

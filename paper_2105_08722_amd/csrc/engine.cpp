@@ -301,6 +301,7 @@ int prepare_slice(Exec& x, Buf& segs, Buf& splits, Buf& redp, const NpcfPlan& pl
         gs.csx = g.csx; gs.csy = g.csy; gs.csz = g.csz;
         gs.Lx = g.Lx; gs.Ly = g.Ly; gs.Lz = g.Lz;
         gs.row0 = (int)rows; gs.nprim = (int)take;
+        finish_seg(gs);
         hsegs.push_back(gs);
         rlo.push_back((int32_t)slo.size());
         for (int64_t r = 0; r < take; r += c.split_rows) {
@@ -339,7 +340,10 @@ int prepare_slice(Exec& x, Buf& segs, Buf& splits, Buf& redp, const NpcfPlan& pl
     GatherArgs& ga = L.ga;
     memset(&ga, 0, sizeof(ga));
     ga.nbins = pl.nbins;
-    for (int b = 0; b <= pl.nbins; ++b) ga.e2[b] = edges[b] * edges[b];
+    for (int b = 0; b <= pl.nbins; ++b) {
+        ga.e2[b] = edges[b] * edges[b];
+        ga.e1[b] = edges[b];
+    }
     ga.kappa = tb->kappa;
     ga.alm = x.alm.p;
     ga.wprim = (double*)x.wprim.p;

@@ -235,6 +235,8 @@ __device__ __forceinline__ GatherSeg load_seg(const GatherSeg* segs, int s)
     g.csx = uni(g.csx); g.csy = uni(g.csy); g.csz = uni(g.csz);
     g.Lx = uni(g.Lx); g.Ly = uni(g.Ly); g.Lz = uni(g.Lz);
     g.row0 = uni(g.row0); g.nprim = uni(g.nprim);
+    g.icsx = uni(g.icsx); g.icsy = uni(g.icsy); g.icsz = uni(g.icsz);
+    g.cull_pad = uni(g.cull_pad); g.frame_eps = uni(g.frame_eps);
     return g;
 }
 
@@ -266,21 +268,20 @@ struct RowFrame {
 
 template <typename R>
 __device__ __forceinline__ RowFrame<R> make_frame(const GatherSeg& g, double xi, double yi, double zi,
-                                                 double R2in, double R2out, int ky0, int kz0, int nyr,
-                                                 double margin)
+                                                 double Rin, double Rout, int ky0, int kz0, int nyr)
 {
     RowFrame<R> f;
-    const double eps = margin * fmin(g.csx, fmin(g.csy, g.csz));
+    const double eps = g.frame_eps;
     f.px = (R)(xi - g.ox); f.py = (R)(yi - g.oy); f.pz = (R)(zi - g.oz);
     f.csx = (R)g.csx; f.csy = (R)g.csy; f.csz = (R)g.csz;
-    f.icsx = (R)(1.0 / g.csx);
+    f.icsx = (R)g.icsx;
     f.eps = (R)eps;
-    const double rc = sqrt(R2out) + eps;
+    const double rc = Rout + eps;
     f.Rc2 = (R)(rc * rc);
-    const double rin = fmax(0.0, sqrt(R2in) - eps);
+    const double rin = fmax(0.0, Rin - eps);
     f.R2in = (R)(rin * rin);
     f.ky0 = ky0; f.kz0 = kz0; f.nyr = nyr;
-    f.inv_nyr = 1.0f / (float)max(nyr, 1);
+    f.inv_nyr = __builtin_amdgcn_rcpf((float)max(nyr, 1));
     return f;
 }
 
@@ -301,8 +302,10 @@ __device__ __forceinline__ RowGeom row_geom(const RowFrame<R>& f, const GatherSe
     rg.hi[0] = rg.hi[1] = 0;
     rg.rowbase = 0;
     rg.code_yz = 0;
-    // r / nyr: the float product is exact below 2^22 rows
-    const int rz = r < (1 << 22) ? (int)(((float)r + 0.5f) * f.inv_nyr) : r / f.nyr;
+    // r / nyr: with inv_nyr within 1 ulp of 1 / nyr the float product stays within
+    // 2^-22 relative of (r + 0.5) / nyr, whose distance from an integer is at least
+    // 0.5 / nyr, so its floor is exact for r + 0.5 < 2^21
+    const int rz = r < (1 << 20) ? (int)(((float)r + 0.5f) * f.inv_nyr) : r / f.nyr;
     const int ky = f.ky0 + (r - rz * f.nyr), kz = f.kz0 + rz;
     int wy = ky, wz = kz, sy = 0, sz = 0;
     if (g.periodic) {
@@ -476,7 +479,8 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
     // periodic images: shift per axis for image codes 0, 1, 2 (-L, 0, +L)
     const double Lx = g.Lx, Ly = g.Ly, Lz = g.Lz;
     // culling uses slightly enlarged cells and radius; the bin test below is exact
-    const double Rc = sqrt(R2out) + 1e-7 * fmin(g.csx, fmin(g.csy, g.csz));
+    const double Rin = uni(a.e1[b_lo]), Rout = uni(a.e1[b_hi]);
+    const double Rc = Rout + g.cull_pad;
 
     int head[NBG], tail[NBG];
 #pragma unroll
@@ -488,8 +492,9 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         for (int q = 0; q < NLM; ++q) { acc[k][q][0] = (T)0; acc[k][q][1] = (T)0; }
 
     // row range (unwrapped cell indices)
-    int ky0 = (int)floor((yi - Rc - g.oy) / g.csy), ky1 = (int)floor((yi + Rc - g.oy) / g.csy);
-    int kz0 = (int)floor((zi - Rc - g.oz) / g.csz), kz1 = (int)floor((zi + Rc - g.oz) / g.csz);
+    // (reciprocal multiplies: the pad of Rc is far above their rounding)
+    int ky0 = (int)floor((yi - Rc - g.oy) * g.icsy), ky1 = (int)floor((yi + Rc - g.oy) * g.icsy);
+    int kz0 = (int)floor((zi - Rc - g.oz) * g.icsz), kz1 = (int)floor((zi + Rc - g.oz) * g.icsz);
     if (!g.periodic) {
         ky0 = max(ky0, 0); ky1 = min(ky1, g.ncy - 1);
         kz0 = max(kz0, 0); kz1 = min(kz1, g.ncz - 1);
@@ -500,9 +505,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
     // exactly in FP64 below), so the set-up runs in FP32 with a margin, in cell
     // units, far above the FP32 rounding of coordinates relative to the grid origin
     // (about n * 2^-23 cells for a grid n cells long).
-    const int nmax = max(g.ncx, max(g.ncy, g.ncz));
-    const RowFrame<float> rf = make_frame<float>(g, xi, yi, zi, R2in, R2out, ky0, kz0, nyr,
-                                                 fmax(1e-3, 1e-6 * (double)nmax));
+    const RowFrame<float> rf = make_frame<float>(g, xi, yi, zi, Rin, Rout, ky0, kz0, nyr);
 
     for (int rb = 0; rb < nrows; rb += kRowsPerBatch) {
         // ---- 1. lane-parallel row set-up: lane r counts its row's pieces, which
@@ -610,7 +613,8 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
                     // mbcnt of that bin's mask, offset by the bin's tail
                     const bool c_in = r2 >= R2in, c_out = r2 < R2out, c_k = r2 >= e2k[1];
                     ok = c_in && c_out;
-                    const unsigned long long okm = __builtin_amdgcn_ballot_w64(ok);
+                    const unsigned long long okm =
+                        __builtin_amdgcn_ballot_w64(c_in) & __builtin_amdgcn_ballot_w64(c_out);
                     const unsigned long long km = __builtin_amdgcn_ballot_w64(c_k);
                     const unsigned long long m1 = okm & km, m0 = okm & ~km;
                     const unsigned r0 = __builtin_amdgcn_mbcnt_hi((unsigned)(m0 >> 32),
@@ -619,7 +623,12 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
                     const unsigned r1 = __builtin_amdgcn_mbcnt_hi((unsigned)(m1 >> 32),
                                                                   __builtin_amdgcn_mbcnt_lo((unsigned)m1, 0u)) +
                                         (unsigned)tail[1];
-                    slot = (int)(c_k ? ((r1 & (kCap - 1)) | (unsigned)kCap) : (r0 & (kCap - 1)));
+                    // select by the lane mask itself (both ranks are computed anyway; a
+                    // conditional would be turned into two divergent branches)
+                    const unsigned s0 = r0 & (kCap - 1), s1 = (r1 & (kCap - 1)) | (unsigned)kCap;
+                    unsigned sl;
+                    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(sl) : "v"(s0), "v"(s1), "s"(km));
+                    slot = (int)sl;
                     tail[0] += __popcll(m0);
                     tail[1] += __popcll(m1);
                 } else {
