@@ -12,11 +12,13 @@
 // registers every kFlushSteps K blocks; the dropped lo*lo term and the two
 // representation errors are each below 2^-18 of |A B|.
 //
-// A block of 16 waves works on one split of primaries; every K block (16
-// primaries) is staged once in LDS for all its waves: an FP32 plane of the
-// coefficients (the row factors) and two packed bf16x2 planes (hi, lo) of
-// w_p a~ (the columns), double buffered so that the global loads of the next K
-// block overlap the MFMAs of this one.
+// A block of 16 waves works on one split of primaries.  The coefficients come in
+// the blocked layout (16 primaries per block, 144 bytes per entry, weights in the
+// padding); each K block is copied as it is from global memory to LDS by direct
+// global-to-LDS loads, kStages - 1 K blocks ahead of the one in use, so the loads
+// never pass through registers and their latency hides behind three K blocks of
+// MFMAs.  Each wave forms its operands from the LDS copy: the row products (A) and
+// w_p a~ of its columns (B), both split into bf16 hi + lo.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -32,15 +34,8 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMfWaves = 16;
 constexpr int kMfThreads = kMfWaves * kWave;
-constexpr int kStageP = 16;          // primaries per K block (K = 32 = 16 x (re, im))
-constexpr int kAStride = 18;         // float2 per entry of the FP32 plane (16 + 2 pad)
-constexpr int kBStride = 20;         // bf16x2 words per entry of a bf16 plane (16 + 4 pad)
-constexpr int kStageBytesPerEntry = kAStride * 8 + 2 * kBStride * 4;
-// staging: each thread moves (entry, pair of primaries) items; consecutive threads
-// take consecutive entries, so the global reads are coalesced along a primary's
-// row and the 16-byte LDS writes of 16 consecutive lanes land in 16 distinct bank
-// slots (the entry stride is 9 slots of 16 bytes)
-constexpr int kMaxStagePairs = (kStageP / 2 * kMfmaMaxEntries + kMfThreads - 1) / kMfThreads;
+constexpr int kStages = 4;           // K blocks resident in LDS (3 in flight while one is read)
+constexpr int kEntBytes = kBlkEntFloats * 4;   // 144 bytes per entry of a block
 constexpr int kFlushSteps = 16;      // FP32 MFMA accumulation over 16 K blocks (256 primaries)
 
 __device__ __forceinline__ unsigned pack_bf16(float x0, float x1)
@@ -71,7 +66,9 @@ template <int KF, int RT, int NC, bool ODD>
 __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int stage_bytes = a.nent * kStageBytesPerEntry;
+    const int blk_b = a.ent_blk * kEntBytes;      // bytes of one K block
+    const int units = (blk_b + 1023) >> 10;       // 1 KiB copy units (64 lanes x 16 bytes)
+    const int stage_b = units << 10;
 
     // blocks of one split run on one XCD (block b is placed on XCD b % 8), so the
     // split's coefficients are shared through that XCD's L2
@@ -81,23 +78,22 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
     const int bj = li % nbj;
     if (split >= a.nsplit) return;          // uniform over the block, before any barrier
 
-    const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // uniform per wave
+    const int lane = threadIdx.x & (kWave - 1);
     const int g = lane >> 4, c16 = lane & 15;
     const int job = bj * kMfWaves + wid;
     const bool active = job < a.njobs;      // wave-uniform
 
-    int row_base = 0, col_base = 0, tile_base = 0, nrt = 0;
+    int row_base = 0, col_base = 0, tile_base = 0;
     if (active) {
         row_base = a.jobs[job * kMfmaJobWidth + 0];
         col_base = a.jobs[job * kMfmaJobWidth + 1];
         tile_base = a.jobs[job * kMfmaJobWidth + 2];
-        nrt = a.jobs[job * kMfmaJobWidth + 3];
     }
-    nrt = __builtin_amdgcn_readfirstlane(nrt);
-    // this lane's row of each row tile: byte offsets of its factor entries in the
-    // FP32 plane (entries are below kMfmaMaxEntries, offsets fit 16 bits, two per
-    // word) and flags (conjugate bits 0..3, bit 4 = Im part), 5 flag bits per row
-    // tile; padded rows and columns read entry 0, their outputs are never mapped
+    // this lane's row of each row tile: byte offsets of its factor entries in a K
+    // block (entries are below kMfmaMaxEntries, offsets fit 16 bits, two per word)
+    // and flags (conjugate bits 0..3, bit 4 = Im part), 5 flag bits per row tile;
+    // padded rows and columns read entry 0, their outputs are never mapped
     constexpr int KW = (KF + 1) / 2;
     unsigned roff[RT][KW], rfl = 0;
 #pragma unroll
@@ -108,7 +104,7 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
 #pragma unroll
         for (int k = 0; k < KF; ++k) {
             const unsigned e = active ? (unsigned)a.rows[r * (KF + 1) + k] : 0u;
-            roff[rt][k / 2] |= (e * kAStride * 8 + 32 * g) << (16 * (k & 1));
+            roff[rt][k / 2] |= (e * kEntBytes + 32 * g) << (16 * (k & 1));
         }
         const unsigned f = active ? (unsigned)a.rows[r * (KF + 1) + KF] : 0u;
         rfl |= ((f & 15u) | (((f >> 8) & 1u) << 4)) << (5 * rt);
@@ -117,7 +113,7 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
 #pragma unroll
     for (int ct = 0; ct < NC; ++ct) {
         const int c = active ? a.cols[col_base + ct * 16 + c16] : 0;
-        coff[ct] = (c < 0 ? 0 : c) * kBStride + 4 * g;
+        coff[ct] = (c < 0 ? 0 : c) * kEntBytes + 32 * g;
     }
 
     f32x4 acc[RT][NC];
@@ -131,120 +127,131 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
             for (int r = 0; r < 4; ++r) acc64[rt][ct][r] = 0.0;
         }
 
+    // K blocks [kb0, kb1) cover the split's primaries [p_lo, p_hi); primaries of a
+    // shared boundary block outside the split get weight 0 (their coefficients
+    // are finite: other rows, or the zero padding of the last block)
     const int p_lo = a.split_lo[split], p_hi = a.split_hi[split];
-    const int nstep = (p_hi - p_lo + kStageP - 1) / kStageP;
+    const int kb0 = p_lo / kBlkRows, kb1 = (p_hi + kBlkRows - 1) / kBlkRows;
+    const int nstep = p_hi > p_lo ? kb1 - kb0 : 0;
 
-    const int npair = kStageP / 2 * a.nent;   // (entry, primary pair) items per K block
-    float4 sv[kMaxStagePairs];
-    float2 sw[kMaxStagePairs];
-    auto gload = [&](int st) {
-        const int p0 = p_lo + st * kStageP;
-#pragma unroll
-        for (int q = 0; q < kMaxStagePairs; ++q) {
-            const int idx = threadIdx.x + q * kMfThreads;
-            sv[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-            sw[q] = make_float2(0.f, 0.f);
-            if (idx < npair) {
-                const int pp = idx / a.nent, e = idx - pp * a.nent;
-                const int p = p0 + 2 * pp;
-                if (p < p_hi) {
-                    const float2 v = a.alm[(size_t)p * a.nent + e];
-                    sv[q].x = v.x; sv[q].y = v.y;
-                    sw[q].x = (float)a.wprim[p];
-                }
-                if (p + 1 < p_hi) {
-                    const float2 v = a.alm[(size_t)(p + 1) * a.nent + e];
-                    sv[q].z = v.x; sv[q].w = v.y;
-                    sw[q].y = (float)a.wprim[p + 1];
-                }
-            }
+    // Copies: wave wid moves units wid, wid + 16, ... of a K block; a wave issues
+    // the same number of copies (ncp) for every K block, so "at most
+    // (kStages - 2) * ncp copies of this wave outstanding" means the copies of the
+    // K block kStages - 2 blocks back have landed.  Past the last K block the last
+    // one is copied again (into a stage nobody reads), which keeps that count.
+    const int ncp = units > wid ? (units - wid + kMfWaves - 1) / kMfWaves : 0;
+    const unsigned char* gsrc = reinterpret_cast<const unsigned char*>(a.alm);
+    auto copy_block = [&](int st) {
+        const int kb = kb0 + (st < nstep ? st : nstep - 1);
+        const unsigned char* src = gsrc + (size_t)kb * blk_b + lane * 16;
+        unsigned char* dst = smem + (size_t)(st % kStages) * stage_b;
+        for (int i = 0; i < ncp; ++i) {
+            const int u = wid + kMfWaves * i;
+            // LDS address = M0 + 16 * lane.  Issued as inline assembly: the compiler
+            // cannot tell the stages of one LDS array apart and would otherwise
+            // wait for every copy in flight before each LDS read; the waits are
+            // explicit below (wait_copies and the end of the kernel).
+            const unsigned m0 = (unsigned)(size_t)(dst + (u << 10));
+            asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                         :
+                         : "s"(m0), "v"(src + (u << 10))
+                         : "memory", "m0");
         }
     };
-    auto lstore = [&](unsigned char* buf) {
-        float2* A = reinterpret_cast<float2*>(buf);
-        unsigned* Bh = reinterpret_cast<unsigned*>(buf + (size_t)a.nent * kAStride * 8);
-        unsigned* Bl = Bh + (size_t)a.nent * kBStride;
-#pragma unroll
-        for (int q = 0; q < kMaxStagePairs; ++q) {
-            const int idx = threadIdx.x + q * kMfThreads;
-            if (idx < npair) {
-                const int pp = idx / a.nent, e = idx - pp * a.nent;
-                *reinterpret_cast<float4*>(A + e * kAStride + 2 * pp) = sv[q];
-                unsigned h0, l0, h1, l1;
-                split2(sw[q].x * sv[q].x, sw[q].x * sv[q].y, h0, l0);
-                split2(sw[q].y * sv[q].z, sw[q].y * sv[q].w, h1, l1);
-                *reinterpret_cast<uint2*>(Bh + e * kBStride + 2 * pp) = make_uint2(h0, h1);
-                *reinterpret_cast<uint2*>(Bl + e * kBStride + 2 * pp) = make_uint2(l0, l1);
-            }
+    auto wait_copies = [&]() {
+        // vmcnt <= (kStages - 2) * ncp; ncp <= 3 for blocks of <= 256 entries
+        static_assert(kStages == 4, "copy wait counts assume 4 stages");
+        switch (ncp) {
+        case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+        case 1: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
+        case 2: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+        default: asm volatile("s_waitcnt vmcnt(6)" ::: "memory"); break;
         }
     };
 
-    if (nstep > 0) {
-        gload(0);
-        lstore(smem);
-    }
-    __syncthreads();
+    if (nstep > 0)
+        for (int st = 0; st < kStages - 1; ++st) copy_block(st);
     for (int st = 0; st < nstep; ++st) {
-        unsigned char* buf = smem + (size_t)(st & 1) * stage_bytes;
-        if (st + 1 < nstep) gload(st + 1);
+        // this wave's copies of K block st have landed; after the barrier every
+        // wave's have, and every wave has finished K block st - 1, whose stage the
+        // next copy overwrites
+        wait_copies();
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        copy_block(st + kStages - 1);
         if (active) {
-            const float2* A = reinterpret_cast<const float2*>(buf);
-            const unsigned* Bh = reinterpret_cast<const unsigned*>(buf + (size_t)a.nent * kAStride * 8);
-            const unsigned* Bl = Bh + (size_t)a.nent * kBStride;
+            const unsigned char* stg = smem + (size_t)(st % kStages) * stage_b;
+            // weights of this lane's primaries 4g .. 4g+3 (padding of entry g)
+            float4 w4 = *reinterpret_cast<const float4*>(stg + g * kEntBytes + 128);
+            const int pb = (kb0 + st) * kBlkRows;
+            if (pb < p_lo || pb + kBlkRows > p_hi) {
+                const int p = pb + 4 * g;
+                w4.x = (p + 0 >= p_lo && p + 0 < p_hi) ? w4.x : 0.f;
+                w4.y = (p + 1 >= p_lo && p + 1 < p_hi) ? w4.y : 0.f;
+                w4.z = (p + 2 >= p_lo && p + 2 < p_hi) ? w4.z : 0.f;
+                w4.w = (p + 3 >= p_lo && p + 3 < p_hi) ? w4.w : 0.f;
+            }
+            // B operands: w a~ of the column entries, split into bf16 hi + lo
             u32x4 bh[NC], bl[NC];
 #pragma unroll
             for (int ct = 0; ct < NC; ++ct) {
-                bh[ct] = *reinterpret_cast<const u32x4*>(Bh + coff[ct]);
-                bl[ct] = *reinterpret_cast<const u32x4*>(Bl + coff[ct]);
+                const float4 v0 = *reinterpret_cast<const float4*>(stg + coff[ct]);
+                const float4 v1 = *reinterpret_cast<const float4*>(stg + coff[ct] + 16);
+                unsigned h, l;
+                split2(w4.x * v0.x, w4.x * v0.y, h, l); bh[ct][0] = h; bl[ct][0] = l;
+                split2(w4.y * v0.z, w4.y * v0.w, h, l); bh[ct][1] = h; bl[ct][1] = l;
+                split2(w4.z * v1.x, w4.z * v1.y, h, l); bh[ct][2] = h; bl[ct][2] = l;
+                split2(w4.w * v1.z, w4.w * v1.w, h, l); bh[ct][3] = h; bl[ct][3] = l;
             }
+            const unsigned char* A = stg;
+            // every row tile is formed, the job's invalid ones too (their rows are
+            // padding that reads entry 0 and their tiles are never mapped): without a
+            // branch per tile the compiler interleaves the tiles' LDS reads, VALU and
+            // MFMAs
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
-                if (rt < nrt) {
-                    // this lane's 4 primaries (4g .. 4g+3) of the row product
-                    float pr[4], pi[4];
-                    const unsigned fl = rfl >> (5 * rt);
-                    {
-                        const float2* src = reinterpret_cast<const float2*>(
-                            reinterpret_cast<const unsigned char*>(A) + (roff[rt][0] & 0xffffu));
-                        const float4 v0 = *reinterpret_cast<const float4*>(src);
-                        const float4 v1 = *reinterpret_cast<const float4*>(src + 2);
-                        const float s = (fl & 1u) ? -1.f : 1.f;
-                        pr[0] = v0.x; pi[0] = s * v0.y; pr[1] = v0.z; pi[1] = s * v0.w;
-                        pr[2] = v1.x; pi[2] = s * v1.y; pr[3] = v1.z; pi[3] = s * v1.w;
-                    }
+                // this lane's 4 primaries (4g .. 4g+3) of the row product
+                float pr[4], pi[4];
+                const unsigned fl = rfl >> (5 * rt);
+                {
+                    const float2* src = reinterpret_cast<const float2*>(A + (roff[rt][0] & 0xffffu));
+                    const float4 v0 = *reinterpret_cast<const float4*>(src);
+                    const float4 v1 = *reinterpret_cast<const float4*>(src + 2);
+                    const float s = (fl & 1u) ? -1.f : 1.f;
+                    pr[0] = v0.x; pi[0] = s * v0.y; pr[1] = v0.z; pi[1] = s * v0.w;
+                    pr[2] = v1.x; pi[2] = s * v1.y; pr[3] = v1.z; pi[3] = s * v1.w;
+                }
 #pragma unroll
-                    for (int k = 1; k < KF; ++k) {
-                        const float2* src = reinterpret_cast<const float2*>(
-                            reinterpret_cast<const unsigned char*>(A) + ((roff[rt][k / 2] >> (16 * (k & 1))) & 0xffffu));
-                        const float4 v0 = *reinterpret_cast<const float4*>(src);
-                        const float4 v1 = *reinterpret_cast<const float4*>(src + 2);
-                        const float s = ((fl >> k) & 1u) ? -1.f : 1.f;
-                        const float ur[4] = {v0.x, v0.z, v1.x, v1.z};
-                        const float ui[4] = {s * v0.y, s * v0.w, s * v1.y, s * v1.w};
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const float nr = pr[q] * ur[q] - pi[q] * ui[q];
-                            const float ni = pr[q] * ui[q] + pi[q] * ur[q];
-                            pr[q] = nr; pi[q] = ni;
-                        }
-                    }
-                    const bool im = ODD && ((fl >> 4) & 1u);
-                    u32x4 ah, al;
+                for (int k = 1; k < KF; ++k) {
+                    const float2* src = reinterpret_cast<const float2*>(
+                        A + ((roff[rt][k / 2] >> (16 * (k & 1))) & 0xffffu));
+                    const float4 v0 = *reinterpret_cast<const float4*>(src);
+                    const float4 v1 = *reinterpret_cast<const float4*>(src + 2);
+                    const float s = ((fl >> k) & 1u) ? -1.f : 1.f;
+                    const float ur[4] = {v0.x, v0.z, v1.x, v1.z};
+                    const float ui[4] = {s * v0.y, s * v0.w, s * v1.y, s * v1.w};
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const float x0 = ODD ? (im ? pi[q] : pr[q]) : pr[q];
-                        const float x1 = ODD ? (im ? pr[q] : -pi[q]) : -pi[q];
-                        unsigned h, l;
-                        split2(x0, x1, h, l);
-                        ah[q] = h;
-                        al[q] = l;
+                        const float nr = pr[q] * ur[q] - pi[q] * ui[q];
+                        const float ni = pr[q] * ui[q] + pi[q] * ur[q];
+                        pr[q] = nr; pi[q] = ni;
                     }
+                }
+                const bool im = ODD && ((fl >> 4) & 1u);
+                u32x4 ah, al;
 #pragma unroll
-                    for (int ct = 0; ct < NC; ++ct) {
-                        acc[rt][ct] = mfma(ah, bh[ct], acc[rt][ct]);
-                        acc[rt][ct] = mfma(ah, bl[ct], acc[rt][ct]);
-                        acc[rt][ct] = mfma(al, bh[ct], acc[rt][ct]);
-                    }
+                for (int q = 0; q < 4; ++q) {
+                    const float x0 = ODD ? (im ? pi[q] : pr[q]) : pr[q];
+                    const float x1 = ODD ? (im ? pr[q] : -pi[q]) : -pi[q];
+                    unsigned h, l;
+                    split2(x0, x1, h, l);
+                    ah[q] = h;
+                    al[q] = l;
+                }
+#pragma unroll
+                for (int ct = 0; ct < NC; ++ct) {
+                    acc[rt][ct] = mfma(ah, bh[ct], acc[rt][ct]);
+                    acc[rt][ct] = mfma(ah, bl[ct], acc[rt][ct]);
+                    acc[rt][ct] = mfma(al, bh[ct], acc[rt][ct]);
                 }
             }
             if ((st + 1) % kFlushSteps == 0 || st + 1 == nstep) {
@@ -258,9 +265,9 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
                     }
             }
         }
-        if (st + 1 < nstep) lstore(smem + (size_t)((st + 1) & 1) * stage_bytes);
-        __syncthreads();
     }
+    // no copy may still be writing LDS when the block ends
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     if (!active) return;
     // output tile layout of the 16x16 MFMA: lane holds column c16, rows 4g .. 4g+3
     double* D = a.D + (size_t)split * a.dense;
@@ -281,18 +288,67 @@ int launch_shape(const MfmaArgs& a, hipStream_t stream)
     const int64_t groups = (a.nsplit + 7) / 8;
     const int64_t blocks = groups * 8 * nbj;
     if (blocks > INT32_MAX) return (int)hipErrorInvalidValue;
-    const size_t lds = 2 * (size_t)a.nent * kStageBytesPerEntry;
+    const size_t stage_b = (blk_bytes(a.nent) + 1023) / 1024 * 1024;
+    const size_t lds = kStages * stage_b;
     auto fn = k_couple_mfma<KF, RT, NC, ODD>;
     static bool attr_set = false;
     if (!attr_set) {
+        const size_t max_lds = kStages * ((blk_bytes(kMfmaMaxEntries) + 1023) / 1024 * 1024);
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           2 * kMfmaMaxEntries * kStageBytesPerEntry);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
         if (e != hipSuccess) return (int)e;
         attr_set = true;
     }
     fn<<<dim3((unsigned)blocks), dim3(kMfThreads), lds, stream>>>(a);
     return (int)hipGetLastError();
+}
+
+// One workgroup per 16-row block: the block's rows are read along the entries
+// (coalesced), transposed through LDS and written as one contiguous block.
+constexpr int kToBlkThreads = 256;
+__global__ void __launch_bounds__(kToBlkThreads) k_to_blocked(const float2* __restrict__ alm,
+                                                              const double* __restrict__ wprim,
+                                                              const GatherSeg* __restrict__ segs, int nseg,
+                                                              int nrows, int nent, int ent_blk, float* out)
+{
+    __shared__ float2 tile[kBlkRows][kMfmaMaxEntries + 1];
+    __shared__ int valid[kBlkRows];
+    const int r0 = blockIdx.x * kBlkRows;
+    if (threadIdx.x < kBlkRows) {
+        // the row belongs to the segment with the last row0 <= row (binary search)
+        const int row = r0 + threadIdx.x;
+        int ok = 0;
+        if (row < nrows) {
+            int lo = 0, hi = nseg - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (segs[mid].row0 <= row) lo = mid; else hi = mid - 1;
+            }
+            ok = row - segs[lo].row0 < segs[lo].nprim;
+        }
+        valid[threadIdx.x] = ok;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kBlkRows * nent; i += kToBlkThreads) {
+        const int r = i / nent, e = i - r * nent;
+        tile[r][e] = valid[r] ? alm[(size_t)(r0 + r) * nent + e] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    float* ob = out + (size_t)blockIdx.x * ent_blk * kBlkEntFloats;
+    for (int i = threadIdx.x; i < ent_blk * kBlkEntFloats; i += kToBlkThreads) {
+        const int e = i / kBlkEntFloats, f = i - e * kBlkEntFloats;
+        float v = 0.f;
+        if (f < 2 * kBlkRows) {
+            if (e < nent) {
+                const float2 c = tile[f >> 1][e];
+                v = (f & 1) ? c.y : c.x;
+            }
+        } else if (e < kBlkRows / 4) {
+            const int r = 4 * e + (f - 2 * kBlkRows);
+            v = valid[r] ? (float)wprim[r0 + r] : 0.f;
+        }
+        ob[i] = v;
+    }
 }
 
 template <int KF, bool ODD>
@@ -309,12 +365,22 @@ int launch_kf(const MfmaArgs& a, int shape, hipStream_t stream)
 
 }  // namespace
 
-int mfma_stage_bytes(int nent) { return 2 * nent * kStageBytesPerEntry; }
+int launch_to_blocked(const float2* alm, const double* wprim, const GatherSeg* segs, int nseg, int nrows,
+                      int nent, float* out, hipStream_t stream)
+{
+    if (nrows <= 0) return (int)hipSuccess;
+    if (nent < 1 || nent > kMfmaMaxEntries || nseg < 1) return (int)hipErrorInvalidValue;
+    const int nblk = (nrows + kBlkRows - 1) / kBlkRows;
+    k_to_blocked<<<dim3((unsigned)nblk), dim3(kToBlkThreads), 0, stream>>>(alm, wprim, segs, nseg, nrows, nent,
+                                                                           blk_entries(nent), out);
+    return (int)hipGetLastError();
+}
 
 int launch_couple_mfma(const MfmaArgs& a, int KF, int shape, hipStream_t stream)
 {
     if (a.njobs == 0 || a.nsplit == 0) return (int)hipSuccess;
-    if (a.nent < 1 || a.nent > kMfmaMaxEntries) return (int)hipErrorInvalidValue;
+    if (a.nent < 1 || a.nent > kMfmaMaxEntries || a.ent_blk != blk_entries(a.nent))
+        return (int)hipErrorInvalidValue;
     switch (KF * 2 + (a.any_odd ? 1 : 0)) {
     case 2: return launch_kf<1, false>(a, shape, stream);
     case 3: return launch_kf<1, true>(a, shape, stream);

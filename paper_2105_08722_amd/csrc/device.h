@@ -121,9 +121,20 @@ int launch_couple(const CoupleArgs& a, int precision, hipStream_t stream);
 
 // Split-BF16 MFMA coupling (couple_mfma.hip): per split y, D[y][tile][16][16] of
 // the wave jobs of one shape (RT row tiles x NC column tiles per wave).
+// Blocked layout of the FP32 coefficients read by the MFMA coupling: rows in
+// blocks of kBlkRows; a block holds, for each entry e < ent_blk, the 16 rows'
+// complex values (16 float2) and 16 bytes of padding, so an entry spans 144 bytes
+// (16-byte LDS reads of 16 different entries then spread over the banks).  The
+// padding of entries 0..3 holds the rows' weights as FP32 (row r: entry r / 4,
+// float r % 4).  A block is copied to LDS as it is.
+constexpr int kBlkRows = 16;
+constexpr int kBlkEntFloats = 36;
+inline int blk_entries(int nent) { return nent < 4 ? 4 : nent; }
+inline size_t blk_bytes(int nent) { return (size_t)blk_entries(nent) * kBlkEntFloats * 4; }
+
 struct MfmaArgs {
-    const float2* alm;        // [nrows][nent] FP32 complex coefficients
-    const double* wprim;      // [nrows]
+    const float* alm;         // blocked coefficients and weights of the slice rows
+    int ent_blk;              // entries per block (blk_entries(nent))
     int nent;
     const int32_t* rows;      // [.][KF + 1]: factor entries, flags
     const int32_t* cols;      // [.]: entry of the last factor (-1: padding)
@@ -137,7 +148,11 @@ struct MfmaArgs {
     int any_odd;              // some rows take the Im part (all-parity multiplets)
 };
 int launch_couple_mfma(const MfmaArgs& a, int KF, int shape, hipStream_t stream);
-int mfma_stage_bytes(int nent);
+// Row-major FP32 coefficients ([nrows][nent] complex) and weights -> blocked layout
+// (out: ceil(nrows / 16) blocks); rows outside every segment's [row0, row0 + nprim)
+// and past nrows become zero with weight zero.
+int launch_to_blocked(const float2* alm, const double* wprim, const GatherSeg* segs, int nseg, int nrows,
+                      int nent, float* out, hipStream_t stream);
 // rows per split that keep the coupling kernels' blocks busy
 int couple_split_rows(int nk, int nbins, int64_t ntuple, int64_t nB, int64_t nrows);
 int couple_ptile(int nbins, int nlm, int precision);

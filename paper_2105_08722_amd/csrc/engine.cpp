@@ -45,7 +45,7 @@ int ensure(Buf& b, size_t bytes)
 static Buf* exec_bufs(Exec& x, int i)
 {
     Buf* all[] = {&x.alm, &x.wprim, &x.T, &x.segs, &x.splits, &x.redp, &x.queues,
-                  &x.misc, &x.zeta, &x.bscale, &x.prim, &x.Tjob};
+                  &x.misc, &x.zeta, &x.bscale, &x.prim, &x.Tjob, &x.almb};
     return i < (int)(sizeof(all) / sizeof(all[0])) ? all[i] : nullptr;
 }
 
@@ -273,8 +273,9 @@ int64_t job_split_rows(const NpcfPlan& pl, const DevTables* tb, int64_t nprim, i
         int64_t nbj = 0;
         for (int sh = 0; sh < kNumMfmaShapes; ++sh) nbj += (tb->mf_njobs[sh] + 15) / 16;
         const int64_t ns = std::max<int64_t>(1, std::min<int64_t>(1024, 2048 / std::max<int64_t>(nbj, 1)));
-        const int64_t rows = std::max<int64_t>(256, (std::max<int64_t>(nprim, 1) + ns - 1) / ns);
-        return std::min<int64_t>(cap, rows);
+        int64_t rows = std::max<int64_t>(256, (std::max<int64_t>(nprim, 1) + ns - 1) / ns);
+        rows = std::min<int64_t>(cap, rows);
+        return std::max<int64_t>(kBlkRows, rows / kBlkRows * kBlkRows);   // whole K blocks
     }
     return std::min<int64_t>(
         cap, couple_split_rows(pl.N - 1, pl.nbins, tb->ntuple, tb->nB, std::max<int64_t>(nprim, 1)));
@@ -290,9 +291,15 @@ int prepare_slice(Exec& x, Buf& segs, Buf& splits, Buf& redp, const NpcfPlan& pl
     std::vector<int32_t> slo, shi, rlo, rhi;
     std::vector<double*> rdst;
     int64_t rows = 0;
+    // The MFMA coupling's K blocks are whole 16-row blocks of the blocked layout;
+    // each job starts on a block so that its blocks, and so its FP32 sums, are the
+    // same as when it runs alone.  Rows between jobs are skipped by the gather and
+    // zero in the blocked copy.
+    const bool blocked = pl.prec == 2;
     for (const Chunk& c : chunks) {
         const int64_t take = c.r1 - c.r0;
         if (take <= 0) continue;
+        if (blocked) rows = (rows + kBlkRows - 1) / kBlkRows * kBlkRows;
         const DevGrid& g = *c.g;
         GatherSeg gs;
         gs.P = g.P; gs.cell_start = g.cell_start; gs.prim = c.prim + c.r0;
@@ -319,6 +326,11 @@ int prepare_slice(Exec& x, Buf& segs, Buf& splits, Buf& redp, const NpcfPlan& pl
     const int nsplit = (int)slo.size(), nred = (int)rlo.size();
     int rc;
     if ((rc = ensure(x.alm, alm_row_bytes(pl) * (size_t)rows))) return rc;
+    // the MFMA coupling reads a blocked copy: whole 16-row blocks, plus 1 KiB that
+    // its 1 KiB copy units may read past the last block
+    const int ent_blk = blk_entries(tb->mf_nent);
+    const int64_t nblk = (rows + kBlkRows - 1) / kBlkRows;
+    if (blocked && (rc = ensure(x.almb, (size_t)nblk * blk_bytes(tb->mf_nent) + 1024))) return rc;
     if ((rc = ensure(x.wprim, sizeof(double) * (size_t)rows))) return rc;
     if ((rc = ensure(x.T, sizeof(double) * (size_t)nsplit * (size_t)outs))) return rc;
     if ((rc = ensure(segs, sizeof(GatherSeg) * hsegs.size()))) return rc;
@@ -367,8 +379,8 @@ int prepare_slice(Exec& x, Buf& segs, Buf& splits, Buf& redp, const NpcfPlan& pl
 
     MfmaArgs& ma = L.ma;
     memset(&ma, 0, sizeof(ma));
-    ma.alm = (const float2*)x.alm.p;
-    ma.wprim = (const double*)x.wprim.p;
+    ma.alm = (const float*)x.almb.p;
+    ma.ent_blk = ent_blk;
     ma.nent = tb->mf_nent;
     ma.rows = tb->mf_rows;
     ma.cols = tb->mf_cols;
@@ -400,6 +412,8 @@ int launch_slice_couple(const SliceLaunch& L, const NpcfPlan& pl, const DevTable
 {
     if (L.rows == 0) return ENCORE_OK;
     if (pl.prec == 2) {
+        HIPTRY((hipError_t)launch_to_blocked((const float2*)L.ga.alm, L.ga.wprim, L.ga.segs, L.ga.nseg,
+                                             (int)L.rows, L.ma.nent, (float*)L.ma.alm, s));
         MfmaArgs ma = L.ma;
         for (int sh = 0; sh < kNumMfmaShapes; ++sh) {
             ma.jobs = tb->mf_jobs[sh];

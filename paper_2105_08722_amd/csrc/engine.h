@@ -55,7 +55,7 @@ struct Buf {
 // One stream and the workspaces of the hot path on it.
 struct Exec {
     hipStream_t s = nullptr;
-    Buf alm, wprim, T, segs, splits, redp, queues, misc, zeta, bscale, prim, Tjob;
+    Buf alm, wprim, T, segs, splits, redp, queues, misc, zeta, bscale, prim, Tjob, almb;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 int exec_init(Exec& x);

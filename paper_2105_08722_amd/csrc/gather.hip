@@ -464,6 +464,10 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         if (uni(a.segs[mid].row0) <= row) slo = mid; else shi = mid - 1;
     }
     const GatherSeg g = load_seg(a.segs, uni(slo));
+    if (row - g.row0 >= g.nprim) {   // a row between jobs (see prepare_slice): no primary
+        item = a.queues ? pop() : -1;
+        continue;
+    }
     const gptr<double4> gP = as_global(g.P);
     const gptr<int32_t> gcs = as_global(g.cell_start);
     const int ip = uni(g.prim[row - g.row0]);
