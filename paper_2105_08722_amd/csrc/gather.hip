@@ -114,6 +114,28 @@ struct GammaTable {
 };
 template <int L> struct Gamma { static constexpr GammaTable<L> t{}; };
 
+// Final scales kappa_lm of the recurrence (the values gather_tables computes):
+// kappa_mm = (-1)^m c_m, c_0 = 1/sqrt(4 pi), c_m = c_{m-1} sqrt((2m+1)/(2m)),
+// kappa_{m+1,m} = sqrt(2m+3) kappa_mm, kappa_lm = a_lm kappa_{l-1,m} (l >= m+2).
+template <int L>
+struct KappaTable {
+    double v[nlm_of(L)];
+    constexpr KappaTable() : v{}
+    {
+        double c = 1.0 / ce_sqrt(4.0 * 3.14159265358979323846);
+        for (int m = 0; m <= L; ++m) {
+            if (m > 0) c *= ce_sqrt((2.0 * m + 1.0) / (2.0 * m));
+            const double kmm = (m % 2) ? -c : c;
+            v[lm_index(m, m)] = kmm;
+            if (m + 1 <= L) v[lm_index(m + 1, m)] = ce_sqrt(2.0 * m + 3.0) * kmm;
+            for (int l = m + 2; l <= L; ++l)
+                v[lm_index(l, m)] = ce_sqrt((4.0 * l * l - 1.0) / ((double)l * l - (double)m * m)) *
+                                    v[lm_index(l - 1, m)];
+        }
+    }
+};
+template <int L> struct Kappa { static constexpr KappaTable<L> t{}; };
+
 // Add w*Y_lm for m in [M0, M1] of one pair into acc (layout [lm][re, im]).
 template <typename T, int L, int M0, int M1>
 __device__ __forceinline__ void accum_pair(T dx, T dy, T dz, T w, T (&acc)[nlm_of(L)][2])
@@ -400,10 +422,11 @@ template <typename T, int L, int NBG, int M0, int M1>
 __host__ __device__ constexpr int gather_wpe()
 {
     constexpr int acc = NBG * ((L + 1) * (L + 1)) * (int)(sizeof(T) / 4);
-    return acc <= 48 ? 5 : (acc <= 72 ? 4 : 2);
+    return acc <= 72 ? 4 : 2;
 }
 
-template <typename T, int L, int NBG, int M0, int M1>
+// PERS: persistent grid (work items pulled from queues); otherwise one item per wave
+template <typename T, int L, int NBG, int M0, int M1, bool PERS>
 __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG, M0, M1>())) k_gather(GatherArgs a)
 {
     using E = typename Entry<T>::type;
@@ -440,23 +463,15 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         }
         return -1;
     };
-    int64_t item;
-    if (a.queues) {
-        item = pop();
-    } else {
-        const int nblk = gridDim.x;
-        const int bid = (blockIdx.x % 8) * (nblk / 8) + blockIdx.x / 8;
-        item = (int64_t)bid * kWavesPerBlock + wib;
-    }
-    while (item >= 0 && item < nitems) {
+    // One work item.  The persistent kernel calls it in a loop, the static kernel
+    // once: there nothing is hoisted out of an item loop, which keeps values that
+    // only the end of the item needs out of the registers of its hot loop.
+    auto work = [&](const int64_t item) __attribute__((always_inline)) {
     const int64_t quad = item / kWavesPerBlock;
     const int64_t rblk = quad / a.ngroups;
     const int grp = uni((int)(quad - rblk * a.ngroups));
     const int row = uni((int)(rblk * kWavesPerBlock + (item - quad * kWavesPerBlock)));
-    if (row >= a.nrows) {   // ragged last row block
-        item = a.queues ? pop() : -1;
-        continue;
-    }
+    if (row >= a.nrows) return;   // ragged last row block
     // segment (catalog) of this row: binary search over the segments' first rows
     int slo = 0, shi = a.nseg - 1;
     while (slo < shi) {
@@ -464,10 +479,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         if (uni(a.segs[mid].row0) <= row) slo = mid; else shi = mid - 1;
     }
     const GatherSeg g = load_seg(a.segs, uni(slo));
-    if (row - g.row0 >= g.nprim) {   // a row between jobs (see prepare_slice): no primary
-        item = a.queues ? pop() : -1;
-        continue;
-    }
+    if (row - g.row0 >= g.nprim) return;   // a row between jobs (see prepare_slice): no primary
     const gptr<double4> gP = as_global(g.P);
     const gptr<int32_t> gcs = as_global(g.cell_start);
     const int ip = uni(g.prim[row - g.row0]);
@@ -752,10 +764,6 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
             x += __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(x), 0x121, 0xf, 0xf, false));
             c[q] = x;
         }
-        // the recurrence scales through LDS (the rings are idle now)
-        double* kap = reinterpret_cast<double*>(scratch);
-        for (int q = lane; q < NLM; q += kWave) kap[q] = a.kappa[q];
-        wave_sync();
         const int rrow = lane >> 4;
         const int sub = (rrow == 1) ? 2 : (rrow == 2 ? 1 : rrow);
         if ((lane & 15) == 0) {
@@ -768,8 +776,8 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
                 const int lmA = (2 * q) % NLM, lmB = (2 * q + 1) % NLM;
                 const bool inA = m_of_lm(lmA) >= M0 && m_of_lm(lmA) <= M1;
                 const bool inB = m_of_lm(lmB) >= M0 && m_of_lm(lmB) <= M1;
-                const int lm = hi ? lmB : lmA;
-                if (vi < nvalid && (hi ? inB : inA)) out[vi] = (T)((double)c[q] * kap[lm]);
+                const double ks = hi ? Kappa<L>::t.v[lmB] : Kappa<L>::t.v[lmA];
+                if (vi < nvalid && (hi ? inB : inA)) out[vi] = (T)((double)c[q] * ks);
             }
         }
         wave_sync();
@@ -795,14 +803,21 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
 #pragma unroll
                     for (int l2 = 0; l2 < kWave; ++l2) s8[l2 & 7] += (double)scratch[lane * 65 + l2];
                     const double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
-                    out[v] = (T)(s * a.kappa[lm]);
+                    out[v] = (T)(s * Kappa<L>::t.v[lm]);
                 }
             }
             wave_sync();
         }
     }
     wave_sync();
-    item = a.queues ? pop() : -1;
+    };
+    if constexpr (PERS) {
+        for (int64_t item = pop(); item >= 0 && item < nitems; item = pop()) work(item);
+    } else {
+        const int nblk = gridDim.x;
+        const int bid = (blockIdx.x % 8) * (nblk / 8) + blockIdx.x / 8;
+        const int64_t item = (int64_t)bid * kWavesPerBlock + wib;
+        if (item < nitems) work(item);
     }
 }
 
@@ -812,18 +827,20 @@ struct KernelCfg {
     int nbg;
     int nm;                 // number of m groups
     int m0[2], m1[2];
-    const void* fn[2];
+    const void* fn[2];      // static grid
+    const void* fnp[2];     // persistent grid
     int lds;                // bytes per block
 };
 
-template <typename T, int L, int NBG, int M0, int M1>
-const void* kfn() { return reinterpret_cast<const void*>(&k_gather<T, L, NBG, M0, M1>); }
+template <typename T, int L, int NBG, int M0, int M1, bool PERS>
+const void* kfn() { return reinterpret_cast<const void*>(&k_gather<T, L, NBG, M0, M1, PERS>); }
 
 template <typename T, int L, int NBG>
 KernelCfg cfg1()
 {
     KernelCfg c{};
-    c.nbg = NBG; c.nm = 1; c.m0[0] = 0; c.m1[0] = L; c.fn[0] = kfn<T, L, NBG, 0, L>();
+    c.nbg = NBG; c.nm = 1; c.m0[0] = 0; c.m1[0] = L;
+    c.fn[0] = kfn<T, L, NBG, 0, L, false>(); c.fnp[0] = kfn<T, L, NBG, 0, L, true>();
     c.lds = kWavesPerBlock * wave_lds_bytes<T, NBG>();
     return c;
 }
@@ -832,8 +849,10 @@ KernelCfg cfg2()
 {
     KernelCfg c{};
     c.nbg = NBG; c.nm = 2;
-    c.m0[0] = 0; c.m1[0] = MS - 1; c.fn[0] = kfn<T, L, NBG, 0, MS - 1>();
-    c.m0[1] = MS; c.m1[1] = L; c.fn[1] = kfn<T, L, NBG, MS, L>();
+    c.m0[0] = 0; c.m1[0] = MS - 1;
+    c.fn[0] = kfn<T, L, NBG, 0, MS - 1, false>(); c.fnp[0] = kfn<T, L, NBG, 0, MS - 1, true>();
+    c.m0[1] = MS; c.m1[1] = L;
+    c.fn[1] = kfn<T, L, NBG, MS, L, false>(); c.fnp[1] = kfn<T, L, NBG, MS, L, true>();
     c.lds = kWavesPerBlock * wave_lds_bytes<T, NBG>();
     return c;
 }
@@ -931,6 +950,7 @@ int launch_gather(const GatherArgs& a0, int lmax, int precision, int nbg, bool p
     const int64_t quads = ((int64_t)a.nrows + kWavesPerBlock - 1) / kWavesPerBlock * a.ngroups;
     if (quads == 0) return (int)hipSuccess;
     for (int g = 0; g < c.nm; ++g) {
+        const void* fn = persistent ? c.fnp[g] : c.fn[g];
         int64_t blocks;
         if (persistent) {
             // one block per resident block slot
@@ -939,7 +959,7 @@ int launch_gather(const GatherArgs& a0, int lmax, int precision, int nbg, bool p
             hipError_t e = hipGetDevice(&dev);
             if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
             if (e == hipSuccess)
-                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c.fn[g], kWave * kWavesPerBlock,
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kWave * kWavesPerBlock,
                                                                  (size_t)c.lds);
             if (e != hipSuccess) return (int)e;
             blocks = std::max(1, per_cu) * (int64_t)prop.multiProcessorCount;
@@ -953,14 +973,14 @@ int launch_gather(const GatherArgs& a0, int lmax, int precision, int nbg, bool p
         if (blocks > INT32_MAX) return (int)hipErrorInvalidValue;
         if (c.lds > 65536) {   // blocks above 64 KiB of LDS need the limit raised once
             static thread_local std::vector<const void*> raised;
-            if (std::find(raised.begin(), raised.end(), c.fn[g]) == raised.end()) {
-                const hipError_t e = hipFuncSetAttribute(c.fn[g], hipFuncAttributeMaxDynamicSharedMemorySize, c.lds);
+            if (std::find(raised.begin(), raised.end(), fn) == raised.end()) {
+                const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, c.lds);
                 if (e != hipSuccess) return (int)e;
-                raised.push_back(c.fn[g]);
+                raised.push_back(fn);
             }
         }
         void* args[] = {&a};
-        hipError_t e = hipLaunchKernel(c.fn[g], dim3((unsigned)blocks), dim3(kWave * kWavesPerBlock),
+        hipError_t e = hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(kWave * kWavesPerBlock),
                                        args, (size_t)c.lds, stream);
         if (e != hipSuccess) return (int)e;
     }
