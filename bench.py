@@ -75,7 +75,7 @@ def cpu_baseline(cfg, target_s):
     n = len(w)
     rng = np.random.default_rng(99)
     cores = os.cpu_count() or 1
-    probe = rng.choice(n, 8 * cores, replace=False)
+    probe = rng.choice(n, 16 * cores, replace=False)
     t0 = time.perf_counter()
     oracle.zeta(cfg["pos"], w, 4, 5, cfg["edges"], box=cfg["box"], primaries=probe, nthreads=cores)
     dt = time.perf_counter() - t0
@@ -178,7 +178,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="splitbf16", choices=["fp32", "fp64", "splitbf16"])
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-tune", action="store_true")

@@ -347,7 +347,10 @@ int prepare_slice(Exec& x, Buf& segs, Buf& splits, Buf& redp, const NpcfPlan& pl
     HIPTRY(hipMemcpyAsync(splits.p, hsplit.data(), sizeof(int32_t) * hsplit.size(), hipMemcpyHostToDevice, s));
     HIPTRY(hipMemcpyAsync(redp.p, rdst.data(), sizeof(double*) * rdst.size(), hipMemcpyHostToDevice, s));
     const int32_t* dsp = (const int32_t*)splits.p;
-    L.persistent = hsegs.size() > 1 || getenv("ENCORE_GATHER_PERSISTENT") != nullptr;
+    // several catalogs: the persistent grid (work stealing across XCD queues) unless
+    // ENCORE_GATHER_PERSISTENT says otherwise (0: static grid, 1: always persistent)
+    L.persistent = hsegs.size() > 1;
+    if (const char* e = getenv("ENCORE_GATHER_PERSISTENT")) L.persistent = atoi(e) != 0;
 
     GatherArgs& ga = L.ga;
     memset(&ga, 0, sizeof(ga));

@@ -468,7 +468,8 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
     // only the end of the item needs out of the registers of its hot loop.
     auto work = [&](const int64_t item) __attribute__((always_inline)) {
     const int64_t quad = item / kWavesPerBlock;
-    const int64_t rblk = quad / a.ngroups;
+    // 32-bit division when the quads fit (always, below 2^31 work items)
+    const int64_t rblk = quad <= INT32_MAX ? (int64_t)((unsigned)quad / (unsigned)a.ngroups) : quad / a.ngroups;
     const int grp = uni((int)(quad - rblk * a.ngroups));
     const int row = uni((int)(rblk * kWavesPerBlock + (item - quad * kWavesPerBlock)));
     if (row >= a.nrows) return;   // ragged last row block
