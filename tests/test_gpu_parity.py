@@ -146,6 +146,27 @@ def test_zeta_matches_oracle(ctx, N, lmax, npts, nbins, periodic, allp, precisio
         assert np.all(_normwise(zg, zo) <= 1e-5 * np.maximum(kappa, 1.0) + 1e-5)
 
 
+@pytest.mark.parametrize("N,lmax,nbins,npts", [(3, 0, 1, 37), (3, 1, 2, 300), (4, 0, 3, 1), (4, 1, 3, 17)])
+def test_splitbf16_smallest_blocks(ctx, N, lmax, nbins, npts):
+    """Split-bf16 with the fewest coefficients per primary (one 16-row block holds
+    fewer entries than its weight slots) and row counts that leave a partial last
+    block: equal to the oracle to the split-bf16 bar."""
+    _say("split-bf16 small blocks N=%d lmax=%d nbins=%d n=%d" % (N, lmax, nbins, npts))
+    L = 40.0
+    pos, w = _uniform(npts, L, 7 * N + lmax + nbins)
+    edges = np.linspace(4.0, 19.0, nbins + 1)
+    with encore.build_grid(ctx, pos, w, r_max=edges[-1], box=L) as g:
+        zg = encore.npcf(ctx, g, N, lmax, edges, precision="splitbf16")
+    zo, za = oracle.zeta(pos, w, N, lmax, edges, box=L, return_abs=True)
+    assert zg.shape == zo.shape
+    if zo.size == 0:
+        return
+    scale = max(np.max(np.abs(zo)), 1e-300)
+    kappa = np.linalg.norm(za, axis=1) / np.maximum(np.linalg.norm(zo, axis=1), 1e-300)
+    assert np.max(np.abs(zg - zo)) <= 5e-5 * scale
+    assert np.all(_normwise(zg, zo) <= 1e-5 * np.maximum(kappa, 1.0) + 1e-5)
+
+
 def test_dmr_weights_and_subset(ctx):
     _say("D-R weighting + primary subset")
     rng = np.random.default_rng(44)
