@@ -324,6 +324,31 @@ int encore_debug_alm(encore_ctx* ctx, const encore_grid* grid, int lmax, int nbi
                      const double* edges, uint32_t flags, const int64_t* primaries, int64_t k,
                      double* alm_out);
 
+/*
+ * Edge correction (Section 3.2, eqs. edge-correction-matrix and
+ * edge-corrected-NPCF).  From the multiplets N_L^B of the data-minus-randoms field
+ * and R_L^B of the randoms alone (both as encore_npcf returns them, same flags),
+ * builds per bin tuple B the coupling matrix
+ *     M_{L L''}(B) = sum_{L'} (R_{L'}^B / R_0^B) E(L'') G^{L L' L''}
+ * with the generalized Gaunt integrals G of eq. generalized-gaunt-def (closed forms
+ * of Appendix A: N = 3, 4, 5), and solves N_{L''}^B / R_0^B = sum_L zeta_L^B M_{L L''}
+ * for zeta on the device (FP64, Gauss-Jordan elimination with partial pivoting).
+ * L, L', L'' run over the multiplets of (npcf, lmax, flags & ENCORE_ALLPARITY);
+ * zeta is returned for those with every principal ell <= lmax_out (the paper
+ * measures at lmax_out + 1), in the same order.
+ *  nmult, rmult  host FP64 [nlam][nB] (encore_num_multiplets x the bin tuples),
+ *                mult_len elements each; row 0 of rmult is R_0.
+ *  zeta          host FP64 [nout][nB]; B with R_0 = 0 or a singular matrix get NaN.
+ *  coupling      NULL or host FP64 [nB][nlam][nlam]: M[B][L][L''].
+ *  n_singular    NULL or the number of B without a solution.
+ * Errors: EINVAL, ESIZE (a buffer too small; the message gives the size),
+ * EUNSUPPORTED (npcf = 6), ENOMEM, EDEVICE.
+ */
+int encore_edge_correct(encore_ctx* ctx, int npcf, int lmax, int nbins, uint32_t flags,
+                        const double* nmult, const double* rmult, size_t mult_len, int lmax_out,
+                        double* zeta, size_t zeta_len, double* coupling, size_t coupling_len,
+                        int64_t* n_singular);
+
 /* Timings (milliseconds, HIP events on the work stream) of the last encore_npcf
  * call on this context: [0] total, [1] gather, [2] coupling, [3] reduce/contract,
  * [4] number of gather launches, [5] number of accepted (primary, secondary) pairs.

@@ -148,6 +148,25 @@ struct MfmaArgs {
     int any_odd;              // some rows take the Im part (all-parity multiplets)
 };
 int launch_couple_mfma(const MfmaArgs& a, int KF, int shape, hipStream_t stream);
+
+// Edge correction (one workgroup per bin tuple B): builds the coupling matrix from
+// the Gaunt terms and the random multiplets, solves for zeta (NaN for B with R_0 = 0
+// or a singular matrix, counted in *nbad).
+struct EdgeArgs {
+    int nlam, nB, nout;
+    const double* nmult;        // [nlam][nB] data-minus-random multiplets
+    const double* rmult;        // [nlam][nB] random multiplets (row 0: L = 0)
+    const int64_t* row_start;   // [nlam * nlam + 1] terms of entry (L, L'')
+    const int32_t* term_lp;     // L'
+    const double* term_val;     // E(L'') G^{L L' L''}
+    double* A;                  // workspace [nB][nlam][nlam]
+    double* rhs;                // workspace [nB][nlam]
+    const int32_t* keep;        // [nout] output multiplets (indices into the list)
+    double* zeta;               // [nout][nB]
+    double* M_out;              // optional [nB][nlam][nlam], M[L][L'']
+    unsigned* nbad;             // += number of B without a solution
+};
+int launch_edge(const EdgeArgs& a, hipStream_t stream);
 // Row-major FP32 coefficients ([nrows][nent] complex) and weights -> blocked layout
 // (out: ceil(nrows / 16) blocks); rows outside every segment's [row0, row0 + nprim)
 // and past nrows become zero with weight zero.

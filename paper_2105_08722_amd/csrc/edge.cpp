@@ -1,0 +1,262 @@
+// Edge correction (Section 3.2, eqs. edge-correction-matrix and
+// edge-corrected-NPCF): host side.
+//
+// The generalized Gaunt integrals G^{L L' L''} (eq. generalized-gaunt-def) come
+// from the closed forms of Appendix A (N = 3, 4, 5): products over the N-1
+// directions of sqrt((2l+1)(2l'+1)(2l''+1)) (l l' l''; 0 0 0), times one 9j symbol
+// for N = 4 and two (with the sqrt((2l12+1)(2l12'+1)(2l12''+1)) factor of the
+// intermediates) for N = 5, over (4 pi)^{(N-1)/2}; for N = 3 the single 3j symbol is
+// squared over 4 pi.  6j symbols by Racah's single sum (DLMF 34.4.3) and 9j symbols
+// by the sum of 6j products (DLMF 34.6.2), in long double.
+//
+// The device builds M_{L L''}(B) = sum_{L'} f_{L'}(B) E(L'') G^{L L' L''} from a
+// list of the nonzero (L, L'') x L' terms grouped by (L, L'') (so each entry is a
+// fixed-order sum) and solves the per-B linear system of eq. edge-correction-matrix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "engine.h"
+
+namespace encore {
+
+namespace {
+
+long double lfact(int n)
+{
+    static long double table[256];
+    static std::once_flag once;
+    std::call_once(once, [] {
+        table[0] = 1.0L;
+        for (int i = 1; i < 256; ++i) table[i] = table[i - 1] * (long double)i;
+    });
+    return table[n];
+}
+
+bool tri(int a, int b, int c) { return c >= std::abs(a - b) && c <= a + b; }
+
+long double delta_sq(int a, int b, int c)
+{
+    return lfact(a + b - c) * lfact(a - b + c) * lfact(-a + b + c) / lfact(a + b + c + 1);
+}
+
+long double sixj(int j1, int j2, int j3, int j4, int j5, int j6)
+{
+    if (!tri(j1, j2, j3) || !tri(j1, j5, j6) || !tri(j4, j2, j6) || !tri(j4, j5, j3)) return 0.0L;
+    const int a[4] = {j1 + j2 + j3, j1 + j5 + j6, j4 + j2 + j6, j4 + j5 + j3};
+    const int b[3] = {j1 + j2 + j4 + j5, j2 + j3 + j5 + j6, j3 + j1 + j6 + j4};
+    const int tlo = std::max({a[0], a[1], a[2], a[3]}), thi = std::min({b[0], b[1], b[2]});
+    long double s = 0.0L;
+    for (int t = tlo; t <= thi; ++t) {
+        long double den = 1.0L;
+        for (int x : a) den *= lfact(t - x);
+        for (int y : b) den *= lfact(y - t);
+        s += ((t & 1) ? -1.0L : 1.0L) * lfact(t + 1) / den;
+    }
+    return s * std::sqrt(delta_sq(j1, j2, j3) * delta_sq(j1, j5, j6) * delta_sq(j4, j2, j6) *
+                         delta_sq(j4, j5, j3));
+}
+
+long double ninej(int j1, int j2, int j3, int j4, int j5, int j6, int j7, int j8, int j9)
+{
+    const int lo = std::max({std::abs(j1 - j9), std::abs(j4 - j8), std::abs(j2 - j6)});
+    const int hi = std::min({j1 + j9, j4 + j8, j2 + j6});
+    long double s = 0.0L;
+    for (int x = lo; x <= hi; ++x)
+        s += (2 * x + 1) * sixj(j1, j4, j7, j8, j9, x) * sixj(j2, j5, j8, j4, x, j6) * sixj(j3, j6, j9, x, j1, j2);
+    return s;
+}
+
+// G^{L L' L''} from Appendix A; rows in the multiplet layout of enumerate_multiplets
+double gaunt(int N, const int32_t* a, const int32_t* b, const int32_t* c)
+{
+    int la[5], lb[5], lc[5];
+    principal_of(N, a, la);
+    principal_of(N, b, lb);
+    principal_of(N, c, lc);
+    long double p = 1.0L;
+    for (int i = 0; i < N - 1; ++i) {
+        if ((la[i] + lb[i] + lc[i]) & 1) return 0.0;   // (l l' l''; 0 0 0) = 0
+        if (!tri(la[i], lb[i], lc[i])) return 0.0;
+        const double w = wigner3j(la[i], lb[i], lc[i], 0, 0, 0);
+        if (w == 0.0) return 0.0;
+        p *= std::sqrt((long double)(2 * la[i] + 1) * (2 * lb[i] + 1) * (2 * lc[i] + 1)) * (long double)w;
+    }
+    const long double fourpi = 4.0L * 3.14159265358979323846264338327950288L;
+    if (N == 3) {   // single direction pair {l, l}: the 3j symbol squared
+        const long double w = wigner3j(la[0], lb[0], lc[0], 0, 0, 0);
+        return (double)(std::sqrt((long double)(2 * la[0] + 1) * (2 * lb[0] + 1) * (2 * lc[0] + 1)) * w * w /
+                        fourpi);
+    }
+    if (N == 4)
+        return (double)(p / std::pow(fourpi, 1.5L) *
+                        ninej(la[0], lb[0], lc[0], la[1], lb[1], lc[1], la[2], lb[2], lc[2]));
+    // N == 5: intermediates l12 at row index 2
+    const int a12 = a[2], b12 = b[2], c12 = c[2];
+    return (double)(p / (fourpi * fourpi) *
+                    std::sqrt((long double)(2 * a12 + 1) * (2 * b12 + 1) * (2 * c12 + 1)) *
+                    ninej(la[0], la[1], a12, lb[0], lb[1], b12, lc[0], lc[1], c12) *
+                    ninej(a12, la[2], la[3], b12, lb[2], lb[3], c12, lc[2], lc[3]));
+}
+
+}  // namespace
+
+const GauntTable& gaunt_table(int N, int lmax, bool allparity)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, bool>, std::unique_ptr<GauntTable>> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    const auto key = std::make_tuple(N, lmax, allparity);
+    auto it = cache.find(key);
+    if (it != cache.end()) return *it->second;
+    auto t = std::make_unique<GauntTable>();
+    const std::vector<int32_t> lam = enumerate_multiplets(N, lmax, allparity);
+    const int W = multiplet_width(N);
+    const int n = (int)(lam.size() / W);
+    t->nlam = n;
+    t->lam = lam;
+    std::vector<int> E(n);
+    for (int i = 0; i < n; ++i) {
+        int ls[5];
+        principal_of(N, &lam[(size_t)i * W], ls);
+        int s = 0;
+        for (int k = 0; k < N - 1; ++k) s += ls[k];
+        E[i] = (s & 1) ? -1 : 1;
+    }
+    t->row_start.assign((size_t)n * n + 1, 0);
+    // entry (L = a, L'' = c) -> terms over L' = b, in increasing b
+    for (int a = 0; a < n; ++a)
+        for (int c = 0; c < n; ++c) {
+            for (int b = 0; b < n; ++b) {
+                const double g = gaunt(N, &lam[(size_t)a * W], &lam[(size_t)b * W], &lam[(size_t)c * W]);
+                if (g != 0.0) {
+                    t->term_lp.push_back(b);
+                    t->term_val.push_back(E[c] * g);
+                }
+            }
+            t->row_start[(size_t)a * n + c + 1] = (int64_t)t->term_lp.size();
+        }
+    auto* out = t.get();
+    cache.emplace(key, std::move(t));
+    return *out;
+}
+
+}  // namespace encore
+
+using namespace encore;
+
+namespace {
+
+struct DevBufs {
+    std::vector<void*> p;
+    ~DevBufs()
+    {
+        for (void* q : p)
+            if (q) (void)hipFree(q);
+    }
+    template <typename T>
+    int get(T** out, size_t n)
+    {
+        void* q = nullptr;
+        const hipError_t e = hipMalloc(&q, sizeof(T) * std::max<size_t>(n, 1));
+        if (e != hipSuccess) return fail(ENCORE_ENOMEM, "hipMalloc (edge correction workspace)");
+        p.push_back(q);
+        *out = (T*)q;
+        return ENCORE_OK;
+    }
+};
+
+}  // namespace
+
+extern "C" int encore_edge_correct(encore_ctx* ctx, int npcf, int lmax, int nbins, uint32_t flags,
+                                   const double* nmult, const double* rmult, size_t mult_len, int lmax_out,
+                                   double* zeta, size_t zeta_len, double* coupling, size_t coupling_len,
+                                   int64_t* n_singular)
+{
+    if (!ctx) return fail(ENCORE_EINVAL, "ctx is NULL");
+    if (npcf < 3 || npcf > 6) return fail(ENCORE_EINVAL, "npcf must be 3..6");
+    if (npcf == 6)
+        return fail(ENCORE_EUNSUPPORTED, "edge correction: generalized Gaunt integrals are built for N = 3, 4, 5");
+    if (lmax < 0 || lmax > kMaxLmax) return fail(ENCORE_EINVAL, "lmax must be 0..10");
+    if (lmax_out < 0 || lmax_out > lmax) return fail(ENCORE_EINVAL, "lmax_out must be 0..lmax");
+    if (nbins < 1 || nbins > kMaxBins) return fail(ENCORE_EINVAL, "nbins must be 1..16");
+    if (!nmult || !rmult || !zeta) return fail(ENCORE_EINVAL, "NULL multiplets or zeta");
+    const bool allp = flags & ENCORE_ALLPARITY;
+    const GauntTable& gt = gaunt_table(npcf, lmax, allp);
+    const int n = gt.nlam;
+    const int64_t nB = binomial(nbins, npcf - 1);
+    const int W = multiplet_width(npcf);
+    std::vector<int32_t> keep;
+    for (int i = 0; i < n; ++i) {
+        int ls[5];
+        principal_of(npcf, &gt.lam[(size_t)i * W], ls);
+        if (*std::max_element(ls, ls + npcf - 1) <= lmax_out) keep.push_back(i);
+    }
+    const int nout = (int)keep.size();
+    if (mult_len < (size_t)n * nB)
+        return fail(ENCORE_ESIZE, "mult_len too small: need " + std::to_string((size_t)n * nB));
+    if (zeta_len < (size_t)nout * nB)
+        return fail(ENCORE_ESIZE, "zeta_len too small: need " + std::to_string((size_t)nout * nB));
+    if (coupling && coupling_len < (size_t)nB * n * n)
+        return fail(ENCORE_ESIZE, "coupling_len too small: need " + std::to_string((size_t)nB * n * n));
+    if (n_singular) *n_singular = 0;
+    if (nB == 0) return ENCORE_OK;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    HIPTRY(hipSetDevice(ctx->device));
+    const hipStream_t s = ctx->main.s;
+    DevBufs d;
+    EdgeArgs a{};
+    a.nlam = n;
+    a.nB = (int)nB;
+    a.nout = nout;
+    double *dn, *dr, *dv, *dA, *dx, *dz, *dM = nullptr;
+    int64_t* drs;
+    int32_t *dlp, *dk;
+    unsigned* dbad;
+    int rc;
+    const size_t nt = gt.term_lp.size();
+    if ((rc = d.get(&dn, (size_t)n * nB)) || (rc = d.get(&dr, (size_t)n * nB)) ||
+        (rc = d.get(&drs, gt.row_start.size())) || (rc = d.get(&dlp, nt)) || (rc = d.get(&dv, nt)) ||
+        (rc = d.get(&dA, (size_t)nB * n * n)) || (rc = d.get(&dx, (size_t)nB * n)) ||
+        (rc = d.get(&dk, (size_t)nout)) || (rc = d.get(&dz, (size_t)nout * nB)) || (rc = d.get(&dbad, 1)))
+        return rc;
+    if (coupling && (rc = d.get(&dM, (size_t)nB * n * n))) return rc;
+    HIPTRY(hipMemcpyAsync(dn, nmult, sizeof(double) * n * nB, hipMemcpyHostToDevice, s));
+    HIPTRY(hipMemcpyAsync(dr, rmult, sizeof(double) * n * nB, hipMemcpyHostToDevice, s));
+    HIPTRY(hipMemcpyAsync(drs, gt.row_start.data(), sizeof(int64_t) * gt.row_start.size(), hipMemcpyHostToDevice, s));
+    if (nt) {
+        HIPTRY(hipMemcpyAsync(dlp, gt.term_lp.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice, s));
+        HIPTRY(hipMemcpyAsync(dv, gt.term_val.data(), sizeof(double) * nt, hipMemcpyHostToDevice, s));
+    }
+    if (nout) HIPTRY(hipMemcpyAsync(dk, keep.data(), sizeof(int32_t) * nout, hipMemcpyHostToDevice, s));
+    HIPTRY((hipError_t)launch_fill_u32(dbad, 1, 0u, s));
+    a.nmult = dn;
+    a.rmult = dr;
+    a.row_start = drs;
+    a.term_lp = dlp;
+    a.term_val = dv;
+    a.A = dA;
+    a.rhs = dx;
+    a.keep = dk;
+    a.zeta = dz;
+    a.M_out = dM;
+    a.nbad = dbad;
+    HIPTRY(hipEventRecord(ctx->main.ev[0], s));
+    HIPTRY((hipError_t)launch_edge(a, s));
+    HIPTRY(hipEventRecord(ctx->main.ev[1], s));
+    unsigned nbad = 0;
+    HIPTRY(hipMemcpyAsync(zeta, dz, sizeof(double) * nout * nB, hipMemcpyDeviceToHost, s));
+    if (coupling) HIPTRY(hipMemcpyAsync(coupling, dM, sizeof(double) * nB * n * n, hipMemcpyDeviceToHost, s));
+    HIPTRY(hipMemcpyAsync(&nbad, dbad, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIPTRY(hipStreamSynchronize(s));
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->main.ev[0], ctx->main.ev[1]) == hipSuccess) ctx->timings[0] = ms;
+    if (n_singular) *n_singular = nbad;
+    return ENCORE_OK;
+}

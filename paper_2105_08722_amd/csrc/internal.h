@@ -49,4 +49,16 @@ struct TermTable {
 };
 const TermTable& term_table(int N, int lmax, bool allparity);
 
+// Generalized Gaunt integrals of the multiplet list (N, lmax, allparity), N = 3..5,
+// as the terms of the edge-correction matrix: entry (L, L'') = a * nlam + c holds
+// terms [row_start[e], row_start[e+1]) of (L' = term_lp, E(L'') G^{L L' L''} = term_val).
+struct GauntTable {
+    int nlam = 0;
+    std::vector<int32_t> lam;          // [nlam][width(N)]
+    std::vector<int64_t> row_start;    // [nlam * nlam + 1]
+    std::vector<int32_t> term_lp;
+    std::vector<double> term_val;
+};
+const GauntTable& gaunt_table(int N, int lmax, bool allparity);
+
 }  // namespace encore

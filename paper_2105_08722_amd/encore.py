@@ -66,6 +66,8 @@ SIGNATURES = {
     "encore_plan_destroy": (_I, [_P]),
     "encore_mfma_plan_stats": (_I, [_I, _I, _I, _U32, _P, _SZ]),
     "encore_autotune": (_I, [_P, _P, _P, _I64, _I64, _P, _I, _I, _I, _P, _U32, _I64, _P, _SZ]),
+    "encore_edge_correct": (_I, [_P, _I, _I, _I, _U32, _P, _P, _SZ, _I, _P, _SZ, _P, _SZ,
+                                 ctypes.POINTER(_I64)]),
 }
 
 _lib = None
@@ -349,6 +351,34 @@ def debug_alm(ctx, grid, lmax, edges, primaries, precision="fp64", full_launch=F
                                   PRECISIONS[precision] | (DEBUG_FULLGRID if full_launch else 0),
                                   _ptr(prim), len(prim), _ptr(out)))
     return out[..., 0] + 1j * out[..., 1]
+
+
+def edge_correct(ctx, N, lmax, nbins, nmult, rmult, allparity=False, lmax_out=None,
+                 return_coupling=False):
+    """encore_edge_correct: edge-corrected zeta [nout, nB] from the multiplets of the
+    data-minus-randoms field (nmult) and of the randoms (rmult), both [nlam, nB] as
+    npcf returns them.  lmax_out (default lmax) keeps the multiplets with every
+    principal ell <= lmax_out.  With return_coupling, also M [nB, nlam, nlam] and the
+    number of bin tuples without a solution."""
+    nm = _f64(nmult, (-1,))
+    rm = _f64(rmult, (-1,))
+    nlam = num_multiplets(N, lmax, allparity)
+    nB = num_bin_tuples(N, nbins)
+    if nm.size != nlam * nB or rm.size != nlam * nB:
+        raise ValueError("nmult and rmult must hold %d x %d values" % (nlam, nB))
+    lo = lmax if lmax_out is None else int(lmax_out)
+    nout = num_multiplets(N, lo, allparity) if 0 <= lo <= lmax else 0
+    z = np.zeros(max(nout * nB, 1))
+    M = np.zeros(max(nB * nlam * nlam, 1)) if return_coupling else None
+    bad = _I64(0)
+    _check(lib().encore_edge_correct(ctx.handle, int(N), int(lmax), int(nbins),
+                                     ALLPARITY if allparity else 0, _ptr(nm), _ptr(rm), nm.size, lo,
+                                     _ptr(z), z.size, _ptr(M), 0 if M is None else M.size,
+                                     ctypes.byref(bad)))
+    z = z[:nout * nB].reshape(nout, nB)
+    if return_coupling:
+        return z, M[:nB * nlam * nlam].reshape(nB, nlam, nlam), int(bad.value)
+    return z
 
 
 def npcf_simple(pos, w, N, lmax, edges, box=None, precision="fp32", allparity=False):
