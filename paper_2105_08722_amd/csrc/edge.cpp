@@ -15,11 +15,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <tuple>
+#include <unordered_map>
 #include <vector>
 
 #include "engine.h"
@@ -73,37 +76,76 @@ long double ninej(int j1, int j2, int j3, int j4, int j5, int j6, int j7, int j8
     return s;
 }
 
-// G^{L L' L''} from Appendix A; rows in the multiplet layout of enumerate_multiplets
-double gaunt(int N, const int32_t* a, const int32_t* b, const int32_t* c)
-{
-    int la[5], lb[5], lc[5];
-    principal_of(N, a, la);
-    principal_of(N, b, lb);
-    principal_of(N, c, lc);
-    long double p = 1.0L;
-    for (int i = 0; i < N - 1; ++i) {
-        if ((la[i] + lb[i] + lc[i]) & 1) return 0.0;   // (l l' l''; 0 0 0) = 0
-        if (!tri(la[i], lb[i], lc[i])) return 0.0;
-        const double w = wigner3j(la[i], lb[i], lc[i], 0, 0, 0);
-        if (w == 0.0) return 0.0;
-        p *= std::sqrt((long double)(2 * la[i] + 1) * (2 * lb[i] + 1) * (2 * lc[i] + 1)) * (long double)w;
+// Evaluates G^{L L' L''} from Appendix A for one multiplet list; the principal and
+// intermediate ells are unpacked once, the 3j symbols with zero m are tabulated and
+// the 9j symbols memoised (one evaluator per thread).
+struct GauntEval {
+    int N;
+    int np;                               // principal ells per multiplet
+    std::vector<int> pl, l12;             // [n][np], [n] (N = 5)
+    std::vector<long double> w0;          // (a b c; 0 0 0), index (a * D + b) * D + c
+    int D;
+    std::unordered_map<uint64_t, long double> memo;
+
+    GauntEval(int N_, const std::vector<int32_t>& lam, int W, int n) : N(N_), np(N_ - 1)
+    {
+        pl.resize((size_t)n * np);
+        l12.assign(n, 0);
+        int lmx = 0;
+        for (int i = 0; i < n; ++i) {
+            principal_of(N, &lam[(size_t)i * W], &pl[(size_t)i * np]);
+            if (N == 5) l12[i] = lam[(size_t)i * W + 2];
+            for (int k = 0; k < np; ++k) lmx = std::max(lmx, pl[(size_t)i * np + k]);
+        }
+        D = lmx + 1;
+        w0.assign((size_t)D * D * D, 0.0L);
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b)
+                for (int c = 0; c < D; ++c)
+                    w0[((size_t)a * D + b) * D + c] = wigner3j(a, b, c, 0, 0, 0);
     }
-    const long double fourpi = 4.0L * 3.14159265358979323846264338327950288L;
-    if (N == 3) {   // single direction pair {l, l}: the 3j symbol squared
-        const long double w = wigner3j(la[0], lb[0], lc[0], 0, 0, 0);
-        return (double)(std::sqrt((long double)(2 * la[0] + 1) * (2 * lb[0] + 1) * (2 * lc[0] + 1)) * w * w /
-                        fourpi);
+    long double nine(int j1, int j2, int j3, int j4, int j5, int j6, int j7, int j8, int j9)
+    {
+        const int v[9] = {j1, j2, j3, j4, j5, j6, j7, j8, j9};
+        uint64_t key = 0;
+        for (int x : v) key = key * 64 + (uint64_t)x;
+        auto it = memo.find(key);
+        if (it != memo.end()) return it->second;
+        const long double r = ninej(j1, j2, j3, j4, j5, j6, j7, j8, j9);
+        memo.emplace(key, r);
+        return r;
     }
-    if (N == 4)
-        return (double)(p / std::pow(fourpi, 1.5L) *
-                        ninej(la[0], lb[0], lc[0], la[1], lb[1], lc[1], la[2], lb[2], lc[2]));
-    // N == 5: intermediates l12 at row index 2
-    const int a12 = a[2], b12 = b[2], c12 = c[2];
-    return (double)(p / (fourpi * fourpi) *
-                    std::sqrt((long double)(2 * a12 + 1) * (2 * b12 + 1) * (2 * c12 + 1)) *
-                    ninej(la[0], la[1], a12, lb[0], lb[1], b12, lc[0], lc[1], c12) *
-                    ninej(a12, la[2], la[3], b12, lb[2], lb[3], c12, lc[2], lc[3]));
-}
+    double operator()(int a, int b, int c)
+    {
+        const int* la = &pl[(size_t)a * np];
+        const int* lb = &pl[(size_t)b * np];
+        const int* lc = &pl[(size_t)c * np];
+        long double p = 1.0L;
+        for (int i = 0; i < np; ++i) {
+            if ((la[i] + lb[i] + lc[i]) & 1) return 0.0;   // (l l' l''; 0 0 0) = 0
+            if (!tri(la[i], lb[i], lc[i])) return 0.0;
+            const long double w = w0[((size_t)la[i] * D + lb[i]) * D + lc[i]];
+            if (w == 0.0L) return 0.0;
+            p *= std::sqrt((long double)(2 * la[i] + 1) * (2 * lb[i] + 1) * (2 * lc[i] + 1)) * w;
+        }
+        const long double fourpi = 4.0L * 3.14159265358979323846264338327950288L;
+        if (N == 3) {   // single direction pair {l, l}: the 3j symbol squared
+            const long double w = w0[((size_t)la[0] * D + lb[0]) * D + lc[0]];
+            return (double)(std::sqrt((long double)(2 * la[0] + 1) * (2 * lb[0] + 1) * (2 * lc[0] + 1)) * w * w /
+                            fourpi);
+        }
+        if (N == 4)
+            return (double)(p / std::pow(fourpi, 1.5L) *
+                            nine(la[0], lb[0], lc[0], la[1], lb[1], lc[1], la[2], lb[2], lc[2]));
+        // N == 5: intermediates l12
+        const int a12 = l12[a], b12 = l12[b], c12 = l12[c];
+        if (!tri(a12, b12, c12)) return 0.0;
+        return (double)(p / (fourpi * fourpi) *
+                        std::sqrt((long double)(2 * a12 + 1) * (2 * b12 + 1) * (2 * c12 + 1)) *
+                        nine(la[0], la[1], a12, lb[0], lb[1], b12, lc[0], lc[1], c12) *
+                        nine(a12, la[2], la[3], b12, lb[2], lb[3], c12, lc[2], lc[3]));
+    }
+};
 
 }  // namespace
 
@@ -129,19 +171,37 @@ const GauntTable& gaunt_table(int N, int lmax, bool allparity)
         for (int k = 0; k < N - 1; ++k) s += ls[k];
         E[i] = (s & 1) ? -1 : 1;
     }
-    t->row_start.assign((size_t)n * n + 1, 0);
-    // entry (L = a, L'' = c) -> terms over L' = b, in increasing b
-    for (int a = 0; a < n; ++a)
-        for (int c = 0; c < n; ++c) {
-            for (int b = 0; b < n; ++b) {
-                const double g = gaunt(N, &lam[(size_t)a * W], &lam[(size_t)b * W], &lam[(size_t)c * W]);
-                if (g != 0.0) {
-                    t->term_lp.push_back(b);
-                    t->term_val.push_back(E[c] * g);
+    // entry (L = a, L'' = c) -> terms over L' = b, in increasing b; rows of a are
+    // evaluated on several threads and joined in order
+    const int nth = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
+    std::vector<std::vector<int32_t>> lp(n);
+    std::vector<std::vector<double>> val(n);
+    std::vector<std::vector<int64_t>> cnt(n);
+    std::atomic<int> next{0};
+    auto worker = [&]() {
+        GauntEval ge(N, lam, W, n);
+        for (int a = next++; a < n; a = next++) {
+            cnt[a].assign(n, 0);
+            for (int c = 0; c < n; ++c)
+                for (int b = 0; b < n; ++b) {
+                    const double g = ge(a, b, c);
+                    if (g != 0.0) {
+                        lp[a].push_back(b);
+                        val[a].push_back(E[c] * g);
+                        ++cnt[a][c];
+                    }
                 }
-            }
-            t->row_start[(size_t)a * n + c + 1] = (int64_t)t->term_lp.size();
         }
+    };
+    std::vector<std::thread> th;
+    for (int k = 0; k < nth; ++k) th.emplace_back(worker);
+    for (auto& x : th) x.join();
+    t->row_start.assign((size_t)n * n + 1, 0);
+    for (int a = 0; a < n; ++a) {
+        for (int c = 0; c < n; ++c) t->row_start[(size_t)a * n + c + 1] = t->row_start[(size_t)a * n + c] + cnt[a][c];
+        t->term_lp.insert(t->term_lp.end(), lp[a].begin(), lp[a].end());
+        t->term_val.insert(t->term_val.end(), val[a].begin(), val[a].end());
+    }
     auto* out = t.get();
     cache.emplace(key, std::move(t));
     return *out;

@@ -4,10 +4,10 @@
 // k_edge_matrix: A[B][L''][L] = M_{L L''}(B) = sum_{L'} f_{L'}(B) E(L'') G^{L L' L''},
 //   f = R_{L'} / R_0, each entry a fixed-order sum over its nonzero terms.
 // k_edge_solve:  solves sum_L A[L''][L] zeta_L = N_{L''} / R_0 (eq.
-//   edge-correction-matrix as written: M transposed) by Gauss-Jordan elimination
-//   with partial pivoting (row exchanges chosen by the first largest |pivot|, so
-//   the result does not depend on thread timing).  B with R_0 = 0 or a zero pivot
-//   get NaN and are counted.
+//   edge-correction-matrix as written: M transposed) by Gaussian elimination with
+//   partial pivoting and back substitution (row exchanges chosen by the first
+//   largest |pivot|, so the result does not depend on thread timing).  B with
+//   R_0 = 0 or a zero pivot get NaN and are counted.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -18,7 +18,7 @@ namespace encore {
 
 namespace {
 
-constexpr int kEdgeThreads = 256;
+constexpr int kEdgeThreads = 1024;   // 16 waves per block: enough loads in flight for the row updates
 
 __global__ void __launch_bounds__(kEdgeThreads) k_edge_matrix(EdgeArgs a)
 {
@@ -30,13 +30,14 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge_matrix(EdgeArgs a)
         f[i] = a.rmult[(size_t)i * a.nB + B] / r0;
     __syncthreads();
     double* A = a.A + (size_t)B * n * n;
-    for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += kEdgeThreads) {
-        const int L = (int)(e / n), Lpp = (int)(e - (int64_t)L * n);
-        double s = 0.0;
-        for (int64_t t = a.row_start[e]; t < a.row_start[e + 1]; ++t) s += a.term_val[t] * f[a.term_lp[t]];
-        A[(size_t)Lpp * n + L] = s;
-        if (a.M_out) a.M_out[(size_t)B * n * n + e] = s;
-    }
+    for (int L = 0; L < n; ++L)
+        for (int Lpp = threadIdx.x; Lpp < n; Lpp += kEdgeThreads) {
+            const int64_t e = (int64_t)L * n + Lpp;
+            double s = 0.0;
+            for (int64_t t = a.row_start[e]; t < a.row_start[e + 1]; ++t) s += a.term_val[t] * f[a.term_lp[t]];
+            A[(size_t)Lpp * n + L] = s;
+            if (a.M_out) a.M_out[(size_t)B * n * n + e] = s;
+        }
 }
 
 __global__ void __launch_bounds__(kEdgeThreads) k_edge_solve(EdgeArgs a)
@@ -84,26 +85,39 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge_solve(EdgeArgs a)
             __syncthreads();
             break;
         }
-        // exchange rows p and k, scale row k by 1 / pivot
-        for (int j = k + threadIdx.x; j <= n; j += kEdgeThreads) {
-            double* ak = (j < n) ? &A[(size_t)k * n + j] : &x[k];
-            double* ap = (j < n) ? &A[(size_t)p * n + j] : &x[p];
-            const double vk = *ak, vp = *ap;
-            *ap = vk;
-            *ak = vp / pv;
+        // exchange rows p and k (columns k.. and the right-hand side)
+        if (p != k)
+            for (int j = k + threadIdx.x; j <= n; j += kEdgeThreads) {
+                double* ak = (j < n) ? &A[(size_t)k * n + j] : &x[k];
+                double* ap = (j < n) ? &A[(size_t)p * n + j] : &x[p];
+                const double vk = *ak;
+                *ak = *ap;
+                *ap = vk;
+            }
+        __syncthreads();
+        for (int r = k + 1 + threadIdx.x; r < n; r += kEdgeThreads) fac[r] = A[(size_t)r * n + k] / pv;
+        __syncthreads();
+        // eliminate column k below the pivot: a wave per row, lanes along the row
+        for (int r = k + 1 + threadIdx.x / kWave; r < n; r += kEdgeThreads / kWave) {
+            const double fr = fac[r];
+            if (fr == 0.0) continue;
+            double* ar = &A[(size_t)r * n];
+            const double* ak = &A[(size_t)k * n];
+#pragma unroll 4
+            for (int j = k + 1 + (threadIdx.x & (kWave - 1)); j < n; j += kWave) ar[j] -= fr * ak[j];
+            if ((threadIdx.x & (kWave - 1)) == 0) x[r] -= fr * x[k];
         }
         __syncthreads();
-        for (int r = threadIdx.x; r < n; r += kEdgeThreads) fac[r] = (r == k) ? 0.0 : A[(size_t)r * n + k];
-        __syncthreads();
-        // eliminate column k from every other row
-        const int w = n - k + 1;   // columns k..n-1 and the right-hand side
-        for (int64_t e = threadIdx.x; e < (int64_t)n * w; e += kEdgeThreads) {
-            const int r = (int)(e / w), j = k + (int)(e - (int64_t)r * w);
-            if (fac[r] == 0.0) continue;
-            if (j < n) A[(size_t)r * n + j] -= fac[r] * A[(size_t)k * n + j];
-            else x[r] -= fac[r] * x[k];
+    }
+    // back substitution on the upper triangle
+    if (!bad) {
+        for (int k = n - 1; k >= 0; --k) {
+            if (threadIdx.x == 0) x[k] /= A[(size_t)k * n + k];
+            __syncthreads();
+            const double xk = x[k];
+            for (int r = threadIdx.x; r < k; r += kEdgeThreads) x[r] -= A[(size_t)r * n + k] * xk;
+            __syncthreads();
         }
-        __syncthreads();
     }
     __syncthreads();
     // outputs: the kept multiplets in output order
