@@ -332,7 +332,7 @@ int encore_debug_alm(encore_ctx* ctx, const encore_grid* grid, int lmax, int nbi
  *     M_{L L''}(B) = sum_{L'} (R_{L'}^B / R_0^B) E(L'') G^{L L' L''}
  * with the generalized Gaunt integrals G of eq. generalized-gaunt-def (closed forms
  * of Appendix A: N = 3, 4, 5), and solves N_{L''}^B / R_0^B = sum_L zeta_L^B M_{L L''}
- * for zeta on the device (FP64, Gauss-Jordan elimination with partial pivoting).
+ * for zeta on the device (FP64, Gaussian elimination with partial pivoting and back substitution).
  * L, L', L'' run over the multiplets of (npcf, lmax, flags & ENCORE_ALLPARITY);
  * zeta is returned for those with every principal ell <= lmax_out (the paper
  * measures at lmax_out + 1), in the same order.
@@ -352,7 +352,8 @@ int encore_edge_correct(encore_ctx* ctx, int npcf, int lmax, int nbins, uint32_t
 /* Timings (milliseconds, HIP events on the work stream) of the last encore_npcf
  * call on this context: [0] total, [1] gather, [2] coupling, [3] reduce/contract,
  * [4] number of gather launches, [5] number of accepted (primary, secondary) pairs.
- * out_len >= 6. */
+ * After encore_edge_correct, [0] is the device time of its matrix build and solves
+ * and [1..5] are zero.  out_len >= 6. */
 int encore_last_timings(const encore_ctx* ctx, double* out, size_t out_len);
 
 #ifdef __cplusplus

@@ -316,6 +316,7 @@ extern "C" int encore_edge_correct(encore_ctx* ctx, int npcf, int lmax, int nbin
     HIPTRY(hipMemcpyAsync(&nbad, dbad, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     HIPTRY(hipStreamSynchronize(s));
     float ms = 0.f;
+    for (double& t : ctx->timings) t = 0.0;
     if (hipEventElapsedTime(&ms, ctx->main.ev[0], ctx->main.ev[1]) == hipSuccess) ctx->timings[0] = ms;
     if (n_singular) *n_singular = nbad;
     return ENCORE_OK;

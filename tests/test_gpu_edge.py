@@ -2,8 +2,8 @@
 
 Tolerance: the device builds the coupling matrix from the same generalized Gaunt
 integrals (closed forms of Appendix A, evaluated independently in long double on
-the host) and solves the per-B systems in FP64 by Gauss-Jordan elimination with
-partial pivoting; the oracle uses numpy's LU solve.  The matrices are close to
+the host) and solves the per-B systems in FP64 by Gaussian elimination with
+partial pivoting and back substitution; the oracle uses numpy's LU solve.  The matrices are close to
 (4 pi)^{-(N-1)/2} times the identity (condition numbers of order one), so both
 results agree to rounding: bound 1e-11 relative to max|zeta| and 1e-12 relative to
 max|M| for the matrices.
