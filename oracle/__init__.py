@@ -17,6 +17,10 @@ Functions and the passages they follow
   NPCF-mult-discrete-binned-estimator (no 1/V), full M sum.
 * dmr_weights: randoms weighted negatively so the total weight is zero
   (Section 4.2, reconstruction of the geometry-corrected NPCF).
+* split_zeta: random-split co-adding (Section 4.2): the randoms are cut into
+  consecutive disjoint parts, each part k gives the D-R catalog data + part k
+  (weights by dmr_weights within the part) and its Z^(k) by `zeta`; the result is
+  the mean over the parts.
 * brute_zeta (oracle.brute): O(N_g^N) tuple sum of P*_Lambda, eq.
   brute-force-npcf, with sympy 3j symbols and scipy Y_lm.
 
@@ -177,6 +181,23 @@ def dmr_weights(w_data, w_rand):
     sd = math.fsum(w_data.tolist())
     sr = math.fsum(w_rand.tolist())
     return np.concatenate([w_data, -w_rand * (sd / sr)])
+
+
+def split_zeta(data_pos, data_w, rand_pos, rand_w, split_sizes, N, lmax, edges, box=None,
+               parity="even", nthreads=0):
+    """Mean over the random parts of the D-R multiplets, and the per-part values
+    [n_parts, n_multiplets, n_bin_tuples] (Section 4.2, random splits co-added)."""
+    data_pos = np.asarray(data_pos, dtype=np.float64)
+    rand_pos = np.asarray(rand_pos, dtype=np.float64)
+    per = []
+    o = 0
+    for n in split_sizes:
+        pos = np.concatenate([data_pos, rand_pos[o:o + n]])
+        w = dmr_weights(data_w, rand_w[o:o + n])
+        per.append(zeta(pos, w, N, lmax, edges, box=box, parity=parity, nthreads=nthreads))
+        o += n
+    per = np.array(per)
+    return per.mean(axis=0), per
 
 
 def normalise(Z, N, edges, volume):
