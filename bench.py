@@ -172,6 +172,51 @@ def served_leg(ctx, edges, njobs, rate, seed=5000):
                         "10 bins [20,160]; 3 lanes" % rate}
 
 
+def splits_leg(ctx, edges, precision, nparts, seed=6000):
+    """Random-split co-adding (Section 4.2): 200k Neyman-Scott data and random parts
+    of 1.5 N_D uniform points each, 4PCF lmax=5, in two regimes: the benchmark's
+    density (periodic 1000 Mpc/h, nparts parts) and 8x that density (500 Mpc/h, 4
+    parts).  One encore_npcf_splits call (the data part of a~ gathered once; per
+    part, data primaries against the part's randoms only) against one
+    encore_npcf_batch call over the same D + R_k catalogs (every pair of every part
+    gathered)."""
+    import numpy as np
+    from paper_2105_08722_amd import encore, synth
+    out = {}
+    for name, box, K in (("box1000", 1000.0, nparts), ("box500", 500.0, 4)):
+        nd = 200_000
+        nr = 3 * nd // 2
+        dpos, dw = synth.neyman_scott(nd, box, seed)
+        rpos, rw = synth.uniform_box(K * nr, box, seed + 7919)
+        gd, gs = encore.build_split_grids(ctx, dpos, dw, rpos, rw, [nr] * K, edges[-1], box=box)
+        try:
+            encore.npcf_splits(ctx, gd, gs, 4, 5, edges, precision=precision)   # warm; builds the randoms-only grids
+            t0 = time.perf_counter()
+            zs = encore.npcf_splits(ctx, gd, gs, 4, 5, edges, precision=precision)
+            t_split = time.perf_counter() - t0
+            tm_s = ctx.last_timings()
+            encore.npcf_batch(ctx, gs, 4, 5, edges, precision=precision)   # warm
+            t0 = time.perf_counter()
+            zb = encore.npcf_batch(ctx, gs, 4, 5, edges, precision=precision)
+            t_batch = time.perf_counter() - t0
+            tm_b = ctx.last_timings()
+        finally:
+            for g in gs:
+                g.free()
+            gd.free()
+        zm = zb.mean(axis=0)
+        prim = K * (nd + nr)
+        out[name] = {"parts": K, "n_data": nd, "randoms_per_part": nr, "precision": precision,
+                     "coadded_s": t_split, "batch_s": t_batch, "speedup": t_batch / t_split,
+                     "primaries_per_s": prim / t_split, "primaries_per_s_batch": prim / t_batch,
+                     "pairs_coadded": tm_s["pairs"], "pairs_batch": tm_b["pairs"],
+                     "gather_ms": tm_s["gather_ms"], "gather_ms_batch": tm_b["gather_ms"],
+                     "max_rel_diff_vs_batch": float(np.max(np.abs(zs - zm)) / np.max(np.abs(zm))),
+                     "workload": "200k Neyman-Scott data + %d random parts of 300k uniform points (D-R per "
+                                 "part), periodic %g Mpc/h, 4PCF lmax=5, 10 bins, grids prebuilt" % (K, box)}
+    return out
+
+
 def edge_leg(ctx):
     """Edge correction of the paper's analyses (Section 5.4): 4PCF measured at
     lmax = 6 for output lmax = 5, and 5PCF measured at lmax = 4 for output lmax = 3,
@@ -213,6 +258,7 @@ def main():
     ap.add_argument("--precision", default="splitbf16", choices=["fp32", "fp64", "splitbf16"])
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-edge", action="store_true", help="skip the edge-correction leg")
+    ap.add_argument("--split-parts", type=int, default=8, help="random parts of the co-adding leg (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
@@ -328,6 +374,11 @@ def main():
         extra["served"] = served_leg(ctx, edges, args.served_jobs, 4.0)
         log("served: p50 %.2f s, p99 %.2f s" % (extra["served"]["p50_latency_s"],
                                                  extra["served"]["p99_latency_s"]))
+    if args.split_parts > 0:
+        log("random-split co-adding leg: %d parts" % args.split_parts)
+        extra["random_splits"] = splits_leg(ctx, edges, args.precision, args.split_parts)
+        log("random splits: %s" % ", ".join("%s co-added %.3f s vs batch %.3f s" % (k, v["coadded_s"], v["batch_s"])
+                                              for k, v in extra["random_splits"].items()))
     if not args.no_edge:
         log("edge-correction leg")
         extra["edge_correction"] = edge_leg(ctx)

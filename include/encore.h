@@ -349,6 +349,41 @@ int encore_edge_correct(encore_ctx* ctx, int npcf, int lmax, int nbins, uint32_t
                         double* zeta, size_t zeta_len, double* coupling, size_t coupling_len,
                         int64_t* n_singular);
 
+/*
+ * Random-split co-adding (Section 4.2, Reconstructing the geometry-corrected
+ * NPCF): the random catalog is cut into disjoint parts R_1..R_K; part k gives the
+ * data-minus-randoms catalog D + R_k, whose multiplets N^(k) are measured as by
+ * encore_npcf, and the mean (1/K) sum_k N^(k) is returned.  The data's share of
+ * the harmonic coefficients of every data primary is the same in each part: it is
+ * gathered ONCE (from data_grid) and kept on the device (n_data rows of
+ * nbins * (lmax+1)(lmax+2)/2 complex values, FP64 or FP32 by precision).  In each
+ * part the data primaries are then gathered against the part's randoms alone (a
+ * grid of R_k with its D-R weights, built from the split grid on first use and
+ * freed with it) and get the kept rows added; the random primaries are gathered
+ * against D + R_k.  Data-data pairs are thus visited once, not K times.
+ *
+ *  data_grid   grid of the data alone (built without ENCORE_DMR).
+ *  split_grids [nsplit] grids built with ENCORE_DMR on D + R_k: the first n_data
+ *              input points are the data catalog, in data_grid's input order, with
+ *              the same positions and weights (checked on the device).  Same
+ *              periodic box as data_grid.
+ *  nsplit      K >= 1.
+ *  npcf, lmax, nbins, edges, flags, volume  as encore_npcf (edges within the
+ *              r_max of every grid).
+ *  zeta        host FP64 [n_multiplets * n_bin_tuples]: the mean over the parts.
+ *  zeta_splits NULL, or host FP64 [nsplit][n_multiplets * n_bin_tuples]: N^(k).
+ *  stream      as encore_npcf.
+ * Timings: [1] includes the data gather, [5] its pairs; [0] excludes building
+ * the randoms-only grids.
+ * Errors: EINVAL (grids that do not match as above), ESIZE, ENOMEM, EDEVICE,
+ * EUNSUPPORTED as encore_npcf.
+ */
+int encore_npcf_splits(encore_ctx* ctx, const encore_grid* data_grid,
+                       const encore_grid* const* split_grids, int nsplit, int npcf, int lmax,
+                       int nbins, const double* edges, uint32_t flags, double volume,
+                       double* zeta, size_t zeta_len, double* zeta_splits,
+                       size_t zeta_splits_len, void* stream);
+
 /* Timings (milliseconds, HIP events on the work stream) of the last encore_npcf
  * call on this context: [0] total, [1] gather, [2] coupling, [3] reduce/contract,
  * [4] number of gather launches, [5] number of accepted (primary, secondary) pairs.

@@ -119,6 +119,8 @@ struct JobRows {
     const encore_grid* grid;
     const int32_t* prim;   // device
     int64_t nprim;
+    const double4* Pq = nullptr;   // random-split jobs (see Chunk)
+    const void* cache = nullptr;
 };
 
 // The hot path over several jobs on the context's main exec (ctx->mu held):
@@ -162,7 +164,7 @@ int run_jobs(encore_ctx* ctx, const std::vector<JobRows>& jobs, const NpcfPlan& 
             if (take == 0 && J.nprim > jpos) break;                  // next slice
             if (take > 0) {
                 chunks.push_back(Chunk{&J.grid->g, J.prim, jpos, jpos + take, sr,
-                                       (double*)x.Tjob.p + (size_t)jcur * outs});
+                                       (double*)x.Tjob.p + (size_t)jcur * outs, J.Pq, J.cache});
                 rows += take;
                 jpos += take;
             }
@@ -285,6 +287,10 @@ int encore_free_grid(encore_grid* grid)
     (void)hipSetDevice(grid->ctx->device);
     (void)hipDeviceSynchronize();
     grid_free(grid->g);
+    if (grid->rand_only) {
+        grid_free(grid->rand_only->g);
+        delete grid->rand_only;
+    }
     grid->ctx->live_grids--;
     delete grid;
     return ENCORE_OK;
@@ -410,6 +416,145 @@ int encore_npcf_batch(encore_ctx* ctx, const encore_grid* const* grids, int njob
             off += grids[j]->g.n;
         }
         return run_jobs(ctx, jobs, pl, flags, edges, 0.0, zeta);
+    });
+}
+
+int encore_npcf_splits(encore_ctx* ctx, const encore_grid* data_grid, const encore_grid* const* split_grids,
+                       int nsplit, int npcf, int lmax, int nbins, const double* edges, uint32_t flags,
+                       double volume, double* zeta, size_t zeta_len, double* zeta_splits,
+                       size_t zeta_splits_len, void* stream)
+{
+    if (!ctx || !data_grid || !split_grids) return fail(ENCORE_EINVAL, "NULL ctx, data_grid or split_grids");
+    if (nsplit < 1) return fail(ENCORE_EINVAL, "nsplit must be >= 1");
+    NpcfPlan pl;
+    int rc;
+    if ((rc = plan_call(npcf, lmax, nbins, edges, flags, &pl))) return rc;
+    pl.nbg = ctx_nbg(ctx, pl);
+    if ((rc = check_grids(split_grids, nsplit, ctx, edges, nbins, flags, volume))) return rc;
+    if ((rc = check_grids(&data_grid, 1, ctx, edges, nbins, 0u, 0.0))) return rc;
+    const DevGrid& gD = data_grid->g;
+    if (gD.dmr) return fail(ENCORE_EINVAL, "data_grid must be built without ENCORE_DMR");
+    for (int k = 0; k < nsplit; ++k) {
+        const DevGrid& g = split_grids[k]->g;
+        const std::string which = "split grid " + std::to_string(k);
+        if (!g.dmr || g.n_data != gD.n)
+            return fail(ENCORE_EINVAL, which + ": needs ENCORE_DMR with n_data = the data grid's size");
+        if (g.periodic != gD.periodic ||
+            (g.periodic && (g.Lx != gD.Lx || g.Ly != gD.Ly || g.Lz != gD.Lz)))
+            return fail(ENCORE_EINVAL, which + ": periodic box differs from the data grid's");
+    }
+    const size_t need = (size_t)(pl.nlam * pl.nB);
+    if (!zeta && need > 0) return fail(ENCORE_EINVAL, "zeta is NULL");
+    if (zeta_len < need) return fail(ENCORE_ESIZE, "zeta needs " + std::to_string(need) + " elements");
+    if (zeta_splits && zeta_splits_len < need * (size_t)nsplit)
+        return fail(ENCORE_ESIZE, "zeta_splits needs " + std::to_string(need * nsplit) + " elements");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    for (double& t : ctx->timings) t = 0.0;
+    if (need == 0) return ENCORE_OK;
+    HIPTRY(hipSetDevice(ctx->device));
+    return on_stream(ctx, stream, [&]() {
+        Exec& x = ctx->main;
+        const hipStream_t s = x.s;
+        int rc2;
+        // every part's data are the data grid's
+        if ((rc2 = ensure(x.misc, 64))) return rc2;
+        int* d_bad = (int*)((char*)x.misc.p + 16);
+        HIPTRY((hipError_t)launch_fill_u32((unsigned*)d_bad, 1, 0u, s));
+        for (int k = 0; k < nsplit; ++k) HIPTRY((hipError_t)launch_split_check(split_grids[k]->g, gD, d_bad, s));
+        int bad = 0;
+        HIPTRY(hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPTRY(hipStreamSynchronize(s));
+        if (bad)
+            return fail(ENCORE_EINVAL, "a split grid's first n_data points differ from the data grid's "
+                                       "(positions and weights, in input order)");
+        // each part's randoms alone (their D-R weights), built once per split grid
+        for (int k = 0; k < nsplit; ++k) {
+            const encore_grid* sg = split_grids[k];
+            if (sg->rand_only) continue;
+            const DevGrid& S = sg->g;
+            const int64_t nr = S.n - S.n_data;
+            double* d_pos = nullptr;
+            double* d_w = nullptr;
+            HIPTRY(hipMalloc(&d_pos, sizeof(double) * 3 * nr));
+            hipError_t e = hipMalloc(&d_w, sizeof(double) * nr);
+            if (e == hipSuccess) e = (hipError_t)launch_split_randoms(S, d_pos, d_w, s);
+            auto* rg = new encore_grid();
+            rg->ctx = ctx;
+            int rcb = e == hipSuccess ? ENCORE_OK : hip_fail(e, "split randoms");
+            if (rcb == ENCORE_OK) {
+                const double box[3] = {S.Lx, S.Ly, S.Lz};
+                double div = 0.0, xsub = 0.0;
+                ctx_cells(ctx, &div, &xsub);
+                rcb = build_grid_dev(ctx->device, d_pos, d_w, nr, 0, false, S.periodic ? box : nullptr, S.r_max,
+                                     div, xsub, s, rg->g);
+            }
+            (void)hipStreamSynchronize(s);
+            if (d_pos) (void)hipFree(d_pos);
+            if (d_w) (void)hipFree(d_w);
+            if (rcb) {
+                delete rg;
+                return rcb;
+            }
+            sg->rand_only = rg;
+        }
+        HIPTRY(hipEventRecord(x.ev[0], s));
+        DevTables* tb = nullptr;
+        if ((rc2 = get_tables_for(ctx, pl, &tb))) return rc2;
+        int64_t nmax = gD.n;
+        for (int k = 0; k < nsplit; ++k) nmax = std::max<int64_t>(nmax, split_grids[k]->rand_only->g.n);
+        if ((rc2 = ensure(x.prim, sizeof(int32_t) * (size_t)nmax))) return rc2;
+        int32_t* prim = (int32_t*)x.prim.p;   // 0, 1, 2, ...: every point of a grid in its cell order
+        HIPTRY((hipError_t)launch_iota(prim, nmax, s));
+
+        // the data part of a~ of every data primary, gathered once into x.cache
+        // (row p: the data grid's point p)
+        const size_t rb = alm_row_bytes(pl);
+        if ((rc2 = ensure(x.cache, rb * (size_t)gD.n))) return rc2;
+        const int64_t cap = cap_rows(pl);
+        unsigned long long* d_pairs = (unsigned long long*)x.misc.p;
+        HIPTRY((hipError_t)launch_fill((double*)d_pairs, 1, 0.0, s));
+        HIPTRY(hipEventRecord(x.ev[1], s));
+        for (int64_t r0 = 0; r0 < gD.n; r0 += cap) {
+            const int64_t r1 = std::min<int64_t>(gD.n, r0 + cap);
+            std::vector<Chunk> chunks{Chunk{&gD, prim, r0, r1, r1 - r0, nullptr}};
+            SliceLaunch L;
+            if ((rc2 = prepare_slice(x, x.segs, x.splits, x.redp, pl, tb, edges, chunks, L))) return rc2;
+            L.ga.alm = (char*)x.cache.p + (size_t)r0 * rb;
+            if ((rc2 = launch_slice_gather(L, pl, s))) return rc2;
+            HIPTRY(hipStreamSynchronize(s));   // the slice tables are rewritten by the next slice
+        }
+        HIPTRY(hipEventRecord(x.ev[2], s));
+        HIPTRY(hipEventSynchronize(x.ev[2]));
+        float ms_cache = 0.f;
+        HIPTRY(hipEventElapsedTime(&ms_cache, x.ev[1], x.ev[2]));
+        unsigned long long pairs_cache = 0;
+        HIPTRY(hipMemcpy(&pairs_cache, d_pairs, sizeof(pairs_cache), hipMemcpyDeviceToHost));
+
+        // per part two jobs: the data primaries against the part's randoms (plus
+        // their cached rows), and the part's random primaries against data + randoms
+        std::vector<JobRows> jobs(2 * (size_t)nsplit);
+        for (int k = 0; k < nsplit; ++k) {
+            const encore_grid* R = split_grids[k]->rand_only;
+            jobs[2 * k] = JobRows{R, prim, gD.n, gD.P, x.cache.p};
+            jobs[2 * k + 1] = JobRows{split_grids[k], prim, R->g.n, R->g.P, nullptr};
+        }
+        std::vector<double> zs(need * 2 * (size_t)nsplit);
+        if ((rc2 = run_jobs(ctx, jobs, pl, flags, edges, volume, zs.data()))) return rc2;
+        ctx->timings[1] += ms_cache;
+        ctx->timings[5] += (double)pairs_cache;
+        // Z of a part = data primaries' + random primaries' sums; the mean over the
+        // parts in part order
+        std::vector<double> zk(need * (size_t)nsplit);
+        for (int k = 0; k < nsplit; ++k)
+            for (size_t i = 0; i < need; ++i)
+                zk[(size_t)k * need + i] = zs[(size_t)(2 * k) * need + i] + zs[(size_t)(2 * k + 1) * need + i];
+        for (size_t i = 0; i < need; ++i) {
+            double acc = 0.0;
+            for (int k = 0; k < nsplit; ++k) acc += zk[(size_t)k * need + i];
+            zeta[i] = acc / nsplit;
+        }
+        if (zeta_splits) std::copy(zk.begin(), zk.end(), zeta_splits);
+        return ENCORE_OK;
     });
 }
 
@@ -598,7 +743,8 @@ int encore_debug_alm(encore_ctx* ctx, const encore_grid* grid, int lmax, int nbi
     hipError_t e = hipMemcpy(d_kg, kap.data(), sizeof(double) * nlm, hipMemcpyHostToDevice);
     const DevGrid& g = grid->g;
     GatherSeg gs;
-    gs.P = g.P; gs.cell_start = g.cell_start; gs.prim = (const int32_t*)x.prim.p;
+    memset(&gs, 0, sizeof(gs));
+    gs.P = g.P; gs.Pq = g.P; gs.nP = (int)g.n; gs.cell_start = g.cell_start; gs.prim = (const int32_t*)x.prim.p;
     gs.ncx = g.ncx; gs.ncy = g.ncy; gs.ncz = g.ncz; gs.periodic = g.periodic;
     gs.ox = g.ox; gs.oy = g.oy; gs.oz = g.oz;
     gs.csx = g.csx; gs.csy = g.csy; gs.csz = g.csz;

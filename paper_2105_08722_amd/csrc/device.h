@@ -17,7 +17,7 @@ constexpr int kWave = 64;        // CDNA wavefront
 // (cz * ncy + cy) * ncx + cx, so the cells of one (cy, cz) row are contiguous.
 struct DevGrid {
     int64_t n = 0;
-    double4* P = nullptr;        // sorted (x, y, z, w) in FP64
+    double4* P = nullptr;        // sorted (x, y, z, w) in FP64; P[n] is a NaN sentinel
     int32_t* perm = nullptr;     // sorted index -> input index
     int32_t* inv = nullptr;      // input index -> sorted index
     int32_t* cell_start = nullptr;  // [ncell + 1]
@@ -27,6 +27,8 @@ struct DevGrid {
     int periodic = 0;
     double Lx = 0, Ly = 0, Lz = 0;
     double r_max = 0;
+    int64_t n_data = 0;   // with dmr: input points [0, n_data) are data
+    int dmr = 0;          // built as a data-minus-randoms catalog
 };
 
 // ------------------------------------------------------------------ grid build
@@ -43,6 +45,13 @@ int launch_map_subset(const int64_t* idx, int64_t k, const int32_t* inv, int64_t
 int launch_fill(double* p, int64_t n, double v, hipStream_t stream);
 int launch_fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t stream);
 int launch_to_double(const void* src, int precision, int64_t n, double* dst, hipStream_t stream);
+// Random-split catalog S (data + one random part, built with dmr) against the
+// data-only grid D: *bad = 1 if a data point of S differs from D's (position or
+// weight, same input index).
+int launch_split_check(const DevGrid& S, const DevGrid& D, int* bad, hipStream_t stream);
+// The random points of S (input order) as arrays pos [n - n_data][3], w (S's
+// data-minus-randoms weights).
+int launch_split_randoms(const DevGrid& S, double* pos, double* w, hipStream_t stream);
 
 // ------------------------------------------------------------------ gather
 // Harmonic coefficient gather (eq. binned-discrete-alm).  A launch covers a
@@ -51,13 +60,15 @@ int launch_to_double(const void* src, int precision, int64_t n, double* dst, hip
 // Work item = (slice row, bin group); rows are written as complex
 // alm[row][nbins][nlm] plus the primary's weight wprim[row].
 struct GatherSeg {
-    const double4* P;
+    const double4* P;      // secondaries (cell-sorted, n points + the NaN sentinel)
     const int32_t* cell_start;
-    const int32_t* prim;   // sorted indices of this segment's primaries
+    const double4* Pq;     // primary records (P, or another grid's points)
+    const int32_t* prim;   // indices into Pq of this segment's primaries
     int ncx, ncy, ncz, periodic;
     double ox, oy, oz, csx, csy, csz;
     double Lx, Ly, Lz;
     int row0, nprim;
+    int nP, pad_;          // points of P (index of the sentinel)
     // derived by finish_seg: reciprocal cell sizes, the pad of the culling radius
     // and the FP32 row set-up margin (both in length units)
     double icsx, icsy, icsz, cull_pad, frame_eps;
@@ -95,6 +106,10 @@ struct GatherArgs {
 // precision: 0 = FP64, 1 = FP32.  nbg: bins per work item (0 or a value without
 // a compiled variant: the default).  persistent: grid sized to the resident waves.
 int launch_gather(const GatherArgs& a, int lmax, int precision, int nbg, bool persistent, hipStream_t stream);
+// alm row row0 + r += cache row prim[r], r < nrows (rows of row_cplx complex
+// values; precision 0: FP64, else FP32)
+int launch_add_cached(void* alm, int precision, int row0, int nrows, const int32_t* prim, const void* cache,
+                      int row_cplx, hipStream_t stream);
 int gather_group_bins(int lmax, int precision, int nbg);
 // compiled bins-per-item values for (lmax, precision), the default first
 std::vector<int> gather_nbg_options(int lmax, int precision);

@@ -45,7 +45,7 @@ int ensure(Buf& b, size_t bytes)
 static Buf* exec_bufs(Exec& x, int i)
 {
     Buf* all[] = {&x.alm, &x.wprim, &x.T, &x.segs, &x.splits, &x.redp, &x.queues,
-                  &x.misc, &x.zeta, &x.bscale, &x.prim, &x.Tjob, &x.almb};
+                  &x.misc, &x.zeta, &x.bscale, &x.prim, &x.Tjob, &x.almb, &x.cache, &x.cmap};
     return i < (int)(sizeof(all) / sizeof(all[0])) ? all[i] : nullptr;
 }
 
@@ -290,6 +290,7 @@ int prepare_slice(Exec& x, Buf& segs, Buf& splits, Buf& redp, const NpcfPlan& pl
     std::vector<GatherSeg> hsegs;
     std::vector<int32_t> slo, shi, rlo, rhi;
     std::vector<double*> rdst;
+    std::vector<CacheAdd> adds;
     int64_t rows = 0;
     // The MFMA coupling's K blocks are whole 16-row blocks of the blocked layout;
     // each job starts on a block so that its blocks, and so its FP32 sums, are the
@@ -302,14 +303,18 @@ int prepare_slice(Exec& x, Buf& segs, Buf& splits, Buf& redp, const NpcfPlan& pl
         if (blocked) rows = (rows + kBlkRows - 1) / kBlkRows * kBlkRows;
         const DevGrid& g = *c.g;
         GatherSeg gs;
+        memset(&gs, 0, sizeof(gs));
         gs.P = g.P; gs.cell_start = g.cell_start; gs.prim = c.prim + c.r0;
         gs.ncx = g.ncx; gs.ncy = g.ncy; gs.ncz = g.ncz; gs.periodic = g.periodic;
         gs.ox = g.ox; gs.oy = g.oy; gs.oz = g.oz;
         gs.csx = g.csx; gs.csy = g.csy; gs.csz = g.csz;
         gs.Lx = g.Lx; gs.Ly = g.Ly; gs.Lz = g.Lz;
         gs.row0 = (int)rows; gs.nprim = (int)take;
+        gs.Pq = c.Pq ? c.Pq : g.P;
+        gs.nP = (int)g.n;
         finish_seg(gs);
         hsegs.push_back(gs);
+        if (c.cache) adds.push_back(CacheAdd{(int)rows, (int)take, c.prim + c.r0, c.cache});
         rlo.push_back((int32_t)slo.size());
         for (int64_t r = 0; r < take; r += c.split_rows) {
             slo.push_back((int32_t)(rows + r));
@@ -321,6 +326,7 @@ int prepare_slice(Exec& x, Buf& segs, Buf& splits, Buf& redp, const NpcfPlan& pl
     }
     L = SliceLaunch();
     L.rows = rows;
+    L.adds = std::move(adds);
     if (rows == 0) return ENCORE_OK;
     if (rows > INT32_MAX || hsegs.size() > 65535) return fail(ENCORE_ESIZE, "slice too large");
     const int nsplit = (int)slo.size(), nred = (int)rlo.size();
@@ -408,6 +414,10 @@ int launch_slice_gather(const SliceLaunch& L, const NpcfPlan& pl, hipStream_t s)
 {
     if (L.rows == 0) return ENCORE_OK;
     HIPTRY((hipError_t)launch_gather(L.ga, pl.lmax, pl.prec == 0 ? 0 : 1, pl.nbg, L.persistent, s));
+    const int row_cplx = pl.nbins * (pl.lmax + 1) * (pl.lmax + 2) / 2;
+    for (const CacheAdd& c : L.adds)
+        HIPTRY((hipError_t)launch_add_cached(L.ga.alm, pl.prec == 0 ? 0 : 1, c.row0, c.nrows, c.prim, c.cache,
+                                             row_cplx, s));
     return ENCORE_OK;
 }
 

@@ -56,6 +56,7 @@ struct Buf {
 struct Exec {
     hipStream_t s = nullptr;
     Buf alm, wprim, T, segs, splits, redp, queues, misc, zeta, bscale, prim, Tjob, almb;
+    Buf cache, cmap;   // random splits: the data part of a~ and the row maps
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 int exec_init(Exec& x);
@@ -110,6 +111,11 @@ struct Chunk {
     int64_t r0, r1;
     int64_t split_rows;
     double* Tdst;          // device [ntuple * nB]
+    // primaries from another point array (null: the grid's own points; prim then
+    // indexes Pq), and cache rows added to the gathered rows (row of primary p +=
+    // cache row p; null: none)
+    const double4* Pq = nullptr;
+    const void* cache = nullptr;
 };
 // Gather + couple + reduce for the chunks (at most cap_rows rows in total).
 // Synchronises x.s before returning; adds the gather / coupling milliseconds.
@@ -121,9 +127,15 @@ int run_slice(Exec& x, const NpcfPlan& pl, const DevTables* tb, const double* ed
 // (asynchronously on x.s) into segs / splits / redp and grows x's workspaces;
 // launch_slice_* then only launch kernels (no allocation, no host synchronisation),
 // so they can be recorded into a HIP graph.
+struct CacheAdd {
+    int row0, nrows;
+    const int32_t* prim;
+    const void* cache;
+};
 struct SliceLaunch {
     int64_t rows = 0;
     bool persistent = false;
+    std::vector<CacheAdd> adds;   // after the gather
     GatherArgs ga;
     CoupleArgs ca;
     MfmaArgs ma;
@@ -168,6 +180,9 @@ struct encore_grid {
     encore_ctx* ctx = nullptr;
     encore::DevGrid g;
     std::atomic<int> plans{0};   // live encore_plan objects on this grid
+    // random-split co-adding: the grid of this D-R catalog's randoms alone (with
+    // their D-R weights), built on first use and freed with this grid
+    mutable encore_grid* rand_only = nullptr;
 };
 
 namespace encore {

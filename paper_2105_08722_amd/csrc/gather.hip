@@ -256,7 +256,8 @@ __device__ __forceinline__ GatherSeg load_seg(const GatherSeg* segs, int s)
     g.ox = uni(g.ox); g.oy = uni(g.oy); g.oz = uni(g.oz);
     g.csx = uni(g.csx); g.csy = uni(g.csy); g.csz = uni(g.csz);
     g.Lx = uni(g.Lx); g.Ly = uni(g.Ly); g.Lz = uni(g.Lz);
-    g.row0 = uni(g.row0); g.nprim = uni(g.nprim);
+    g.Pq = uni(g.Pq);
+    g.row0 = uni(g.row0); g.nprim = uni(g.nprim); g.nP = uni(g.nP);
     g.icsx = uni(g.icsx); g.icsy = uni(g.icsy); g.icsz = uni(g.icsz);
     g.cull_pad = uni(g.cull_pad); g.frame_eps = uni(g.frame_eps);
     return g;
@@ -484,7 +485,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
     const gptr<double4> gP = as_global(g.P);
     const gptr<int32_t> gcs = as_global(g.cell_start);
     const int ip = uni(g.prim[row - g.row0]);
-    const double4 Pi = g.P[ip];
+    const double4 Pi = g.Pq[ip];
     const double xi = uni(Pi.x), yi = uni(Pi.y), zi = uni(Pi.z);
     const int b_lo = grp * NBG;
     const int b_hi = min(b_lo + NBG, a.nbins);
@@ -554,10 +555,10 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         // ---- 2./3. candidates, 64 per chunk: lane l of the chunk at flat position p0
         //      takes candidate p0 + l, whose entry (particle index | image code) is
         //      p0 + l plus the delta of the last piece starting at or before it.
-        //      Positions past the batch take the primary itself (r = 0 < R_in, always
-        //      rejected).  Piece descriptors are held 64 at a time in VGPRs (lane l:
-        //      piece gbase + l) and read with readlane.
-        const unsigned self_entry = (unsigned)ip | ((unsigned)kCenterCode << kCodeShift);
+        //      Positions past the batch take the grid's sentinel point (NaN position:
+        //      every bin compare is false).  Piece descriptors are held 64 at a time
+        //      in VGPRs (lane l: piece gbase + l) and read with readlane.
+        const unsigned self_entry = (unsigned)g.nP | ((unsigned)kCenterCode << kCodeShift);
         int gbase = 0;
         unsigned dl_v = 0;
         int fs_v = 0;
@@ -694,7 +695,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
                 }(std::make_integer_sequence<int, NBG>{});
             };
             // two chunks per iteration, alternating prefetch registers; the
-            // prefetch is unconditional (past the last chunk it loads the primary)
+            // prefetch is unconditional (past the last chunk it loads the sentinel)
             // so that waiting for a chunk's loads never waits for the next's
             unsigned me_a = fetch(0);
             double4 q_a = load_point(gP, (int)(me_a & kStartMask));
@@ -986,6 +987,41 @@ int launch_gather(const GatherArgs& a0, int lmax, int precision, int nbg, bool p
         if (e != hipSuccess) return (int)e;
     }
     return (int)hipSuccess;
+}
+
+namespace {
+// One block per row: the row of primary prim[r] gets cache row prim[r] (its
+// cached data part; complex entries, 2 * T each) added.
+template <typename T>
+__global__ void __launch_bounds__(256) k_add_cached(T* __restrict__ alm, int row0, const int32_t* __restrict__ prim,
+                                                   const T* __restrict__ cache, int row_cplx)
+{
+    const int r = blockIdx.x;
+    const int src = prim[r];
+    using V = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+    V* dst = reinterpret_cast<V*>(alm) + (int64_t)(row0 + r) * row_cplx;
+    const V* cs = reinterpret_cast<const V*>(cache) + (int64_t)src * row_cplx;
+    for (int c = threadIdx.x; c < row_cplx; c += 256) {
+        V v = dst[c];
+        const V u = cs[c];
+        v.x += u.x;
+        v.y += u.y;
+        dst[c] = v;
+    }
+}
+}  // namespace
+
+int launch_add_cached(void* alm, int precision, int row0, int nrows, const int32_t* prim, const void* cache,
+                      int row_cplx, hipStream_t stream)
+{
+    if (nrows <= 0) return (int)hipSuccess;
+    if (precision == 0)
+        k_add_cached<double><<<dim3((unsigned)nrows), dim3(256), 0, stream>>>(
+            static_cast<double*>(alm), row0, prim, static_cast<const double*>(cache), row_cplx);
+    else
+        k_add_cached<float><<<dim3((unsigned)nrows), dim3(256), 0, stream>>>(
+            static_cast<float*>(alm), row0, prim, static_cast<const float*>(cache), row_cplx);
+    return (int)hipGetLastError();
 }
 
 }  // namespace encore

@@ -194,7 +194,11 @@ __global__ void k_gather_sorted(const double* __restrict__ pos, const double* __
                                 double4* __restrict__ P, int32_t* __restrict__ inv)
 {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= n) return;
+    if (k > n) return;
+    if (k == n) {   // sentinel past the last point: NaN position, never binned
+        P[n] = make_double4(NAN, NAN, NAN, 0.0);
+        return;
+    }
     const int32_t i = perm[k];
     P[k] = make_double4(pos[3 * (int64_t)i], pos[3 * (int64_t)i + 1], pos[3 * (int64_t)i + 2], w[i]);
     inv[i] = (int32_t)k;
@@ -276,6 +280,44 @@ int launch_to_double(const void* src, int precision, int64_t n, double* dst, hip
     return (int)hipGetLastError();
 }
 
+// Split grid S (data then one random part) against the data-only grid D.
+__global__ void k_split_check(const double4* __restrict__ PS, const int32_t* __restrict__ invS, int64_t n_data,
+                              const double4* __restrict__ PD, const int32_t* __restrict__ invD,
+                              int* __restrict__ bad)
+{
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n_data) return;
+    const double4 q = PS[invS[j]];
+    const double4 r = PD[invD[j]];
+    if (!(q.x == r.x && q.y == r.y && q.z == r.z && q.w == r.w)) atomicOr(bad, 1);
+}
+
+__global__ void k_split_randoms(const double4* __restrict__ PS, const int32_t* __restrict__ invS, int64_t n_data,
+                                int64_t n, double* __restrict__ pos, double* __restrict__ w)
+{
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n - n_data) return;
+    const double4 q = PS[invS[n_data + j]];
+    pos[3 * j] = q.x;
+    pos[3 * j + 1] = q.y;
+    pos[3 * j + 2] = q.z;
+    w[j] = q.w;
+}
+
+int launch_split_check(const DevGrid& S, const DevGrid& D, int* bad, hipStream_t stream)
+{
+    if (S.n_data <= 0) return 0;
+    k_split_check<<<nblocks(S.n_data), kBlock, 0, stream>>>(S.P, S.inv, S.n_data, D.P, D.inv, bad);
+    return (int)hipGetLastError();
+}
+
+int launch_split_randoms(const DevGrid& S, double* pos, double* w, hipStream_t stream)
+{
+    if (S.n <= S.n_data) return 0;
+    k_split_randoms<<<nblocks(S.n - S.n_data), kBlock, 0, stream>>>(S.P, S.inv, S.n_data, S.n, pos, w);
+    return (int)hipGetLastError();
+}
+
 #define HIPCHK(x)                                                                   \
     do {                                                                            \
         hipError_t e_ = (x);                                                        \
@@ -316,6 +358,8 @@ int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, in
     g.n = n;
     g.periodic = periodic ? 1 : 0;
     g.r_max = r_max;
+    g.dmr = dmr ? 1 : 0;
+    g.n_data = dmr ? n_data : n;
     // the gather packs a particle index and a 6-bit image code into one int
     if (n >= (int64_t(1) << 26)) {
         snprintf(errbuf, errlen, "catalog of %lld points exceeds the 2^26-point limit of one grid",
@@ -405,7 +449,7 @@ int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, in
     HIPCHK(hipMalloc(&g.cell_start, sizeof(int32_t) * (ncell + 1)));
     HIPCHK(hipMalloc(&g.perm, sizeof(int32_t) * n));
     HIPCHK(hipMalloc(&g.inv, sizeof(int32_t) * n));
-    HIPCHK(hipMalloc(&g.P, sizeof(double4) * n));
+    HIPCHK(hipMalloc(&g.P, sizeof(double4) * (n + 1)));
     HIPCHK(hipMemsetAsync(d_count, 0, sizeof(int32_t) * ncell, stream));
     k_cell_count<<<nblocks(n), kBlock, 0, stream>>>(d_pos, n, g.ncx, g.ncy, g.ncz, g.ox, g.oy, g.oz,
                                                     g.csx, g.csy, g.csz, d_cell, d_count);
@@ -413,7 +457,7 @@ int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, in
     HIPCHK(hipMemsetAsync(d_count, 0, sizeof(int32_t) * ncell, stream));
     k_scatter<<<nblocks(n), kBlock, 0, stream>>>(d_cell, n, g.cell_start, d_count, g.perm);
     k_cell_sort<<<nblocks(ncell), kBlock, 0, stream>>>(g.cell_start, (int)ncell, g.perm);
-    k_gather_sorted<<<nblocks(n), kBlock, 0, stream>>>(d_pos, wsrc, g.perm, n, g.P, g.inv);
+    k_gather_sorted<<<nblocks(n + 1), kBlock, 0, stream>>>(d_pos, wsrc, g.perm, n, g.P, g.inv);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream));
     rc = 0;

@@ -48,6 +48,7 @@ SIGNATURES = {
     "encore_grid_size": (_I64, [_P]),
     "encore_npcf": (_I, [_P, _P, _I, _I, _I, _P, _U32, _D, _P, _SZ, _P, _I64, _P]),
     "encore_npcf_batch": (_I, [_P, _P, _I, _I, _I, _I, _P, _U32, _P, _SZ, _P]),
+    "encore_npcf_splits": (_I, [_P, _P, _P, _I, _I, _I, _I, _P, _U32, _D, _P, _SZ, _P, _SZ, _P]),
     "encore_npcf_simple": (_I, [_P, _P, _I64, _I, _I, _I, _P, _P, _U32, _P, _SZ]),
     "encore_num_multiplets": (_I64, [_I, _I, _U32]),
     "encore_num_bin_tuples": (_I64, [_I, _I]),
@@ -337,6 +338,59 @@ def npcf_batch(ctx, grids, N, lmax, edges, precision="fp32", allparity=False, no
     _check(lib().encore_npcf_batch(ctx.handle, ctypes.cast(handles, _P), nj, int(N), int(lmax), nbins,
                                    _ptr(edges), flags, _ptr(out), out.size, stream))
     return out[:nj * nlam * nB].reshape(nj, nlam, nB)
+
+
+def npcf_splits(ctx, data_grid, split_grids, N, lmax, edges, precision="fp32", allparity=False,
+                normalize=False, volume=0.0, return_splits=False, stream=None):
+    """encore_npcf_splits: mean over random parts of the D-R multiplets, float64
+    [n_multiplets, n_bin_tuples] (with return_splits, also [n_splits, ...] per part).
+    data_grid: the data alone; split_grids: D + R_k with n_data = len(data)."""
+    edges = _f64(edges, (-1,))
+    nbins = len(edges) - 1
+    flags = PRECISIONS[precision] | (ALLPARITY if allparity else 0) | (NORMALIZE if normalize else 0)
+    nlam = num_multiplets(N, lmax, allparity)
+    nB = num_bin_tuples(N, nbins)
+    ns = len(split_grids)
+    handles = (_P * max(ns, 1))(*[g.handle.value for g in split_grids])
+    out = np.zeros(max(nlam * nB, 1))
+    per = np.zeros(max(ns * nlam * nB, 1)) if return_splits else None
+    _check(lib().encore_npcf_splits(ctx.handle, data_grid.handle, ctypes.cast(handles, _P), ns, int(N),
+                                    int(lmax), nbins, _ptr(edges), flags, float(volume), _ptr(out), out.size,
+                                    _ptr(per) if per is not None else None, per.size if per is not None else 0,
+                                    stream))
+    z = out[:nlam * nB].reshape(nlam, nB)
+    if return_splits:
+        return z, per[:ns * nlam * nB].reshape(ns, nlam, nB)
+    return z
+
+
+def build_split_grids(ctx, data_pos, data_w, rand_pos, rand_w, split_sizes, r_max, box=None):
+    """Grids for npcf_splits: the data alone, then data + each consecutive part of
+    the randoms (split_sizes points each) with D-R weights.  Returns (data_grid,
+    [split grids]); the caller frees them."""
+    data_pos = _f64(data_pos, (-1, 3))
+    data_w = _f64(data_w, (-1,))
+    rand_pos = _f64(rand_pos, (-1, 3))
+    rand_w = _f64(rand_w, (-1,))
+    sizes = [int(x) for x in split_sizes]
+    if sum(sizes) != len(rand_w) or any(x < 1 for x in sizes):
+        raise ValueError("split_sizes must be >= 1 and add up to the number of randoms")
+    nd = len(data_w)
+    gd = build_grid(ctx, data_pos, data_w, r_max, box=box)
+    grids = []
+    try:
+        o = 0
+        for n in sizes:
+            pos = np.concatenate([data_pos, rand_pos[o:o + n]])
+            w = np.concatenate([data_w, rand_w[o:o + n]])
+            grids.append(build_grid(ctx, pos, w, r_max, box=box, n_data=nd))
+            o += n
+    except Exception:
+        for g in grids:
+            g.free()
+        gd.free()
+        raise
+    return gd, grids
 
 
 def debug_alm(ctx, grid, lmax, edges, primaries, precision="fp64", full_launch=False):

@@ -1,0 +1,211 @@
+"""Random-split co-adding on the device (through the C ABI) against the FP64 oracle.
+
+The device gathers the data's share of every data primary's coefficients once and
+adds it to each part's gather of the data primaries against that part's randoms;
+the oracle computes each part's D-R multiplets from scratch.  Both are the same sums in another
+grouping, so the bars are those of the one-catalog parity tests: FP64 1e-10 of
+max|Z|; FP32 2e-5 of max|Z|; split-bf16 5e-5 of max|Z| and
+e_L <= 1e-5 max(kappa_L, 1) + 1e-5.  Against the device's own one-catalog path on
+each part: FP64 1e-12 of max|Z| (rounding order only).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_08722_amd import encore, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print("[gpu-splits] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = encore.Context(0)
+    yield c
+    c.close()
+
+
+def _normwise(zg, zo):
+    num = np.linalg.norm(zg - zo, axis=1)
+    den = np.linalg.norm(zo, axis=1)
+    keep = den > 1e-9 * max(den.max(), 1e-300)
+    return np.where(keep, num / np.where(keep, den, 1.0), 0.0)
+
+
+def _catalog(nd, nr, L, seed):
+    rng = np.random.default_rng(seed)
+    dpos, _ = synth.neyman_scott(nd, L, seed, nbar_parent=3e-4, sigma=2.0)
+    dw = rng.uniform(0.8, 1.2, len(dpos))
+    rpos = rng.uniform(0, L, (nr, 3))
+    rw = rng.uniform(0.5, 1.5, nr)
+    return dpos, dw, rpos, rw
+
+
+def _free(gd, gs):
+    for g in gs:
+        g.free()
+    gd.free()
+
+
+def _check(zg, zo, za, precision):
+    scale = np.max(np.abs(zo))
+    if precision == "fp64":
+        assert np.max(np.abs(zg - zo)) <= 1e-10 * scale
+    elif precision == "fp32":
+        assert np.max(np.abs(zg - zo)) <= 2e-5 * scale
+    else:
+        kappa = np.linalg.norm(za, axis=1) / np.maximum(np.linalg.norm(zo, axis=1), 1e-300)
+        assert np.max(np.abs(zg - zo)) <= 5e-5 * scale
+        assert np.all(_normwise(zg, zo) <= 1e-5 * np.maximum(kappa, 1.0) + 1e-5)
+
+
+CASES = [  # N, lmax, nbins, periodic, allparity, sizes of the random parts
+    (3, 4, 4, True, False, [500, 730, 610]),
+    (4, 3, 5, True, False, [900, 777]),
+    (4, 2, 4, False, True, [640, 500, 700, 333]),
+    (5, 1, 5, True, False, [800]),
+]
+
+
+@pytest.mark.parametrize("N,lmax,nbins,periodic,allp,sizes", CASES)
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "splitbf16"])
+def test_splits_match_oracle(ctx, N, lmax, nbins, periodic, allp, sizes, precision):
+    _say("splits N=%d lmax=%d nbins=%d periodic=%s allparity=%s parts=%s %s"
+         % (N, lmax, nbins, periodic, allp, sizes, precision))
+    L = 60.0
+    dpos, dw, rpos, rw = _catalog(400, sum(sizes), L, 3 * N + lmax)
+    edges = np.linspace(3.0, 22.0, nbins + 1)
+    box = L if periodic else None
+    parity = "all" if allp else "even"
+    gd, gs = encore.build_split_grids(ctx, dpos, dw, rpos, rw, sizes, edges[-1], box=box)
+    try:
+        zg, per = encore.npcf_splits(ctx, gd, gs, N, lmax, edges, precision=precision, allparity=allp,
+                                     return_splits=True)
+    finally:
+        _free(gd, gs)
+    zo, pero = oracle.split_zeta(dpos, dw, rpos, rw, sizes, N, lmax, edges, box=box, parity=parity)
+    assert zg.shape == zo.shape and per.shape == pero.shape
+    # conditioning of each part (sum of magnitudes) for the split-bf16 bar
+    o = 0
+    for k, n in enumerate(sizes):
+        pos = np.concatenate([dpos, rpos[o:o + n]])
+        w = oracle.dmr_weights(dw, rw[o:o + n])
+        za = oracle.zeta(pos, w, N, lmax, edges, box=box, parity=parity, return_abs=True)[1] \
+            if precision == "splitbf16" else None
+        _check(per[k], pero[k], za, precision)
+        o += n
+    assert np.max(np.abs(zg - per.mean(axis=0))) <= 1e-14 * np.max(np.abs(per))
+    _say("  max|dZ|/max|Z| = %.2e" % (np.max(np.abs(zg - zo)) / np.max(np.abs(zo))))
+
+
+def test_splits_equal_one_catalog_path(ctx, monkeypatch):
+    """Each part against encore_npcf on the same D + R_k grid (FP64), with slices
+    of 97 rows so the data gather and every part run over several slices."""
+    _say("splits vs one-catalog path, small slices")
+    monkeypatch.setenv("ENCORE_MAX_SLICE_ROWS", "97")
+    L = 70.0
+    sizes = [700, 1100, 900]
+    dpos, dw, rpos, rw = _catalog(600, sum(sizes), L, 12)
+    edges = np.linspace(4.0, 24.0, 5)
+    gd, gs = encore.build_split_grids(ctx, dpos, dw, rpos, rw, sizes, edges[-1], box=L)
+    try:
+        zg, per = encore.npcf_splits(ctx, gd, gs, 4, 3, edges, precision="fp64", return_splits=True)
+        one = np.array([encore.npcf(ctx, g, 4, 3, edges, precision="fp64") for g in gs])
+    finally:
+        _free(gd, gs)
+    assert np.max(np.abs(per - one)) <= 1e-12 * np.max(np.abs(one))
+    assert np.max(np.abs(zg - one.mean(axis=0))) <= 1e-12 * np.max(np.abs(one))
+
+
+def test_splits_pairs_skip_data_data(ctx):
+    """The accepted-pair count of a split call is the data gather's pairs plus, per
+    part, every pair except the data-data ones: the one-catalog count minus the
+    data-only count, per part (data-data pairs are gathered once, not per part)."""
+    _say("splits pair count")
+    L = 60.0
+    sizes = [500, 650]
+    dpos, dw, rpos, rw = _catalog(500, sum(sizes), L, 4)
+    edges = np.linspace(3.0, 20.0, 4)
+    gd, gs = encore.build_split_grids(ctx, dpos, dw, rpos, rw, sizes, edges[-1], box=L)
+    try:
+        encore.npcf(ctx, gd, 3, 2, edges, precision="fp32")
+        p_dd = ctx.last_timings()["pairs"]
+        p_one = 0.0
+        for g in gs:
+            encore.npcf(ctx, g, 3, 2, edges, precision="fp32")
+            p_one += ctx.last_timings()["pairs"]
+        encore.npcf_splits(ctx, gd, gs, 3, 2, edges, precision="fp32")
+        p_split = ctx.last_timings()["pairs"]
+    finally:
+        _free(gd, gs)
+    assert p_dd > 0
+    assert p_split == p_dd + p_one - len(sizes) * p_dd
+
+
+def test_splits_data_outside_randoms_box(ctx):
+    """Non-periodic catalogs whose randoms cover only part of the data's extent: the
+    data primaries outside the randoms' grid still see every random in range."""
+    _say("splits, data beyond the randoms' bounding box")
+    rng = np.random.default_rng(31)
+    dpos = rng.uniform(0.0, 80.0, (500, 3))
+    dw = rng.uniform(0.8, 1.2, 500)
+    rpos = rng.uniform(20.0, 60.0, (1200, 3))
+    rw = rng.uniform(0.5, 1.5, 1200)
+    sizes = [500, 700]
+    edges = np.linspace(3.0, 18.0, 5)
+    gd, gs = encore.build_split_grids(ctx, dpos, dw, rpos, rw, sizes, edges[-1])
+    try:
+        zg = encore.npcf_splits(ctx, gd, gs, 4, 2, edges, precision="fp64")
+    finally:
+        _free(gd, gs)
+    zo, _ = oracle.split_zeta(dpos, dw, rpos, rw, sizes, 4, 2, edges)
+    assert np.max(np.abs(zg - zo)) <= 1e-10 * np.max(np.abs(zo))
+
+
+def test_splits_errors(ctx):
+    _say("splits errors")
+    L = 50.0
+    dpos, dw, rpos, rw = _catalog(200, 600, L, 6)
+    edges = np.linspace(3.0, 15.0, 4)
+    gd, gs = encore.build_split_grids(ctx, dpos, dw, rpos, rw, [300, 300], edges[-1], box=L)
+    bad = []
+    try:
+        # no parts
+        with pytest.raises(encore.EncoreError) as e:
+            encore.npcf_splits(ctx, gd, [], 3, 2, edges)
+        assert e.value.code == encore.EINVAL
+        # the data grid built as a D-R catalog
+        g_dmr = encore.build_grid(ctx, np.concatenate([dpos, rpos]), np.concatenate([dw, rw]), edges[-1],
+                                  box=L, n_data=200)
+        bad.append(g_dmr)
+        with pytest.raises(encore.EncoreError) as e:
+            encore.npcf_splits(ctx, g_dmr, gs, 3, 2, edges)
+        assert e.value.code == encore.EINVAL
+        # a part whose data are in another order
+        perm = np.random.default_rng(1).permutation(200)
+        g_perm = encore.build_grid(ctx, np.concatenate([dpos[perm], rpos[:300]]),
+                                   np.concatenate([dw[perm], rw[:300]]), edges[-1], box=L, n_data=200)
+        bad.append(g_perm)
+        with pytest.raises(encore.EncoreError) as e:
+            encore.npcf_splits(ctx, gd, [gs[0], g_perm], 3, 2, edges)
+        assert e.value.code == encore.EINVAL
+        # a part without the periodic box
+        g_open = encore.build_grid(ctx, np.concatenate([dpos, rpos[:300]]), np.concatenate([dw, rw[:300]]),
+                                   edges[-1], n_data=200)
+        bad.append(g_open)
+        with pytest.raises(encore.EncoreError) as e:
+            encore.npcf_splits(ctx, gd, [g_open], 3, 2, edges)
+        assert e.value.code == encore.EINVAL
+        # the valid call still works after the refusals
+        z = encore.npcf_splits(ctx, gd, gs, 3, 2, edges, precision="fp64")
+        assert np.all(np.isfinite(z))
+    finally:
+        for g in bad:
+            g.free()
+        _free(gd, gs)
