@@ -300,7 +300,7 @@ def main():
     if not args.no_tune:
         t0 = time.perf_counter()
         tuned = encore.autotune(ctx, cfg["pos"], cfg["w"], N, L, edges, box=cfg["box"],
-                                n_data=cfg["n_data"], precision=args.precision, n_sample=32768)
+                                n_data=cfg["n_data"], precision=args.precision, n_sample=131072)
         tuned["tuning_s"] = time.perf_counter() - t0
         log("autotune: %s" % tuned)
 
