@@ -123,6 +123,29 @@ def test_splits_equal_one_catalog_path(ctx, monkeypatch):
     assert np.max(np.abs(zg - one.mean(axis=0))) <= 1e-12 * np.max(np.abs(one))
 
 
+def test_splits_dense_equal_batch_fp64(ctx):
+    """A denser catalog (30k clustered data, three parts of 45k randoms, periodic
+    200 Mpc/h, 4PCF lmax 3): every part's N from the co-added call equals the
+    one-catalog path's on the same D + R_k grid (FP64, rounding order only)."""
+    _say("splits dense, FP64, vs batched one-catalog path")
+    L = 200.0
+    sizes = [45000, 45000, 45000]
+    rng = np.random.default_rng(77)
+    dpos, _ = synth.neyman_scott(30000, L, 77, nbar_parent=2e-4, sigma=3.0)
+    dw = rng.uniform(0.8, 1.2, len(dpos))
+    rpos = rng.uniform(0, L, (sum(sizes), 3))
+    rw = rng.uniform(0.5, 1.5, sum(sizes))
+    edges = np.linspace(5.0, 40.0, 6)
+    gd, gs = encore.build_split_grids(ctx, dpos, dw, rpos, rw, sizes, edges[-1], box=L)
+    try:
+        zg, per = encore.npcf_splits(ctx, gd, gs, 4, 3, edges, precision="fp64", return_splits=True)
+        zb = encore.npcf_batch(ctx, gs, 4, 3, edges, precision="fp64")
+    finally:
+        _free(gd, gs)
+    assert np.max(np.abs(per - zb)) <= 1e-12 * np.max(np.abs(zb))
+    assert np.max(np.abs(zg - zb.mean(axis=0))) <= 1e-12 * np.max(np.abs(zb))
+
+
 def test_splits_pairs_skip_data_data(ctx):
     """The accepted-pair count of a split call is the data gather's pairs plus, per
     part, every pair except the data-data ones: the one-catalog count minus the
