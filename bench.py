@@ -210,6 +210,7 @@ def splits_leg(ctx, edges, precision, nparts, seed=6000):
                      "coadded_s": t_split, "batch_s": t_batch, "speedup": t_batch / t_split,
                      "primaries_per_s": prim / t_split, "primaries_per_s_batch": prim / t_batch,
                      "pairs_coadded": tm_s["pairs"], "pairs_batch": tm_b["pairs"],
+                     "data_part_kept": bool(tm_s["pairs"] < tm_b["pairs"]),
                      "gather_ms": tm_s["gather_ms"], "gather_ms_batch": tm_b["gather_ms"],
                      "max_rel_diff_vs_batch": float(np.max(np.abs(zs - zm)) / np.max(np.abs(zm))),
                      "workload": "200k Neyman-Scott data + %d random parts of 300k uniform points (D-R per "

@@ -360,7 +360,11 @@ int encore_edge_correct(encore_ctx* ctx, int npcf, int lmax, int nbins, uint32_t
  * part the data primaries are then gathered against the part's randoms alone (a
  * grid of R_k with its D-R weights, built from the split grid on first use and
  * freed with it) and get the kept rows added; the random primaries are gathered
- * against D + R_k.  Data-data pairs are thus visited once, not K times.
+ * against D + R_k.  Data-data pairs are thus visited once, not K times.  This is
+ * done when the parts hold at least 6,000 points per r_max^3 on average (r_max =
+ * edges[nbins]); below that a work item's cost is mostly its cell geometry, not its
+ * pairs, and each part runs as one catalog (same result up to rounding order).  The
+ * environment variable ENCORE_SPLIT_CACHE=1 / 0 forces either way.
  *
  *  data_grid   grid of the data alone (built without ENCORE_DMR).
  *  split_grids [nsplit] grids built with ENCORE_DMR on D + R_k: the first n_data
@@ -374,7 +378,7 @@ int encore_edge_correct(encore_ctx* ctx, int npcf, int lmax, int nbins, uint32_t
  *  zeta_splits NULL, or host FP64 [nsplit][n_multiplets * n_bin_tuples]: N^(k).
  *  stream      as encore_npcf.
  * Timings: [1] includes the data gather, [5] its pairs; [0] excludes building
- * the randoms-only grids.
+ * the randoms-only grids (with the data part kept).
  * Errors: EINVAL (grids that do not match as above), ESIZE, ENOMEM, EDEVICE,
  * EUNSUPPORTED as encore_npcf.
  */

@@ -115,6 +115,10 @@ int check_grids(const encore_grid* const* grids, int njobs, const encore_ctx* ct
     return ENCORE_OK;
 }
 
+// points per r_max^3 (averaged over the parts) from which encore_npcf_splits keeps
+// the data part of a~: measured break-even between 2,000 (0.95x) and 16,000 (1.09x)
+constexpr double kSplitCacheDensity = 6000.0;
+
 struct JobRows {
     const encore_grid* grid;
     const int32_t* prim;   // device
@@ -467,6 +471,39 @@ int encore_npcf_splits(encore_ctx* ctx, const encore_grid* data_grid, const enco
         if (bad)
             return fail(ENCORE_EINVAL, "a split grid's first n_data points differ from the data grid's "
                                        "(positions and weights, in input order)");
+        // Keeping the data part pays where pairs dominate a work item's cost (dense
+        // catalogs); at a few thousand points per r_max^3 the item's geometry work
+        // dominates, and visiting the data-data pairs in every part costs less than
+        // the extra data-only gather.  ENCORE_SPLIT_CACHE=0 / 1 forces the choice.
+        double dens = 0.0;
+        for (int k = 0; k < nsplit; ++k) {
+            const DevGrid& S = split_grids[k]->g;
+            const double V = (S.ncx * S.csx) * (S.ncy * S.csy) * (S.ncz * S.csz);
+            dens += (double)S.n / V / nsplit;
+        }
+        const double rmax = edges[nbins];
+        bool use_cache = dens * rmax * rmax * rmax >= kSplitCacheDensity;
+        if (const char* e = getenv("ENCORE_SPLIT_CACHE")) use_cache = atoi(e) != 0;
+        if (!use_cache) {
+            // each part as one catalog; the mean in part order
+            int64_t nmax = 0;
+            for (int k = 0; k < nsplit; ++k) nmax = std::max<int64_t>(nmax, split_grids[k]->g.n);
+            if ((rc2 = ensure(x.prim, sizeof(int32_t) * (size_t)nmax))) return rc2;
+            HIPTRY((hipError_t)launch_iota((int32_t*)x.prim.p, nmax, s));
+            HIPTRY(hipEventRecord(x.ev[0], s));
+            std::vector<JobRows> jobs(nsplit);
+            for (int k = 0; k < nsplit; ++k)
+                jobs[k] = JobRows{split_grids[k], (const int32_t*)x.prim.p, split_grids[k]->g.n};
+            std::vector<double> zk(need * (size_t)nsplit);
+            if ((rc2 = run_jobs(ctx, jobs, pl, flags, edges, volume, zk.data()))) return rc2;
+            for (size_t i = 0; i < need; ++i) {
+                double acc = 0.0;
+                for (int k = 0; k < nsplit; ++k) acc += zk[(size_t)k * need + i];
+                zeta[i] = acc / nsplit;
+            }
+            if (zeta_splits) std::copy(zk.begin(), zk.end(), zeta_splits);
+            return ENCORE_OK;
+        }
         // each part's randoms alone (their D-R weights), built once per split grid
         for (int k = 0; k < nsplit; ++k) {
             const encore_grid* sg = split_grids[k];

@@ -1,8 +1,9 @@
 """Random-split co-adding on the device (through the C ABI) against the FP64 oracle.
 
-The device gathers the data's share of every data primary's coefficients once and
-adds it to each part's gather of the data primaries against that part's randoms;
-the oracle computes each part's D-R multiplets from scratch.  Both are the same sums in another
+With the data part kept (ENCORE_SPLIT_CACHE=1) the device gathers the data's share
+of every data primary's coefficients once and adds it to each part's gather of the
+data primaries against that part's randoms; without it (=0) each part runs as one
+catalog.  The oracle computes each part's D-R multiplets from scratch.  Both are the same sums in another
 grouping, so the bars are those of the one-catalog parity tests: FP64 1e-10 of
 max|Z|; FP32 2e-5 of max|Z|; split-bf16 5e-5 of max|Z| and
 e_L <= 1e-5 max(kappa_L, 1) + 1e-5.  Against the device's own one-catalog path on
@@ -75,9 +76,11 @@ CASES = [  # N, lmax, nbins, periodic, allparity, sizes of the random parts
 
 @pytest.mark.parametrize("N,lmax,nbins,periodic,allp,sizes", CASES)
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "splitbf16"])
-def test_splits_match_oracle(ctx, N, lmax, nbins, periodic, allp, sizes, precision):
-    _say("splits N=%d lmax=%d nbins=%d periodic=%s allparity=%s parts=%s %s"
-         % (N, lmax, nbins, periodic, allp, sizes, precision))
+@pytest.mark.parametrize("cache", ["1", "0"])
+def test_splits_match_oracle(ctx, monkeypatch, N, lmax, nbins, periodic, allp, sizes, precision, cache):
+    _say("splits N=%d lmax=%d nbins=%d periodic=%s allparity=%s parts=%s %s cache=%s"
+         % (N, lmax, nbins, periodic, allp, sizes, precision, cache))
+    monkeypatch.setenv("ENCORE_SPLIT_CACHE", cache)
     L = 60.0
     dpos, dw, rpos, rw = _catalog(400, sum(sizes), L, 3 * N + lmax)
     edges = np.linspace(3.0, 22.0, nbins + 1)
@@ -109,6 +112,7 @@ def test_splits_equal_one_catalog_path(ctx, monkeypatch):
     of 97 rows so the data gather and every part run over several slices."""
     _say("splits vs one-catalog path, small slices")
     monkeypatch.setenv("ENCORE_MAX_SLICE_ROWS", "97")
+    monkeypatch.setenv("ENCORE_SPLIT_CACHE", "1")
     L = 70.0
     sizes = [700, 1100, 900]
     dpos, dw, rpos, rw = _catalog(600, sum(sizes), L, 12)
@@ -123,11 +127,12 @@ def test_splits_equal_one_catalog_path(ctx, monkeypatch):
     assert np.max(np.abs(zg - one.mean(axis=0))) <= 1e-12 * np.max(np.abs(one))
 
 
-def test_splits_dense_equal_batch_fp64(ctx):
+def test_splits_dense_equal_batch_fp64(ctx, monkeypatch):
     """A denser catalog (30k clustered data, three parts of 45k randoms, periodic
-    200 Mpc/h, 4PCF lmax 3): every part's N from the co-added call equals the
-    one-catalog path's on the same D + R_k grid (FP64, rounding order only)."""
+    200 Mpc/h, 4PCF lmax 3): every part's N from the co-added call (data part kept)
+    equals the one-catalog path's on the same D + R_k grid (FP64, rounding order only)."""
     _say("splits dense, FP64, vs batched one-catalog path")
+    monkeypatch.setenv("ENCORE_SPLIT_CACHE", "1")
     L = 200.0
     sizes = [45000, 45000, 45000]
     rng = np.random.default_rng(77)
@@ -146,10 +151,11 @@ def test_splits_dense_equal_batch_fp64(ctx):
     assert np.max(np.abs(zg - zb.mean(axis=0))) <= 1e-12 * np.max(np.abs(zb))
 
 
-def test_splits_pairs_skip_data_data(ctx):
-    """The accepted-pair count of a split call is the data gather's pairs plus, per
-    part, every pair except the data-data ones: the one-catalog count minus the
-    data-only count, per part (data-data pairs are gathered once, not per part)."""
+def test_splits_pairs_skip_data_data(ctx, monkeypatch):
+    """With the data part kept, the accepted-pair count of a split call is the data
+    gather's pairs plus, per part, every pair except the data-data ones: the
+    one-catalog count minus the data-only count, per part (data-data pairs are
+    gathered once, not per part).  Without it, the one-catalog counts."""
     _say("splits pair count")
     L = 60.0
     sizes = [500, 650]
@@ -163,18 +169,52 @@ def test_splits_pairs_skip_data_data(ctx):
         for g in gs:
             encore.npcf(ctx, g, 3, 2, edges, precision="fp32")
             p_one += ctx.last_timings()["pairs"]
+        monkeypatch.setenv("ENCORE_SPLIT_CACHE", "1")
         encore.npcf_splits(ctx, gd, gs, 3, 2, edges, precision="fp32")
         p_split = ctx.last_timings()["pairs"]
+        monkeypatch.setenv("ENCORE_SPLIT_CACHE", "0")
+        encore.npcf_splits(ctx, gd, gs, 3, 2, edges, precision="fp32")
+        p_plain = ctx.last_timings()["pairs"]
     finally:
         _free(gd, gs)
     assert p_dd > 0
     assert p_split == p_dd + p_one - len(sizes) * p_dd
+    assert p_plain == p_one
 
 
-def test_splits_data_outside_randoms_box(ctx):
+def test_splits_default_choice(ctx, monkeypatch):
+    """Without ENCORE_SPLIT_CACHE the data part is kept only for dense parts (at
+    least 6,000 points per r_max^3): a sparse catalog gathers every part's pairs, a
+    dense one visits the data-data pairs once; both equal the batched one-catalog
+    path (FP64)."""
+    _say("splits default choice")
+    monkeypatch.delenv("ENCORE_SPLIT_CACHE", raising=False)
+    L = 60.0
+    rng = np.random.default_rng(90)
+    for nd, nr, dense in ((800, 1200, False), (70000, 105000, True)):
+        dpos = rng.uniform(0, L, (nd, 3))
+        dw = rng.uniform(0.8, 1.2, nd)
+        rpos = rng.uniform(0, L, (2 * nr, 3))
+        rw = rng.uniform(0.5, 1.5, 2 * nr)
+        edges = np.linspace(4.0, 20.0, 4)
+        assert ((nd + nr) / L ** 3 * 20.0 ** 3 >= 6000) == dense
+        gd, gs = encore.build_split_grids(ctx, dpos, dw, rpos, rw, [nr, nr], edges[-1], box=L)
+        try:
+            zg = encore.npcf_splits(ctx, gd, gs, 3, 2, edges, precision="fp64")
+            p_split = ctx.last_timings()["pairs"]
+            zb = encore.npcf_batch(ctx, gs, 3, 2, edges, precision="fp64")
+            p_batch = ctx.last_timings()["pairs"]
+        finally:
+            _free(gd, gs)
+        assert np.max(np.abs(zg - zb.mean(axis=0))) <= 1e-12 * np.max(np.abs(zb))
+        assert (p_split < p_batch) == dense
+
+
+def test_splits_data_outside_randoms_box(ctx, monkeypatch):
     """Non-periodic catalogs whose randoms cover only part of the data's extent: the
     data primaries outside the randoms' grid still see every random in range."""
     _say("splits, data beyond the randoms' bounding box")
+    monkeypatch.setenv("ENCORE_SPLIT_CACHE", "1")
     rng = np.random.default_rng(31)
     dpos = rng.uniform(0.0, 80.0, (500, 3))
     dw = rng.uniform(0.8, 1.2, 500)
