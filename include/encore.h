@@ -356,7 +356,8 @@ int encore_edge_correct(encore_ctx* ctx, int npcf, int lmax, int nbins, uint32_t
  * encore_npcf, and the mean (1/K) sum_k N^(k) is returned.  The data's share of
  * the harmonic coefficients of every data primary is the same in each part: it is
  * gathered ONCE (from data_grid) and kept on the device (n_data rows of
- * nbins * (lmax+1)(lmax+2)/2 complex values, FP64 or FP32 by precision).  In each
+ * nbins * (lmax+1)(lmax+2)/2 complex values, FP64 or FP32 by precision, in a
+ * grow-only workspace of the context, freed with it).  In each
  * part the data primaries are then gathered against the part's randoms alone (a
  * grid of R_k with its D-R weights, built from the split grid on first use and
  * freed with it) and get the kept rows added; the random primaries are gathered
