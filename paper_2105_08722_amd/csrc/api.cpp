@@ -636,7 +636,7 @@ int encore_autotune(encore_ctx* ctx, const double* pos, const double* w, int64_t
     const int gprec = pl.prec == 0 ? 0 : 1;
     const std::vector<int> nbgs = gather_nbg_options(lmax, gprec);
     // cell shapes tried: (y/z divisor of r_max, extra x subdivision); the default first
-    static const double kCells[][2] = {{6, 4}, {6, 8}, {8, 4}, {8, 8}, {8, 2}, {5, 4}, {4, 6}, {10, 4}};
+    static const double kCells[][2] = {{5, 8}, {5, 6}, {6, 8}, {5, 4}, {4, 6}, {6, 4}, {8, 4}, {4, 8}};
     // The sample: 16 runs of consecutive cell-sorted primaries spread over the grid,
     // so that neighbouring work items share cells as in a full pass (a scattered
     // sample would time cache misses that a full pass does not have).

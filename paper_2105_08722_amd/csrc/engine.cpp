@@ -500,7 +500,7 @@ double cell_divisor(double tuned)
         if (v >= 1.0 && v <= 32.0) return v;
     }
     if (tuned >= 1.0 && tuned <= 32.0) return tuned;
-    return 6.0;   // cell side r_max / 6
+    return 5.0;   // cell side r_max / 5
 }
 
 double cell_x_subdiv(double tuned)
@@ -514,7 +514,7 @@ double cell_x_subdiv(double tuned)
         if (v >= 1 && v <= 8) return v;
     }
     if (tuned >= 1.0 && tuned <= 8.0) return tuned;
-    return 4.0;
+    return 8.0;
 }
 
 int ctx_nbg(encore_ctx* ctx, const NpcfPlan& pl)
