@@ -262,8 +262,10 @@ int encore_mfma_plan_stats(int npcf, int lmax, int nbins, uint32_t flags, int64_
 
 /*
  * Autotuner of the launch shapes: builds trial grids of the catalog (host arrays,
- * as encore_build_grid) with several cell shapes (cell side r_max/d on y and z,
- * r_max/(d*s) on x, where one cell row is a contiguous particle range) and times,
+ * as encore_build_grid) with 8 cell shapes (cell side r_max/d on y and z,
+ * r_max/(d*s) on x, where one cell row is a contiguous particle range; (d, s) =
+ * (5, 8) -- the default without tuning --, (5, 6), (6, 8), (5, 4), (4, 6), (6, 4),
+ * (8, 4), (4, 8)) and times,
  * for each, the gather + coupling of this job (as encore_npcf) over a sample of
  * n_sample primaries (16 runs of consecutive cell-sorted primaries spread over the
  * grid, so that neighbouring work items share cells as in a full pass), for every compiled
