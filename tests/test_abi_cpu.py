@@ -130,3 +130,12 @@ def test_host_argument_errors():
             encore.lib().encore_multiplet_table(4, 5, 0, None, 0))
     assert e.value.code == encore.ESIZE
     assert "needs" in str(e.value)
+
+
+def test_split_grids_refuse_bad_sizes():
+    """build_split_grids checks the part sizes before touching the device."""
+    rng = np.random.default_rng(0)
+    d, r = rng.uniform(0, 10, (5, 3)), rng.uniform(0, 10, (9, 3))
+    for sizes in ([4, 4], [9, 0], [10], [-1, 10]):
+        with pytest.raises(ValueError):
+            encore.build_split_grids(None, d, np.ones(5), r, np.ones(9), sizes, 2.0)

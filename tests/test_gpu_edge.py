@@ -128,3 +128,16 @@ def test_edge_end_to_end_survey_window(ctx):
     # the window couples multiplets: M is not the periodic scaled identity
     n = M.shape[1]
     assert np.max(np.abs(M - (4 * np.pi) ** -1.5 * np.eye(n)[None])) > 1e-4
+
+
+def test_edge_timings(ctx):
+    """After an edge correction the timing slots hold its device time alone."""
+    _say("edge correction timings")
+    N, lmax, nbins = 4, 2, 4
+    nB = encore.num_bin_tuples(N, nbins)
+    Nm, R = _window_multiplets(N, lmax, nB, "even", 3)
+    encore.edge_correct(ctx, N, lmax, nbins, Nm, R)
+    t = ctx.last_timings()
+    assert t["total_ms"] > 0.0
+    assert t["gather_ms"] == 0.0 and t["couple_ms"] == 0.0 and t["contract_ms"] == 0.0
+    assert t["batches"] == 0 and t["pairs"] == 0
