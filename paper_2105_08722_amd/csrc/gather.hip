@@ -12,14 +12,19 @@
 //  2. Candidate test, 64 candidates per step: separation in FP64 exactly as the
 //     definition orders it (x_j - x_i, then the periodic image), r^2 =
 //     (dx*dx + dy*dy) + dz*dz without contraction, bin by comparing r^2 with the
-//     squared edges.  Accepted pairs are pushed into one LDS ring per bin
-//     (slot from an LDS atomic).
+//     squared edges.  Accepted pairs are pushed into one LDS ring per bin (slots
+//     from lane-mask ballots and mbcnt ranks, no atomics).
 //  3. Drain: whenever a ring holds 64 pairs, all 64 lanes pop one pair each, form
 //     Y_lm by the monic Legendre recurrence in z times (x + i y)^m and add w Y into
 //     per-lane register accumulators of that bin (the bin is wave-uniform, so the
 //     register index is static).
-//  4. Reduce the 64 lanes' accumulators through LDS (FP64 sums), scale by the
-//     recurrence normalisation kappa_lm and write the complex coefficients.
+//  4. Reduce the 64 lanes' accumulators (FP32: cross-lane swaps and row
+//     rotations; FP64: through LDS), scale by the recurrence normalisation
+//     kappa_lm and write the complex coefficients.
+//
+// Primaries are read from the segment's primary array (the catalog's own points,
+// or another grid's), candidates from its cell-sorted points; lanes past the last
+// candidate take the grid's NaN sentinel point, which no bin accepts.
 //
 // Y_lm = N_lm(z) (x + i y)^m for a unit vector (Condon-Shortley phase inside N_lm);
 // N_lm = kappa_lm R_lm with R_mm = 1, R_{m+1,m} = z, R_lm = z R_{l-1,m} - gamma_lm R_{l-2,m}.
@@ -558,7 +563,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         //      Positions past the batch take the grid's sentinel point (NaN position:
         //      every bin compare is false).  Piece descriptors are held 64 at a time
         //      in VGPRs (lane l: piece gbase + l) and read with readlane.
-        const unsigned self_entry = (unsigned)g.nP | ((unsigned)kCenterCode << kCodeShift);
+        const unsigned fill_entry = (unsigned)g.nP | ((unsigned)kCenterCode << kCodeShift);
         int gbase = 0;
         unsigned dl_v = 0;
         int fs_v = 0;
@@ -588,7 +593,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         }
         // entries of the chunk at p0 (uniform, increasing from call to call)
         auto fetch = [&](int p0) -> unsigned {
-            if (p0 >= total) return self_entry;
+            if (p0 >= total) return fill_entry;
             while (fnext <= p0) {
                 ++sg;
                 dcur = dnext;
@@ -606,7 +611,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
                     desc(sg + 1, dnext, fnext);
                 } while (fnext < p0 + kWave);
             }
-            if (p0 + kWave > total && (int)pl >= total) me = self_entry;
+            if (p0 + kWave > total && (int)pl >= total) me = fill_entry;
             return me;
         };
         {
