@@ -175,29 +175,29 @@ def served_leg(ctx, edges, njobs, rate, seed=5000):
 def splits_leg(ctx, edges, precision, nparts, seed=6000):
     """Random-split co-adding (Section 4.2): 200k Neyman-Scott data and random parts
     of 1.5 N_D uniform points each, 4PCF lmax=5, in two regimes: the benchmark's
-    density (periodic 1000 Mpc/h, nparts parts) and 8x that density (500 Mpc/h, 4
-    parts).  One encore_npcf_splits call (the data part of a~ gathered once; per
+    density (periodic 1000 Mpc/h, nparts parts, the bench precision) and 8x that
+    density (500 Mpc/h, 4 parts, FP64: the precision in which the data part is kept).  One encore_npcf_splits call (the data part of a~ gathered once; per
     part, data primaries against the part's randoms only) against one
     encore_npcf_batch call over the same D + R_k catalogs (every pair of every part
     gathered)."""
     import numpy as np
     from paper_2105_08722_amd import encore, synth
     out = {}
-    for name, box, K in (("box1000", 1000.0, nparts), ("box500", 500.0, 4)):
+    for name, box, K, prec in (("box1000", 1000.0, nparts, precision), ("box500_fp64", 500.0, 4, "fp64")):
         nd = 200_000
         nr = 3 * nd // 2
         dpos, dw = synth.neyman_scott(nd, box, seed)
         rpos, rw = synth.uniform_box(K * nr, box, seed + 7919)
         gd, gs = encore.build_split_grids(ctx, dpos, dw, rpos, rw, [nr] * K, edges[-1], box=box)
         try:
-            encore.npcf_splits(ctx, gd, gs, 4, 5, edges, precision=precision)   # warm; builds the randoms-only grids
+            encore.npcf_splits(ctx, gd, gs, 4, 5, edges, precision=prec)   # warm; builds the randoms-only grids
             t0 = time.perf_counter()
-            zs = encore.npcf_splits(ctx, gd, gs, 4, 5, edges, precision=precision)
+            zs = encore.npcf_splits(ctx, gd, gs, 4, 5, edges, precision=prec)
             t_split = time.perf_counter() - t0
             tm_s = ctx.last_timings()
-            encore.npcf_batch(ctx, gs, 4, 5, edges, precision=precision)   # warm
+            encore.npcf_batch(ctx, gs, 4, 5, edges, precision=prec)   # warm
             t0 = time.perf_counter()
-            zb = encore.npcf_batch(ctx, gs, 4, 5, edges, precision=precision)
+            zb = encore.npcf_batch(ctx, gs, 4, 5, edges, precision=prec)
             t_batch = time.perf_counter() - t0
             tm_b = ctx.last_timings()
         finally:
@@ -206,7 +206,7 @@ def splits_leg(ctx, edges, precision, nparts, seed=6000):
             gd.free()
         zm = zb.mean(axis=0)
         prim = K * (nd + nr)
-        out[name] = {"parts": K, "n_data": nd, "randoms_per_part": nr, "precision": precision,
+        out[name] = {"parts": K, "n_data": nd, "randoms_per_part": nr, "precision": prec,
                      "coadded_s": t_split, "batch_s": t_batch, "speedup": t_batch / t_split,
                      "primaries_per_s": prim / t_split, "primaries_per_s_batch": prim / t_batch,
                      "pairs_coadded": tm_s["pairs"], "pairs_batch": tm_b["pairs"],

@@ -364,10 +364,13 @@ int encore_edge_correct(encore_ctx* ctx, int npcf, int lmax, int nbins, uint32_t
  * grid of R_k with its D-R weights, built from the split grid on first use and
  * freed with it) and get the kept rows added; the random primaries are gathered
  * against D + R_k.  Data-data pairs are thus visited once, not K times.  This is
- * done when the parts hold at least 6,000 points per r_max^3 on average (r_max =
- * edges[nbins]); below that a work item's cost is mostly its cell geometry, not its
- * pairs, and each part runs as one catalog (same result up to rounding order).  The
- * environment variable ENCORE_SPLIT_CACHE=1 / 0 forces either way.
+ * done with ENCORE_PREC_FP64 when the parts hold at least 6,000 points per r_max^3
+ * on average (r_max = edges[nbins]); below that a work item's cost is mostly its
+ * cell geometry, not its pairs, and in the FP32 modes the separate data and random
+ * shares of a coefficient, each much larger than their D-R sum, would cost accuracy
+ * (1.6e-3 instead of 1e-6 of max|Z| measured on a dense catalog).  Otherwise each
+ * part runs as one catalog (same result up to rounding order).  The environment
+ * variable ENCORE_SPLIT_CACHE=1 / 0 forces either way.
  *
  *  data_grid   grid of the data alone (built without ENCORE_DMR).
  *  split_grids [nsplit] grids built with ENCORE_DMR on D + R_k: the first n_data

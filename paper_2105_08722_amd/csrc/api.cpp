@@ -474,7 +474,11 @@ int encore_npcf_splits(encore_ctx* ctx, const encore_grid* data_grid, const enco
         // Keeping the data part pays where pairs dominate a work item's cost (dense
         // catalogs); at a few thousand points per r_max^3 the item's geometry work
         // dominates, and visiting the data-data pairs in every part costs less than
-        // the extra data-only gather.  ENCORE_SPLIT_CACHE=0 / 1 forces the choice.
+        // the extra data-only gather.  It is only taken with FP64 coefficients: the
+        // data and random shares of a D-R coefficient are each far larger than their
+        // sum, so adding two FP32 sums loses what one interleaved FP32 sum keeps
+        // (measured: 1.6e-3 against 1e-6 of max|Z| on a dense catalog).
+        // ENCORE_SPLIT_CACHE=0 / 1 forces the choice.
         double dens = 0.0;
         for (int k = 0; k < nsplit; ++k) {
             const DevGrid& S = split_grids[k]->g;
@@ -482,7 +486,7 @@ int encore_npcf_splits(encore_ctx* ctx, const encore_grid* data_grid, const enco
             dens += (double)S.n / V / nsplit;
         }
         const double rmax = edges[nbins];
-        bool use_cache = dens * rmax * rmax * rmax >= kSplitCacheDensity;
+        bool use_cache = pl.prec == 0 && dens * rmax * rmax * rmax >= kSplitCacheDensity;
         if (const char* e = getenv("ENCORE_SPLIT_CACHE")) use_cache = atoi(e) != 0;
         if (!use_cache) {
             // each part as one catalog; the mean in part order

@@ -183,10 +183,10 @@ def test_splits_pairs_skip_data_data(ctx, monkeypatch):
 
 
 def test_splits_default_choice(ctx, monkeypatch):
-    """Without ENCORE_SPLIT_CACHE the data part is kept only for dense parts (at
-    least 6,000 points per r_max^3): a sparse catalog gathers every part's pairs, a
-    dense one visits the data-data pairs once; both equal the batched one-catalog
-    path (FP64)."""
+    """Without ENCORE_SPLIT_CACHE the data part is kept only in FP64 and for dense
+    parts (at least 6,000 points per r_max^3): a sparse catalog gathers every part's
+    pairs, a dense one visits the data-data pairs once; both equal the batched
+    one-catalog path (FP64).  FP32 gathers every part's pairs."""
     _say("splits default choice")
     monkeypatch.delenv("ENCORE_SPLIT_CACHE", raising=False)
     L = 60.0
@@ -208,6 +208,15 @@ def test_splits_default_choice(ctx, monkeypatch):
             _free(gd, gs)
         assert np.max(np.abs(zg - zb.mean(axis=0))) <= 1e-12 * np.max(np.abs(zb))
         assert (p_split < p_batch) == dense
+        if dense:
+            # the FP32 modes never keep the data part by default (accuracy)
+            gd, gs = encore.build_split_grids(ctx, dpos, dw, rpos, rw, [nr, nr], edges[-1], box=L)
+            try:
+                encore.npcf_splits(ctx, gd, gs, 3, 2, edges, precision="fp32")
+                p32 = ctx.last_timings()["pairs"]
+            finally:
+                _free(gd, gs)
+            assert p32 == p_batch
 
 
 def test_splits_data_outside_randoms_box(ctx, monkeypatch):
