@@ -331,10 +331,14 @@ int encore_debug_alm(encore_ctx* ctx, const encore_grid* grid, int lmax, int nbi
  * edge-corrected-NPCF).  From the multiplets N_L^B of the data-minus-randoms field
  * and R_L^B of the randoms alone (both as encore_npcf returns them, same flags),
  * builds per bin tuple B the coupling matrix
- *     M_{L L''}(B) = sum_{L'} (R_{L'}^B / R_0^B) E(L'') G^{L L' L''}
+ *     M_{L L''}(B) = sum_{L'} (R_{L'}^B / R_0^B) s(L, L') E(L'') G^{L L' L''}
  * with the generalized Gaunt integrals G of eq. generalized-gaunt-def (closed forms
  * of Appendix A: N = 3, 4, 5), and solves N_{L''}^B / R_0^B = sum_L zeta_L^B M_{L L''}
  * for zeta on the device (FP64, Gaussian elimination with partial pivoting and back substitution).
+ * The paper's equations are written for the complex multiplets; odd multiplets are
+ * imaginary and are passed and returned as their imaginary parts, which gives the
+ * factor s(L, L') = i * i = -1 to terms with L and L' both odd (+1 otherwise).  In
+ * these real numbers M is symmetric.
  * L, L', L'' run over the multiplets of (npcf, lmax, flags & ENCORE_ALLPARITY);
  * zeta is returned for those with every principal ell <= lmax_out (the paper
  * measures at lmax_out + 1), in the same order.

@@ -10,7 +10,12 @@ Follows Section 3.2 (Edge Correction) of the paper:
   `gaunt_closed` is the closed form of Appendix A for N = 3, 4, 5 (3j and 9j
   symbols); the two are pinned against each other in tests/test_edge_oracle.py.
 * coupling matrix M_{L L''}(B) = sum_{L'} f_{L'}(B) E(L'') G^{L L' L''} with
-  f_{L'} = R_{L'} / R_0 (eq. edge-correction-matrix);
+  f_{L'} = R_{L'} / R_0 (eq. edge-correction-matrix).  The paper writes it for the
+  complex multiplets; odd multiplets are imaginary (Section 3.1) and are carried
+  here, as everywhere in this package, by their imaginary parts.  Written for
+  those real numbers the sum gains i * i = -1 in every term whose L and L' are
+  both odd (G vanishes unless L, L', L'' hold an even number of odd multiplets, so
+  no other factor of i is left over);
 * the edge-corrected estimator solves N_{L''} / R_0 = sum_L zeta_L M_{L L''} for
   zeta, one linear system per bin tuple B (eq. edge-corrected-NPCF; the system is
   solved as written in eq. edge-correction-matrix, i.e. with M transposed).
@@ -158,14 +163,17 @@ def gaunt_tensor(N, lmax, parity="even", method="closed"):
 
 
 def coupling_matrix(N, lmax, R, parity="even"):
-    """M[B, L, L''] = sum_L' (R[L', B] / R[0, B]) E(L'') G[L, L', L''] for multiplets
-    R[L, B] of the randoms (row 0 is L = 0)."""
+    """M[B, L, L''] = sum_L' (R[L', B] / R[0, B]) s(L, L') E(L'') G[L, L', L''] for
+    multiplets R[L, B] of the randoms (row 0 is L = 0; odd rows are imaginary parts),
+    with s(L, L') = -1 when L and L' are both odd (i * i), else +1."""
     lams = multiplets(N, lmax, parity)
     G = gaunt_tensor(N, lmax, parity)
     E = np.array([parity_E(N, x) for x in lams], dtype=float)
+    odd = E < 0
+    s = np.where(odd[:, None] & odd[None, :], -1.0, 1.0)
     R = np.asarray(R, dtype=float)
     f = R / R[0][None, :]
-    return np.einsum("pb,lpq,q->blq", f, G, E)
+    return np.einsum("pb,lpq,lp,q->blq", f, G, s, E)
 
 
 def edge_correct(N, lmax, Nmult, Rmult, parity="even", lmax_out=None):

@@ -9,9 +9,14 @@
 // squared over 4 pi.  6j symbols by Racah's single sum (DLMF 34.4.3) and 9j symbols
 // by the sum of 6j products (DLMF 34.6.2), in long double.
 //
-// The device builds M_{L L''}(B) = sum_{L'} f_{L'}(B) E(L'') G^{L L' L''} from a
-// list of the nonzero (L, L'') x L' terms grouped by (L, L'') (so each entry is a
+// The device builds M_{L L''}(B) = sum_{L'} f_{L'}(B) s(L, L') E(L'') G^{L L' L''} from
+// a list of the nonzero (L, L'') x L' terms grouped by (L, L'') (so each entry is a
 // fixed-order sum) and solves the per-B linear system of eq. edge-correction-matrix.
+// The paper's equations hold for the complex multiplets; odd multiplets are
+// imaginary (Section 3.1) and enter here as their imaginary parts, so a term whose
+// L and L' are both odd carries i * i = -1: s(L, L') = -1 then, +1 otherwise.  (G
+// vanishes unless L, L', L'' hold an even number of odd multiplets, so the other
+// factors of i cancel against the one of L''.)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -187,7 +192,7 @@ const GauntTable& gaunt_table(int N, int lmax, bool allparity)
                     const double g = ge(a, b, c);
                     if (g != 0.0) {
                         lp[a].push_back(b);
-                        val[a].push_back(E[c] * g);
+                        val[a].push_back((E[a] < 0 && E[b] < 0 ? -1.0 : 1.0) * E[c] * g);
                         ++cnt[a][c];
                     }
                 }

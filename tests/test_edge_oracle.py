@@ -83,3 +83,76 @@ def test_solution_recovers_known_zeta(N, lmax):
     Zo = edge.edge_correct(N, lmax, Nm, R, lmax_out=lmax - 1)
     keep = [lams.index(x) for x in multiplets(N, lmax - 1)]
     assert np.array_equal(Zo, Z[keep])
+
+
+def _sphere_nodes(deg):
+    """Gauss-Legendre in cos(theta) x uniform phi: exact for polynomials of degree
+    <= deg on the sphere."""
+    x, wx = np.polynomial.legendre.leggauss(deg // 2 + 1)
+    nphi = deg + 1
+    phi = 2.0 * np.pi * np.arange(nphi) / nphi
+    st = np.sqrt(1.0 - x * x)
+    v = np.stack([np.outer(st, np.cos(phi)), np.outer(st, np.sin(phi)),
+                  np.outer(x, np.ones(nphi))], axis=-1).reshape(-1, 3)
+    w = np.outer(wx, np.full(nphi, 2.0 * np.pi / nphi)).reshape(-1)
+    return v, w
+
+
+def _product_projection(N, lmax, z, r):
+    """N_L'' / R_0 from the functional identity of eq. edge-correction-tmp,
+    [sum_L zeta_L P_L(R^)] [sum_L' f_L' P_L'(R^)] = sum_L'' (N_L'' / R_0) P_L''(R^),
+    projected on P_L'' by orthonormality (eq. basis-orthogonality) with a quadrature
+    exact for the degree 3 lmax integrands.  P_L from sympy 3j symbols and scipy
+    Y_lm (oracle.brute), no Gaunt integral anywhere.  Coefficients are carried as
+    real numbers, Re for even and Im for odd multiplets, as the estimator returns
+    them; the complex ones are rebuilt here."""
+    from itertools import product as iprod
+    from oracle import brute
+    from oracle.basis import parity_E
+    lams = multiplets(N, lmax, "all")
+    odd = np.array([parity_E(N, x) < 0 for x in lams])
+    v1, w1 = _sphere_nodes(3 * lmax)
+    K = N - 1
+    idx = np.array(list(iprod(range(len(w1)), repeat=K)))
+    vecs = v1[idx]                                   # [P, K, 3]
+    wts = np.prod(w1[idx], axis=1)
+    P = np.stack([brute.basis_function(N, lam, vecs) for lam in lams])
+    assert np.max(np.abs((P * wts) @ P.conj().T - np.eye(len(lams)))) < 1e-12
+    cz = np.where(odd, 1j, 1.0) * z
+    cf = np.where(odd, 1j, 1.0) * r / r[0]
+    F = (cz @ P) * (cf @ P)
+    assert np.max(np.abs(F.imag)) < 1e-12 * np.max(np.abs(F))   # a real function
+    cN = (P.conj() * wts) @ F
+    return np.where(odd, cN.imag, cN.real), odd
+
+
+@pytest.mark.parametrize("N,lmax", [(3, 2), (4, 1), (4, 2), (5, 1)])
+def test_coupling_matrix_matches_product_projection(N, lmax):
+    """Pins eq. edge-correction-matrix in mixed parity: sum_L zeta_L M_{L L''} equals
+    the projection of the product of the zeta and window functions, for windows
+    with odd multiplets.  For the real multiplets (Im of the odd ones) M comes out
+    symmetric, so the index order of the solve cannot matter; the i * i sign of
+    the odd x odd terms does: the matrix without it misses the projection."""
+    from oracle.basis import parity_E
+    lams = multiplets(N, lmax, "all")
+    n = len(lams)
+    G = edge.gaunt_tensor(N, lmax, "all")
+    E = np.array([parity_E(N, x) for x in lams], dtype=float)
+    rng = np.random.default_rng(11 + N + lmax)
+    worst = 0.0
+    for trial in range(3):
+        z = rng.normal(size=n)
+        r = rng.normal(0.0, 0.3, n)
+        r[0] = rng.uniform(1.0, 2.0)
+        nq, odd = _product_projection(N, lmax, z, r)
+        M = edge.coupling_matrix(N, lmax, r[:, None], "all")[0]
+        assert np.max(np.abs(M - M.T)) < 1e-15
+        worst = max(worst, np.max(np.abs(z @ M - nq)))
+        if N >= 4:   # N = 3 has only even multiplets (l1 = l2)
+            assert odd.any() and (~odd).any()
+            unsigned = np.einsum("p,lpq,q->lq", r / r[0], G, E)
+            assert np.max(np.abs(z @ unsigned - nq)) > 1e-3
+        # the edge correction recovers zeta from the projected N
+        Z = edge.edge_correct(N, lmax, (nq * r[0])[:, None], r[:, None], parity="all")
+        assert np.max(np.abs(Z[:, 0] - z)) < 1e-11
+    assert worst < 1e-12
