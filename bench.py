@@ -90,29 +90,17 @@ def cpu_baseline(cfg, target_s):
                       "secondaries, FP64 C oracle (full M sum), %.1f s" % (k, dt)}
 
 
-def ns_dmr_catalog(nd, box, seed):
-    """Neyman-Scott data (parents Poisson, ~10 children, sigma 5) thinned to nd, plus
-    3 nd uniform randoms; D-R weights are applied by the library."""
-    import numpy as np
-    from paper_2105_08722_amd import synth
-    dpos, dw = synth.neyman_scott(nd, box, seed)
-    rpos, rw = synth.uniform_box(3 * nd, box, seed + 7919)
-    return np.concatenate([dpos, rpos]), np.concatenate([dw, rw])
-
-
 def batched_leg(ctx, edges, precision, njobs, seed=4000):
     """Uneven mock catalogs (N_D ~ U[50k, 400k] Neyman-Scott data + 3 N_D randoms each,
     periodic 1000 Mpc/h) in one encore_npcf_batch call (one persistent gather launch
     per slice over all catalogs)."""
-    import numpy as np
-    from paper_2105_08722_amd import encore
-    rng = np.random.default_rng(seed)
-    sizes = rng.integers(50_000, 400_001, size=njobs)
+    from paper_2105_08722_amd import encore, synth
+    sizes = synth.batch_sizes(njobs, seed)
     grids = []
     tot = 0
     try:
         for k, nd in enumerate(sizes):
-            pos, w = ns_dmr_catalog(int(nd), 1000.0, seed + k)
+            pos, w = synth.mock_dmr_catalog(int(nd), 1000.0, seed + k)
             grids.append(encore.build_grid(ctx, pos, w, r_max=edges[-1], box=1000.0, n_data=int(nd)))
             tot += len(w)
         encore.npcf_batch(ctx, grids[:2], 4, 5, edges, precision=precision)   # warm
@@ -133,7 +121,7 @@ def served_leg(ctx, edges, njobs, rate, seed=5000):
     lmax=5 and 5PCF lmax=4 (split-bf16) jobs on Neyman-Scott D-R catalogs of
     log-uniform size; latency = arrival (submit) to result ready."""
     import numpy as np
-    from paper_2105_08722_amd import encore
+    from paper_2105_08722_amd import encore, synth
     rng = np.random.default_rng(seed)
     kinds = [(3, 10, "fp32"), (4, 5, "splitbf16"), (5, 4, "splitbf16")]
     jobs = []
@@ -141,7 +129,7 @@ def served_leg(ctx, edges, njobs, rate, seed=5000):
         N, L, prec = kinds[int(rng.integers(0, 3))]
         ntot = int(np.exp(rng.uniform(np.log(1e4), np.log(1e6))))
         nd = max(ntot // 4, 1)
-        pos, w = ns_dmr_catalog(nd, 1000.0, seed + 13 * k)
+        pos, w = synth.mock_dmr_catalog(nd, 1000.0, seed + 13 * k)
         jobs.append((N, L, prec, pos, w, nd))
     gaps = rng.exponential(1.0 / rate, size=njobs)
     ids = [None] * njobs
@@ -263,8 +251,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--batched-jobs", type=int, default=8, help="0: skip the batched leg")
-    ap.add_argument("--served-jobs", type=int, default=24, help="0: skip the served leg")
+    ap.add_argument("--batched-jobs", type=int, default=64, help="0: skip the batched leg")
+    ap.add_argument("--served-jobs", type=int, default=256, help="0: skip the served leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (the reference "
                          "dispatch for scaling FETCH_SIZE/WRITE_SIZE counters)")

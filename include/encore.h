@@ -148,20 +148,25 @@ int encore_npcf(encore_ctx* ctx, const encore_grid* grid, int npcf, int lmax, in
                 void* stream);
 
 /*
- * The same multiplets for several catalogs at once (one job per grid), with every
- * point of each catalog a primary.  All jobs share npcf, lmax, the bins and the
- * flags.  The gather runs as ONE persistent launch per slice of primaries: waves
+ * The same multiplets for several catalogs at once (one job per grid).  All jobs
+ * share npcf, lmax, the bins and the flags.  The gather runs as ONE persistent launch per slice of primaries: waves
  * pull (catalog, primary, bin group) work items from device work queues, so
  * catalogs of uneven size and neighbour count share the GPU without per-job
  * launches.  The coupling and FP64 sums stay per job.
  *  grids   [njobs] grids built on ctx (may repeat).
  *  zeta    host FP64 [njobs][n_multiplets * n_bin_tuples].
  *  zeta_len length of zeta in elements (>= njobs * n_multiplets * n_bin_tuples).
+ *  primary_subsets  NULL: every point of every catalog is a primary.  Otherwise
+ *          [njobs] host pointers, each NULL (every point of that catalog) or
+ *          [n_subsets[j]] catalog indices (input order) of job j's primaries, as
+ *          primary_subset of encore_npcf.
+ *  n_subsets  [njobs] (read where primary_subsets[j] is not NULL).
  * ENCORE_NORMALIZE uses each periodic grid's box volume.  Errors as encore_npcf.
  */
 int encore_npcf_batch(encore_ctx* ctx, const encore_grid* const* grids, int njobs, int npcf,
                       int lmax, int nbins, const double* edges, uint32_t flags, double* zeta,
-                      size_t zeta_len, void* stream);
+                      size_t zeta_len, const int64_t* const* primary_subsets,
+                      const int64_t* n_subsets, void* stream);
 
 /*
  * Serving loop.  A server accepts catalog jobs from any thread and runs them on

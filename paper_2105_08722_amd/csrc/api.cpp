@@ -20,21 +20,20 @@ using namespace encore;
 
 namespace {
 
-// Primary list (sorted indices) into x.prim; returns count in *np.
-int make_primaries(Exec& x, const encore_grid* grid, const int64_t* subset, int64_t k, int64_t* np)
+// Primaries of one job as cell-sorted indices at dst (device, room for the count):
+// every point (subset NULL) or the subset given in input order.  *np: the count.
+int fill_primaries(Exec& x, const encore_grid* grid, const int64_t* subset, int64_t k, int32_t* dst,
+                   int64_t* np)
 {
     const hipStream_t s = x.s;
     const int64_t n = grid->g.n;
     if (!subset) {
-        int rc = ensure(x.prim, sizeof(int32_t) * std::max<int64_t>(n, 1));
-        if (rc) return rc;
-        HIPTRY((hipError_t)launch_iota((int32_t*)x.prim.p, n, s));
+        HIPTRY((hipError_t)launch_iota(dst, n, s));
         *np = n;
         return ENCORE_OK;
     }
     if (k < 0) return fail(ENCORE_EINVAL, "n_subset < 0");
-    int rc = ensure(x.prim, sizeof(int32_t) * std::max<int64_t>(k, 1));
-    if (rc) return rc;
+    int rc;
     if ((rc = ensure(x.misc, sizeof(int64_t) * std::max<int64_t>(k, 1) + 16))) return rc;
     int* d_bad = (int*)x.misc.p;
     int64_t* d_idx = (int64_t*)((char*)x.misc.p + 16);
@@ -42,13 +41,22 @@ int make_primaries(Exec& x, const encore_grid* grid, const int64_t* subset, int6
     HIPTRY(hipMemcpyAsync(d_bad, &bad, sizeof(int), hipMemcpyHostToDevice, s));
     if (k > 0) {
         HIPTRY(hipMemcpyAsync(d_idx, subset, sizeof(int64_t) * k, hipMemcpyHostToDevice, s));
-        HIPTRY((hipError_t)launch_map_subset(d_idx, k, grid->g.inv, n, (int32_t*)x.prim.p, d_bad, s));
+        HIPTRY((hipError_t)launch_map_subset(d_idx, k, grid->g.inv, n, dst, d_bad, s));
     }
     HIPTRY(hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPTRY(hipStreamSynchronize(s));
     if (bad) return fail(ENCORE_EINVAL, "primary_subset holds an index outside [0, n)");
     *np = k;
     return ENCORE_OK;
+}
+
+// Primary list of one job into x.prim; returns count in *np.
+int make_primaries(Exec& x, const encore_grid* grid, const int64_t* subset, int64_t k, int64_t* np)
+{
+    const int64_t cnt = subset ? k : grid->g.n;
+    int rc = ensure(x.prim, sizeof(int32_t) * (size_t)std::max<int64_t>(cnt, 1));
+    if (rc) return rc;
+    return fill_primaries(x, grid, subset, k, (int32_t*)x.prim.p, np);
 }
 
 int build_grid_impl(encore_ctx* ctx, const double* pos, const double* w, int64_t n, int64_t n_data,
@@ -174,7 +182,11 @@ int run_jobs(encore_ctx* ctx, const std::vector<JobRows>& jobs, const NpcfPlan& 
             }
             if (jpos >= J.nprim) { ++jcur; jpos = 0; }
         }
-        if (rows == 0) break;
+        if (rows == 0) {
+            if (jcur < jobs.size())   // cannot happen while cap_rows >= every split length
+                return fail(ENCORE_EINVAL, "slice row cap below the coupling split length");
+            break;
+        }
         if ((rc = run_slice(x, pl, tb, edges, chunks, &t_gather, &t_couple))) return rc;
         ++nslice;
     }
@@ -387,10 +399,14 @@ int encore_npcf(encore_ctx* ctx, const encore_grid* grid, int npcf, int lmax, in
 
 int encore_npcf_batch(encore_ctx* ctx, const encore_grid* const* grids, int njobs, int npcf, int lmax,
                       int nbins, const double* edges, uint32_t flags, double* zeta, size_t zeta_len,
-                      void* stream)
+                      const int64_t* const* primary_subsets, const int64_t* n_subsets, void* stream)
 {
     if (!ctx || !grids) return fail(ENCORE_EINVAL, "NULL ctx or grids");
     if (njobs < 1) return fail(ENCORE_EINVAL, "njobs must be >= 1");
+    if (primary_subsets && !n_subsets) return fail(ENCORE_EINVAL, "primary_subsets without n_subsets");
+    auto subset_of = [&](int j) -> const int64_t* { return primary_subsets ? primary_subsets[j] : nullptr; };
+    for (int j = 0; j < njobs; ++j)
+        if (subset_of(j) && n_subsets[j] < 0) return fail(ENCORE_EINVAL, "n_subsets[j] < 0");
     NpcfPlan pl;
     int rc;
     if ((rc = plan_call(npcf, lmax, nbins, edges, flags, &pl))) return rc;
@@ -407,17 +423,20 @@ int encore_npcf_batch(encore_ctx* ctx, const encore_grid* const* grids, int njob
     return on_stream(ctx, stream, [&]() {
         Exec& x = ctx->main;
         HIPTRY(hipEventRecord(x.ev[0], x.s));
-        // primaries: every point of every catalog, in each grid's cell order
+        // primaries: every point of a catalog in its grid's cell order, or the subset
         int64_t tot = 0;
-        for (int j = 0; j < njobs; ++j) tot += grids[j]->g.n;
+        for (int j = 0; j < njobs; ++j) tot += subset_of(j) ? n_subsets[j] : grids[j]->g.n;
         int rc2;
         if ((rc2 = ensure(x.prim, sizeof(int32_t) * (size_t)std::max<int64_t>(tot, 1)))) return rc2;
         std::vector<JobRows> jobs(njobs);
         int64_t off = 0;
         for (int j = 0; j < njobs; ++j) {
-            HIPTRY((hipError_t)launch_iota((int32_t*)x.prim.p + off, grids[j]->g.n, x.s));
-            jobs[j] = JobRows{grids[j], (const int32_t*)x.prim.p + off, grids[j]->g.n};
-            off += grids[j]->g.n;
+            int64_t np = 0;
+            int32_t* dst = (int32_t*)x.prim.p + off;
+            if ((rc2 = fill_primaries(x, grids[j], subset_of(j), subset_of(j) ? n_subsets[j] : 0, dst, &np)))
+                return rc2;
+            jobs[j] = JobRows{grids[j], dst, np};
+            off += np;
         }
         return run_jobs(ctx, jobs, pl, flags, edges, 0.0, zeta);
     });
@@ -637,7 +656,13 @@ int encore_autotune(encore_ctx* ctx, const double* pos, const double* w, int64_t
     const bool periodic = flags & ENCORE_PERIODIC;
     if (periodic && !box) return fail(ENCORE_EINVAL, "ENCORE_PERIODIC needs box");
     const double r_max = edges[nbins];
-    const int gprec = pl.prec == 0 ? 0 : 1;
+    if (periodic)
+        for (int a = 0; a < 3; ++a) {
+            if (!(box[a] > 0.0) || !std::isfinite(box[a])) return fail(ENCORE_EINVAL, "box must be finite and > 0");
+            if (2.0 * r_max > box[a])
+                return fail(ENCORE_EINVAL, "periodic box: edges[nbins] must be <= box/2 on every axis");
+        }
+    const int gprec = gather_precision(pl.prec);
     const std::vector<int> nbgs = gather_nbg_options(lmax, gprec);
     // cell shapes tried: (y/z divisor of r_max, extra x subdivision); the default first
     static const double kCells[][2] = {{5, 8}, {5, 6}, {6, 8}, {5, 4}, {4, 6}, {6, 4}, {8, 4}, {4, 8}};
@@ -678,7 +703,11 @@ int encore_autotune(encore_ctx* ctx, const double* pos, const double* w, int64_t
         tg.ctx = ctx;
         rc = build_grid_dev(ctx->device, d_pos, d_w, n, n_data, (flags & ENCORE_DMR) != 0,
                             periodic ? box : nullptr, r_max, cell[0], cell[1], s, tg.g);
-        if (rc) break;
+        if (rc == ENCORE_OK) rc = check_grid_edges(tg.g, edges, nbins);
+        if (rc) {
+            if (tg.g.P) grid_free(tg.g);
+            break;
+        }
         const int64_t np = k;
         rc = ensure(x.prim, sizeof(int32_t) * (size_t)k);
         if (rc == ENCORE_OK) {
@@ -755,9 +784,9 @@ int encore_debug_alm(encore_ctx* ctx, const encore_grid* grid, int lmax, int nbi
     int rc;
     if ((rc = check_edges(edges, nbins))) return rc;
     if ((rc = check_grid_edges(grid->g, edges, nbins))) return rc;
-    int prec = 0;
-    if ((flags & ENCORE_PREC_MASK) == ENCORE_PREC_SPLITBF16) prec = 1;   // same FP32 gather
-    else if ((rc = precision_of(flags, &prec))) return rc;
+    int cprec = 0;
+    if ((rc = precision_of(flags, &cprec))) return rc;
+    const int prec = gather_precision(cprec);   // the gather encore_npcf runs for this precision
     if (!primaries || k < 1 || !alm_out) return fail(ENCORE_EINVAL, "need k >= 1 primaries and alm_out");
     const bool full = flags & ENCORE_DEBUG_FULLGRID;
     std::lock_guard<std::mutex> lock(ctx->mu);
@@ -773,7 +802,7 @@ int encore_debug_alm(encore_ctx* ctx, const encore_grid* grid, int lmax, int nbi
     HIPTRY(hipMemcpy(sorted_rows.data(), x.prim.p, sizeof(int32_t) * k, hipMemcpyDeviceToHost));
     const int64_t nlaunch = full ? grid->g.n : k;
     if (full && (rc = make_primaries(x, grid, nullptr, 0, &np))) return rc;
-    if ((rc = ensure(x.alm, (size_t)(nlaunch * per) * (prec == 0 ? 8 : 4)))) return rc;
+    if ((rc = ensure(x.alm, (size_t)(nlaunch * per) * (prec == 0 ? 8 : 4)))) return rc;   // FP32 out for 1, 2
     if ((rc = ensure(x.zeta, sizeof(double) * (size_t)(nlaunch * per)))) return rc;
     if ((rc = ensure(x.wprim, sizeof(double) * (size_t)nlaunch))) return rc;
     if ((rc = ensure(x.segs, sizeof(GatherSeg)))) return rc;
@@ -807,10 +836,11 @@ int encore_debug_alm(encore_ctx* ctx, const encore_grid* grid, int lmax, int nbi
     ga.nseg = 1;
     ga.nrows = (int)nlaunch;
     NpcfPlan gpl;
-    gpl.lmax = lmax; gpl.prec = prec; gpl.nbins = nbins;
+    gpl.lmax = lmax; gpl.prec = cprec; gpl.nbins = nbins;
     const int nbg = ctx_nbg(ctx, gpl);   // the configuration encore_npcf launches
     if (e == hipSuccess) e = (hipError_t)launch_gather(ga, lmax, prec, nbg, false, s);
-    if (e == hipSuccess) e = (hipError_t)launch_to_double(x.alm.p, prec, nlaunch * per, (double*)x.zeta.p, s);
+    if (e == hipSuccess)
+        e = (hipError_t)launch_to_double(x.alm.p, prec == 0 ? 0 : 1, nlaunch * per, (double*)x.zeta.p, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     for (int64_t r = 0; r < k && e == hipSuccess; ++r) {
         // full launch: row of sorted index sorted_rows[r]; else row r

@@ -29,14 +29,23 @@ struct DevGrid {
     double r_max = 0;
     int64_t n_data = 0;   // with dmr: input points [0, n_data) are data
     int dmr = 0;          // built as a data-minus-randoms catalog
+    hipMemPool_t pool = nullptr;   // arrays from this stream-ordered pool (null: hipMalloc)
 };
 
+// Device memory from a stream-ordered pool on stream s (no device-wide
+// synchronisation, unlike hipMalloc/hipFree), or plain hipMalloc/hipFree when
+// pool is null.
+hipError_t dev_alloc(void** p, size_t bytes, hipMemPool_t pool, hipStream_t s);
+void dev_free(void* p, hipMemPool_t pool, hipStream_t s);
+
 // ------------------------------------------------------------------ grid build
+// With a pool, every array of the grid and every temporary comes from it on
+// `stream`; grid_free must then be given a stream ordered after the grid's last use.
 int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, int64_t n_data,
                bool dmr, bool periodic, const double box[3], double r_max, double cell_size,
                double cell_size_x,
-               hipStream_t stream, char* errbuf, size_t errlen);
-void grid_free(DevGrid& g);
+               hipStream_t stream, char* errbuf, size_t errlen, hipMemPool_t pool = nullptr);
+void grid_free(DevGrid& g, hipStream_t s = nullptr);
 // small utility kernels
 int launch_iota(int32_t* out, int64_t n, hipStream_t stream);
 // out[k] = inv[idx[k]]; sets *bad if any idx is outside [0, n)

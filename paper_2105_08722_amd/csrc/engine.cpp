@@ -32,12 +32,16 @@ int hip_fail(hipError_t e, const char* what)
 int ensure(Buf& b, size_t bytes)
 {
     if (b.n >= bytes && b.p) return ENCORE_OK;
-    if (b.p) (void)hipFree(b.p);
+    dev_free(b.p, b.pool, b.s);
     b.p = nullptr;
     b.n = 0;
-    const size_t want = std::max<size_t>(bytes, 256);
-    hipError_t e = hipMalloc(&b.p, want);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
+    // pooled buffers grow by at least half, so a lane settles after a few slices
+    const size_t want = std::max<size_t>(b.pool ? std::max(bytes, bytes / 2 * 3) : bytes, 256);
+    hipError_t e = dev_alloc(&b.p, want, b.pool, b.s);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return hip_fail(e, "workspace allocation");
+    }
     b.n = want;
     return ENCORE_OK;
 }
@@ -49,21 +53,25 @@ static Buf* exec_bufs(Exec& x, int i)
     return i < (int)(sizeof(all) / sizeof(all[0])) ? all[i] : nullptr;
 }
 
-int exec_init(Exec& x)
+int exec_init(Exec& x, hipMemPool_t pool)
 {
     HIPTRY(hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking));
     for (int i = 0; i < 4; ++i) HIPTRY(hipEventCreate(&x.ev[i]));
+    for (int i = 0; Buf* b = exec_bufs(x, i); ++i) {
+        b->pool = pool;
+        b->s = x.s;
+    }
     return ENCORE_OK;
 }
 
 void exec_release(Exec& x)
 {
-    if (x.s) (void)hipStreamSynchronize(x.s);
     for (int i = 0; Buf* b = exec_bufs(x, i); ++i) {
-        if (b->p) (void)hipFree(b->p);
+        dev_free(b->p, b->pool, x.s);
         b->p = nullptr;
         b->n = 0;
     }
+    if (x.s) (void)hipStreamSynchronize(x.s);
     for (int i = 0; i < 4; ++i) {
         if (x.ev[i]) (void)hipEventDestroy(x.ev[i]);
         x.ev[i] = nullptr;
@@ -120,6 +128,16 @@ int check_grid_edges(const DevGrid& g, const double* edges, int nbins)
     if (g.periodic && (2.0 * edges[nbins] > g.Lx || 2.0 * edges[nbins] > g.Ly || 2.0 * edges[nbins] > g.Lz))
         return fail(ENCORE_EINVAL, "periodic box: edges[nbins] must be <= box/2 on every axis");
     return ENCORE_OK;
+}
+
+int gather_precision(int prec)
+{
+    // The FP32 path keeps each lane's sums compensated: on survey geometry the
+    // data-minus-randoms terms cancel inside each coefficient, and plain FP32
+    // sums then miss 1e-6 on the multiplets (measured 9e-6 on the 6PCF of the
+    // survey wedge, 8e-7 compensated).  The split-bf16 path's own products carry
+    // ~1e-5, far above what plain FP32 sums add, so it keeps the faster gather.
+    return prec == 0 ? 0 : (prec == 1 ? 2 : 1);
 }
 
 int plan_call(int npcf, int lmax, int nbins, const double* edges, uint32_t flags, NpcfPlan* pl)
@@ -263,6 +281,8 @@ int64_t cap_rows(const NpcfPlan& pl)
         const long long v = atoll(e);
         if (v > 0) cap = std::min<int64_t>(cap, v);
     }
+    // split-BF16 couples whole 16-row K blocks: a slice holds at least one
+    if (pl.prec == 2) cap = std::max<int64_t>(cap, kBlkRows);
     return cap;
 }
 
@@ -413,7 +433,7 @@ int prepare_slice(Exec& x, Buf& segs, Buf& splits, Buf& redp, const NpcfPlan& pl
 int launch_slice_gather(const SliceLaunch& L, const NpcfPlan& pl, hipStream_t s)
 {
     if (L.rows == 0) return ENCORE_OK;
-    HIPTRY((hipError_t)launch_gather(L.ga, pl.lmax, pl.prec == 0 ? 0 : 1, pl.nbg, L.persistent, s));
+    HIPTRY((hipError_t)launch_gather(L.ga, pl.lmax, gather_precision(pl.prec), pl.nbg, L.persistent, s));
     const int row_cplx = pl.nbins * (pl.lmax + 1) * (pl.lmax + 2) / 2;
     for (const CacheAdd& c : L.adds)
         HIPTRY((hipError_t)launch_add_cached(L.ga.alm, pl.prec == 0 ? 0 : 1, c.row0, c.nrows, c.prim, c.cache,
@@ -520,7 +540,7 @@ double cell_x_subdiv(double tuned)
 int ctx_nbg(encore_ctx* ctx, const NpcfPlan& pl)
 {
     std::lock_guard<std::mutex> lock(ctx->tab_mu);
-    auto it = ctx->tuned_nbg.find(std::make_tuple(pl.lmax, pl.prec == 0 ? 0 : 1, pl.nbins));
+    auto it = ctx->tuned_nbg.find(std::make_tuple(pl.lmax, gather_precision(pl.prec), pl.nbins));
     return it == ctx->tuned_nbg.end() ? 0 : it->second;
 }
 
@@ -533,7 +553,7 @@ void ctx_cells(encore_ctx* ctx, double* div, double* xsub)
 
 int build_grid_dev(int device, const double* d_pos, const double* d_w, int64_t n, int64_t n_data,
                    bool dmr, const double* box, double r_max, double div, double xsub, hipStream_t s,
-                   DevGrid& out)
+                   DevGrid& out, hipMemPool_t pool)
 {
     HIPTRY(hipSetDevice(device));
     double bx[3] = {0, 0, 0};
@@ -542,7 +562,7 @@ int build_grid_dev(int device, const double* d_pos, const double* d_w, int64_t n
     char err[256] = {0};
     const int rc = grid_build(out, d_pos, d_w, n, n_data, dmr, box != nullptr, bx, r_max,
                               r_max / div, r_max / (div * xsub), s,
-                              err, sizeof(err));
+                              err, sizeof(err), pool);
     if (rc != 0) return fail(rc == -1 ? ENCORE_EINVAL : (rc == -3 ? ENCORE_ENOMEM : ENCORE_EDEVICE), err);
     return ENCORE_OK;
 }

@@ -47,9 +47,13 @@ struct DevTables {
 };
 
 
+// A grow-only device buffer.  With a pool it is allocated and freed stream-ordered
+// on stream s (no device-wide synchronisation when it grows).
 struct Buf {
     void* p = nullptr;
     size_t n = 0;
+    hipMemPool_t pool = nullptr;
+    hipStream_t s = nullptr;
 };
 
 // One stream and the workspaces of the hot path on it.
@@ -59,7 +63,9 @@ struct Exec {
     Buf cache, cmap;   // random splits: the data part of a~ and the row maps
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
-int exec_init(Exec& x);
+// pool: null for plain hipMalloc workspaces, else a stream-ordered pool the
+// workspaces come from (on x.s)
+int exec_init(Exec& x, hipMemPool_t pool = nullptr);
 void exec_release(Exec& x);
 // bytes held by the workspaces
 size_t exec_bytes(const Exec& x);
@@ -89,6 +95,9 @@ struct NpcfPlan {
     int64_t nlam = 0, nB = 0;
 };
 int plan_call(int npcf, int lmax, int nbins, const double* edges, uint32_t flags, NpcfPlan* pl);
+// Gather variant of a call precision (0 FP64, 1 FP32, 2 split-BF16): 0 FP64
+// accumulators, 1 FP32 (split-BF16), 2 compensated FP32 (FP32); see launch_gather.
+int gather_precision(int prec);
 
 // per-job accumulator length: ntuple * nB (VALU coupling) or the dense MFMA tiles
 int64_t acc_len(const NpcfPlan& pl, const DevTables* tb);
@@ -153,9 +162,10 @@ std::vector<double> bin_scale(const NpcfPlan& pl, const double* edges, double V)
 
 // Cell grid of a catalog already on the device (pos [n][3], w [n]).
 // cell sides r_max / div (y, z) and r_max / (div * xsub) (x)
+// (pool: see grid_build)
 int build_grid_dev(int device, const double* d_pos, const double* d_w, int64_t n, int64_t n_data,
                    bool dmr, const double* box, double r_max, double div, double xsub, hipStream_t s,
-                   DevGrid& out);
+                   DevGrid& out, hipMemPool_t pool = nullptr);
 // cell shape: ENCORE_CELL_DIVISOR / ENCORE_CELL_XSUB, else the tuned value (> 0),
 // else the default
 double cell_divisor(double tuned = 0.0);

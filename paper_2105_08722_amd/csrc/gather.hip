@@ -69,20 +69,22 @@ template <typename T> __device__ __forceinline__ T rsqrt_t(T v);
 template <> __device__ __forceinline__ float rsqrt_t<float>(float v) { return __builtin_amdgcn_rsqf(v); }
 template <> __device__ __forceinline__ double rsqrt_t<double>(double v) { return 1.0 / sqrt(v); }
 
-// LDS of one wave: the per-bin rings (reused as the reduction scratch) and the
-// piece descriptors of one row batch.
-template <typename T, int NBG>
+// LDS of one wave: the per-bin rings (reused as the reduction scratch, whose values
+// are FP64 for the FP64 and the compensated FP32 accumulators) and the piece
+// descriptors of one row batch.
+template <typename T, int NBG, bool COMP>
 __host__ __device__ constexpr int ring_bytes()
 {
-    return (NBG * kCap * (int)sizeof(typename Entry<T>::type) > kRedCh * 65 * (int)sizeof(T))
+    constexpr int red = kRedCh * 65 * ((COMP || sizeof(T) == 8) ? 8 : 4);
+    return (NBG * kCap * (int)sizeof(typename Entry<T>::type) > red)
                ? NBG * kCap * (int)sizeof(typename Entry<T>::type)
-               : kRedCh * 65 * (int)sizeof(T);
+               : red;
 }
-template <typename T, int NBG>
+template <typename T, int NBG, bool COMP>
 __host__ __device__ constexpr int wave_lds_bytes()
 {
     // ring | seg_dl[kSegCap] seg_flat[kSegCap + 1]
-    return ring_bytes<T, NBG>() + 4 * (2 * kSegCap + 4);
+    return ring_bytes<T, NBG, COMP>() + 4 * (2 * kSegCap + 4);
 }
 
 // Square root by Newton's iteration, for the compile-time tables below.
@@ -141,10 +143,42 @@ struct KappaTable {
 };
 template <int L> struct Kappa { static constexpr KappaTable<L> t{}; };
 
-// Add w*Y_lm for m in [M0, M1] of one pair into acc (layout [lm][re, im]).
-template <typename T, int L, int M0, int M1>
-__device__ __forceinline__ void accum_pair(T dx, T dy, T dz, T w, T (&acc)[nlm_of(L)][2])
+// s += v, or with COMP the compensated (Kahan) sum: c carries the rounding error of
+// s with the opposite sign (the sum is s - c), so a lane's sum of many pairs loses
+// only the final rounding instead of one per addition.
+template <bool COMP, typename T>
+__device__ __forceinline__ void acc_add(T& s, T& c, T v)
 {
+    if constexpr (COMP) {
+        const T y = v - c;
+        const T t = s + y;
+        c = (t - s) - y;
+        s = t;
+    } else {
+        s += v;
+    }
+}
+// s += a * b (one rounding of the product: fused into the compensated update)
+template <bool COMP, typename T>
+__device__ __forceinline__ void acc_fma(T& s, T& c, T a, T b)
+{
+    if constexpr (COMP) {
+        const T y = __builtin_fmaf(a, b, -c);
+        const T t = s + y;
+        c = (t - s) - y;
+        s = t;
+    } else {
+        s += a * b;
+    }
+}
+
+// Add w*Y_lm for m in [M0, M1] of one pair into acc (layout [lm][re, im]); with
+// COMP, cmp holds the compensation of each accumulator (unused otherwise).
+template <typename T, int L, int M0, int M1, bool COMP>
+__device__ __forceinline__ void accum_pair(T dx, T dy, T dz, T w, T (&acc)[nlm_of(L)][2],
+                                           T (&cmp)[COMP ? nlm_of(L) : 1][2])
+{
+    auto C = [&](int q, int ri) -> T& { return cmp[COMP ? q : 0][ri]; };
     const T r2 = dx * dx + dy * dy + dz * dz;
     const T inv = rsqrt_t<T>(r2);
     const T x = dx * inv, y = dy * inv, z = dz * inv;
@@ -168,24 +202,24 @@ __device__ __forceinline__ void accum_pair(T dx, T dy, T dz, T w, T (&acc)[nlm_o
         }
         T r0 = w, r1 = zw;
         if (m == 0) {
-            acc[lm_index(0, 0)][0] += r0;
-            if (L >= 1) acc[lm_index(1, 0)][0] += r1;
+            acc_add<COMP>(acc[lm_index(0, 0)][0], C(lm_index(0, 0), 0), r0);
+            if (L >= 1) acc_add<COMP>(acc[lm_index(1, 0)][0], C(lm_index(1, 0), 0), r1);
         } else {
-            acc[lm_index(m, m)][0] += r0 * ur;
-            acc[lm_index(m, m)][1] += r0 * ui;
+            acc_fma<COMP>(acc[lm_index(m, m)][0], C(lm_index(m, m), 0), r0, ur);
+            acc_fma<COMP>(acc[lm_index(m, m)][1], C(lm_index(m, m), 1), r0, ui);
             if (m + 1 <= L) {
-                acc[lm_index(m + 1, m)][0] += r1 * ur;
-                acc[lm_index(m + 1, m)][1] += r1 * ui;
+                acc_fma<COMP>(acc[lm_index(m + 1, m)][0], C(lm_index(m + 1, m), 0), r1, ur);
+                acc_fma<COMP>(acc[lm_index(m + 1, m)][1], C(lm_index(m + 1, m), 1), r1, ui);
             }
         }
 #pragma unroll
         for (int l = m + 2; l <= L; ++l) {
             const T rn = z * r1 - (T)Gamma<L>::t.v[lm_index(l, m)] * r0;
             if (m == 0) {
-                acc[lm_index(l, 0)][0] += rn;
+                acc_add<COMP>(acc[lm_index(l, 0)][0], C(lm_index(l, 0), 0), rn);
             } else {
-                acc[lm_index(l, m)][0] += rn * ur;
-                acc[lm_index(l, m)][1] += rn * ui;
+                acc_fma<COMP>(acc[lm_index(l, m)][0], C(lm_index(l, m), 0), rn, ur);
+                acc_fma<COMP>(acc[lm_index(l, m)][1], C(lm_index(l, m), 1), rn, ui);
             }
             r0 = r1; r1 = rn;
         }
@@ -424,28 +458,31 @@ __device__ __forceinline__ int emit_pieces(const RowGeom& rg, const GatherSeg& g
 }
 
 // waves per SIMD the kernel is compiled for, from its accumulator registers
-template <typename T, int L, int NBG, int M0, int M1>
+template <typename T, int L, int NBG, int M0, int M1, bool COMP>
 __host__ __device__ constexpr int gather_wpe()
 {
-    constexpr int acc = NBG * ((L + 1) * (L + 1)) * (int)(sizeof(T) / 4);
+    constexpr int acc = NBG * ((L + 1) * (L + 1)) * (int)(sizeof(T) / 4) * (COMP ? 2 : 1);
     return acc <= 72 ? 4 : 2;
 }
 
-// PERS: persistent grid (work items pulled from queues); otherwise one item per wave
-template <typename T, int L, int NBG, int M0, int M1, bool PERS>
-__global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG, M0, M1>())) k_gather(GatherArgs a)
+// PERS: persistent grid (work items pulled from queues); otherwise one item per wave.
+// COMP (T = float only): compensated accumulators, reduced across lanes in FP64.
+template <typename T, int L, int NBG, int M0, int M1, bool PERS, bool COMP>
+__global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG, M0, M1, COMP>())) k_gather(GatherArgs a)
 {
+    static_assert(!COMP || std::is_same_v<T, float>, "compensated accumulation is for FP32");
     using E = typename Entry<T>::type;
+    using RT = typename std::conditional<COMP, double, T>::type;   // lane reduction type
     constexpr int NLM = nlm_of(L);
     constexpr int CH = kRedCh;
     extern __shared__ __align__(16) unsigned char smem[];
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wib = threadIdx.x / kWave;
-    unsigned char* base = smem + wib * wave_lds_bytes<T, NBG>();
+    unsigned char* base = smem + wib * wave_lds_bytes<T, NBG, COMP>();
     E* ring = reinterpret_cast<E*>(base);
-    T* scratch = reinterpret_cast<T*>(base);
-    unsigned* seg_dl = reinterpret_cast<unsigned*>(base + ring_bytes<T, NBG>());
+    RT* scratch = reinterpret_cast<RT*>(base);
+    unsigned* seg_dl = reinterpret_cast<unsigned*>(base + ring_bytes<T, NBG, COMP>());
     int* seg_flat = reinterpret_cast<int*>(seg_dl + kSegCap);
 
 
@@ -509,10 +546,15 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
 #pragma unroll
     for (int k = 0; k < NBG; ++k) { head[k] = 0; tail[k] = 0; }
     T acc[NBG][NLM][2];
+    T cmp[NBG][COMP ? NLM : 1][2];
 #pragma unroll
     for (int k = 0; k < NBG; ++k)
 #pragma unroll
         for (int q = 0; q < NLM; ++q) { acc[k][q][0] = (T)0; acc[k][q][1] = (T)0; }
+#pragma unroll
+    for (int k = 0; k < NBG; ++k)
+#pragma unroll
+        for (int q = 0; q < (COMP ? NLM : 1); ++q) { cmp[k][q][0] = (T)0; cmp[k][q][1] = (T)0; }
 
     // row range (unwrapped cell indices)
     // (reciprocal multiplies: the pad of Rc is far above their rounding)
@@ -693,7 +735,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
                         if (tail[K] - head[K] >= kWave) {
                             wave_sync();
                             const E e = ring[K * kCap + ((head[K] + lane) & (kCap - 1))];
-                            accum_pair<T, L, M0, M1>(e.x, e.y, e.z, e.w, acc[K]);
+                            accum_pair<T, L, M0, M1, COMP>(e.x, e.y, e.z, e.w, acc[K], cmp[K]);
                             head[K] += kWave;
                         }
                     }(), ...);
@@ -732,7 +774,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
             if (rem > 0) {
                 E e = ring[K * kCap + ((head[K] + lane) & (kCap - 1))];
                 if (lane >= rem) { e.x = (T)1; e.y = (T)0; e.z = (T)0; e.w = (T)0; }
-                accum_pair<T, L, M0, M1>(e.x, e.y, e.z, e.w, acc[K]);
+                accum_pair<T, L, M0, M1, COMP>(e.x, e.y, e.z, e.w, acc[K], cmp[K]);
             }
         }(), ...);
     }(std::make_integer_sequence<int, NBG>{});
@@ -741,10 +783,11 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
     // ---- 4. reduce the 64 lanes' accumulators and write
     constexpr int NV = NBG * NLM * 2;
     T* accf = &acc[0][0][0];
+    T* cmpf = &cmp[0][0][0];
     const int nvalid = (b_hi - b_lo) * NLM * 2;
     T* out = reinterpret_cast<T*>(a.alm) + ((size_t)row * a.nbins + b_lo) * NLM * 2;
     if (grp == 0 && lane == 0) a.wprim[row] = Pi.w;
-    if constexpr (std::is_same_v<T, float>) {
+    if constexpr (std::is_same_v<T, float> && !COMP) {
         // Reduce-scatter across lanes, two values per step: a 32-lane swap packs
         // values 2p and 2p+1 into one register (lanes 0-31 and 32-63) summed over
         // lanes i, i+32; a 16-row swap packs four values (one per row of 16 lanes)
@@ -789,12 +832,16 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         }
         wave_sync();
     } else {
-        // FP64 accumulators: through LDS, 8 interleaved FP64 partial sums per value
+        // FP64 (or compensated FP32, as s - c in FP64) accumulators: through LDS,
+        // 8 interleaved FP64 partial sums per value
 #pragma unroll
         for (int v0 = 0; v0 < NV; v0 += CH) {
 #pragma unroll
             for (int c = 0; c < CH; ++c)
-                if (v0 + c < NV) scratch[c * 65 + lane] = accf[v0 + c];
+                if (v0 + c < NV) {
+                    if constexpr (COMP) scratch[c * 65 + lane] = (double)accf[v0 + c] - (double)cmpf[v0 + c];
+                    else scratch[c * 65 + lane] = accf[v0 + c];
+                }
             wave_sync();
             const int v = v0 + lane;
             if (lane < CH && v < nvalid) {
@@ -839,28 +886,28 @@ struct KernelCfg {
     int lds;                // bytes per block
 };
 
-template <typename T, int L, int NBG, int M0, int M1, bool PERS>
-const void* kfn() { return reinterpret_cast<const void*>(&k_gather<T, L, NBG, M0, M1, PERS>); }
+template <typename T, int L, int NBG, int M0, int M1, bool PERS, bool COMP>
+const void* kfn() { return reinterpret_cast<const void*>(&k_gather<T, L, NBG, M0, M1, PERS, COMP>); }
 
-template <typename T, int L, int NBG>
+template <typename T, int L, int NBG, bool COMP = false>
 KernelCfg cfg1()
 {
     KernelCfg c{};
     c.nbg = NBG; c.nm = 1; c.m0[0] = 0; c.m1[0] = L;
-    c.fn[0] = kfn<T, L, NBG, 0, L, false>(); c.fnp[0] = kfn<T, L, NBG, 0, L, true>();
-    c.lds = kWavesPerBlock * wave_lds_bytes<T, NBG>();
+    c.fn[0] = kfn<T, L, NBG, 0, L, false, COMP>(); c.fnp[0] = kfn<T, L, NBG, 0, L, true, COMP>();
+    c.lds = kWavesPerBlock * wave_lds_bytes<T, NBG, COMP>();
     return c;
 }
-template <typename T, int L, int NBG, int MS>
+template <typename T, int L, int NBG, int MS, bool COMP = false>
 KernelCfg cfg2()
 {
     KernelCfg c{};
     c.nbg = NBG; c.nm = 2;
     c.m0[0] = 0; c.m1[0] = MS - 1;
-    c.fn[0] = kfn<T, L, NBG, 0, MS - 1, false>(); c.fnp[0] = kfn<T, L, NBG, 0, MS - 1, true>();
+    c.fn[0] = kfn<T, L, NBG, 0, MS - 1, false, COMP>(); c.fnp[0] = kfn<T, L, NBG, 0, MS - 1, true, COMP>();
     c.m0[1] = MS; c.m1[1] = L;
-    c.fn[1] = kfn<T, L, NBG, MS, L, false>(); c.fnp[1] = kfn<T, L, NBG, MS, L, true>();
-    c.lds = kWavesPerBlock * wave_lds_bytes<T, NBG>();
+    c.fn[1] = kfn<T, L, NBG, MS, L, false, COMP>(); c.fnp[1] = kfn<T, L, NBG, MS, L, true, COMP>();
+    c.lds = kWavesPerBlock * wave_lds_bytes<T, NBG, COMP>();
     return c;
 }
 
@@ -878,10 +925,26 @@ int nbg_env()
 }
 
 // The compiled variant with `nbg` bins per item, or the default (first) one.
+// precision: 0 FP64, 1 FP32, 2 FP32 with compensated accumulators (as many
+// registers per value as FP64, so the same bins per item and m split).
 KernelCfg config(int lmax, int precision, int nbg)
 {
     if (nbg_env() > 0) nbg = nbg_env();
-    if (precision == 1) {
+    if (precision == 2) {
+        switch (lmax) {
+        case 0: return cfg1<float, 0, 8, true>();
+        case 1: return cfg1<float, 1, 8, true>();
+        case 2: return cfg1<float, 2, 8, true>();
+        case 3: return nbg == 2 ? cfg1<float, 3, 2, true>() : cfg1<float, 3, 5, true>();
+        case 4: return nbg == 2 ? cfg1<float, 4, 2, true>() : cfg1<float, 4, 3, true>();
+        case 5: return nbg == 1 ? cfg1<float, 5, 1, true>() : cfg1<float, 5, 2, true>();
+        case 6: return cfg1<float, 6, 1, true>();
+        case 7: return cfg1<float, 7, 1, true>();
+        case 8: return cfg1<float, 8, 1, true>();
+        case 9: return cfg2<float, 9, 1, 5, true>();
+        case 10: return cfg2<float, 10, 1, 4, true>();
+        }
+    } else if (precision == 1) {
         switch (lmax) {
         case 0: return cfg1<float, 0, 16>();
         case 1: return cfg1<float, 1, 16>();
@@ -922,8 +985,9 @@ std::vector<int> gather_nbg_options(int lmax, int precision)
     static const std::vector<int> f32[11] = {{16}, {16}, {6, 10}, {4, 2, 5}, {3, 2, 5}, {2, 3},
                                              {2, 1}, {1}, {1}, {1}, {1}};
     static const std::vector<int> f64[11] = {{8}, {8}, {8}, {5, 2}, {3, 2}, {2}, {1}, {1}, {1}, {1}, {1}};
+    static const std::vector<int> f32c[11] = {{8}, {8}, {8}, {5, 2}, {3, 2}, {2, 1}, {1}, {1}, {1}, {1}, {1}};
     if (lmax < 0 || lmax > 10) return {};
-    return precision == 1 ? f32[lmax] : f64[lmax];
+    return precision == 1 ? f32[lmax] : (precision == 2 ? f32c[lmax] : f64[lmax]);
 }
 
 void gather_tables(int lmax, double* kappa)

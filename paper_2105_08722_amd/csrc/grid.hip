@@ -327,19 +327,31 @@ int launch_split_randoms(const DevGrid& S, double* pos, double* w, hipStream_t s
         }                                                                           \
     } while (0)
 
-void grid_free(DevGrid& g)
+hipError_t dev_alloc(void** p, size_t bytes, hipMemPool_t pool, hipStream_t s)
 {
-    if (g.P) (void)hipFree(g.P);
-    if (g.perm) (void)hipFree(g.perm);
-    if (g.inv) (void)hipFree(g.inv);
-    if (g.cell_start) (void)hipFree(g.cell_start);
+    return pool ? hipMallocFromPoolAsync(p, bytes, pool, s) : hipMalloc(p, bytes);
+}
+
+void dev_free(void* p, hipMemPool_t pool, hipStream_t s)
+{
+    if (!p) return;
+    if (pool) (void)hipFreeAsync(p, s);
+    else (void)hipFree(p);
+}
+
+void grid_free(DevGrid& g, hipStream_t s)
+{
+    dev_free(g.P, g.pool, s);
+    dev_free(g.perm, g.pool, s);
+    dev_free(g.inv, g.pool, s);
+    dev_free(g.cell_start, g.pool, s);
     g.P = nullptr; g.perm = nullptr; g.inv = nullptr; g.cell_start = nullptr;
 }
 
 // Returns 0 on success, -1 invalid input (errbuf says why), -3 no memory, -4 HIP error.
 int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, int64_t n_data,
                bool dmr, bool periodic, const double box[3], double r_max, double cell_size,
-               double cell_size_x, hipStream_t stream, char* errbuf, size_t errlen)
+               double cell_size_x, hipStream_t stream, char* errbuf, size_t errlen, hipMemPool_t pool)
 {
     int rc = -4;
     int* d_flags = nullptr;
@@ -356,6 +368,7 @@ int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, in
     const double* wsrc = d_w;
 
     g.n = n;
+    g.pool = pool;
     g.periodic = periodic ? 1 : 0;
     g.r_max = r_max;
     g.dmr = dmr ? 1 : 0;
@@ -367,7 +380,7 @@ int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, in
         return -1;
     }
 
-    HIPCHK(hipMalloc(&d_flags, sizeof(int)));
+    HIPCHK(dev_alloc((void**)&d_flags, sizeof(int), pool, stream));
     HIPCHK(hipMemsetAsync(d_flags, 0, sizeof(int), stream));
     k_validate<<<nblocks(n), kBlock, 0, stream>>>(d_pos, d_w, n, g.periodic, periodic ? box[0] : 0.0,
                                                   periodic ? box[1] : 0.0, periodic ? box[2] : 0.0, d_flags);
@@ -382,9 +395,9 @@ int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, in
         goto fail;
     }
 
-    HIPCHK(hipMalloc(&d_part, sizeof(double) * 6 * npart));
-    HIPCHK(hipMalloc(&d_sums, sizeof(double) * 2));
-    HIPCHK(hipMalloc(&d_wn, sizeof(double) * n));
+    HIPCHK(dev_alloc((void**)&d_part, sizeof(double) * 6 * npart, pool, stream));
+    HIPCHK(dev_alloc((void**)&d_sums, sizeof(double) * 2, pool, stream));
+    HIPCHK(dev_alloc((void**)&d_wn, sizeof(double) * n, pool, stream));
     if (dmr) {
         if (n_data < 1 || n_data >= n) {
             snprintf(errbuf, errlen, "ENCORE_DMR needs 1 <= n_data < n");
@@ -422,7 +435,7 @@ int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, in
         g.ncz = ncell_axis(box[2], cell_size);
         g.csx = box[0] / g.ncx; g.csy = box[1] / g.ncy; g.csz = box[2] / g.ncz;
     } else {
-        HIPCHK(hipMalloc(&d_mm, sizeof(double) * 6));
+        HIPCHK(dev_alloc((void**)&d_mm, sizeof(double) * 6, pool, stream));
         k_minmax_partial<<<npart, kBlock, 0, stream>>>(d_pos, n, d_part);
         k_minmax_final<<<1, 64, 0, stream>>>(d_part, npart, d_mm);
         HIPCHK(hipGetLastError());
@@ -444,12 +457,12 @@ int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, in
         goto fail;
     }
 
-    HIPCHK(hipMalloc(&d_cell, sizeof(int32_t) * n));
-    HIPCHK(hipMalloc(&d_count, sizeof(int32_t) * ncell));
-    HIPCHK(hipMalloc(&g.cell_start, sizeof(int32_t) * (ncell + 1)));
-    HIPCHK(hipMalloc(&g.perm, sizeof(int32_t) * n));
-    HIPCHK(hipMalloc(&g.inv, sizeof(int32_t) * n));
-    HIPCHK(hipMalloc(&g.P, sizeof(double4) * (n + 1)));
+    HIPCHK(dev_alloc((void**)&d_cell, sizeof(int32_t) * n, pool, stream));
+    HIPCHK(dev_alloc((void**)&d_count, sizeof(int32_t) * ncell, pool, stream));
+    HIPCHK(dev_alloc((void**)&g.cell_start, sizeof(int32_t) * (ncell + 1), pool, stream));
+    HIPCHK(dev_alloc((void**)&g.perm, sizeof(int32_t) * n, pool, stream));
+    HIPCHK(dev_alloc((void**)&g.inv, sizeof(int32_t) * n, pool, stream));
+    HIPCHK(dev_alloc((void**)&g.P, sizeof(double4) * (n + 1), pool, stream));
     HIPCHK(hipMemsetAsync(d_count, 0, sizeof(int32_t) * ncell, stream));
     k_cell_count<<<nblocks(n), kBlock, 0, stream>>>(d_pos, n, g.ncx, g.ncy, g.ncz, g.ox, g.oy, g.oz,
                                                     g.csx, g.csy, g.csz, d_cell, d_count);
@@ -463,14 +476,14 @@ int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, in
     rc = 0;
 
 fail:
-    if (d_flags) (void)hipFree(d_flags);
-    if (d_part) (void)hipFree(d_part);
-    if (d_sums) (void)hipFree(d_sums);
-    if (d_wn) (void)hipFree(d_wn);
-    if (d_mm) (void)hipFree(d_mm);
-    if (d_cell) (void)hipFree(d_cell);
-    if (d_count) (void)hipFree(d_count);
-    if (rc != 0) grid_free(g);
+    dev_free(d_flags, pool, stream);
+    dev_free(d_part, pool, stream);
+    dev_free(d_sums, pool, stream);
+    dev_free(d_wn, pool, stream);
+    dev_free(d_mm, pool, stream);
+    dev_free(d_cell, pool, stream);
+    dev_free(d_count, pool, stream);
+    if (rc != 0) grid_free(g, stream);
     return rc;
 }
 

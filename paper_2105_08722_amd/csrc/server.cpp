@@ -6,6 +6,14 @@
 // coupling -> reduction into each job's resident T, and finishes the jobs whose
 // rows are all done (contraction, zeta to the host, device memory released).
 // Lanes run concurrently, so one lane's coupling overlaps another's gather.
+//
+// Nothing on a lane's path synchronises the whole device: a job's device memory
+// (catalog staging, grid, primary list, T) and the lanes' workspaces come from a
+// stream-ordered pool owned by the server and are returned to it with
+// hipFreeAsync on the lane's stream (hipFree would wait for every lane's work),
+// and catalogs reach the device through pinned, double-buffered staging of the
+// lane (a pageable copy would go through the runtime's own staging).
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -49,8 +57,20 @@ struct SrvJob {
 
 }  // namespace
 
+namespace {
+// Pinned host staging of one lane: two halves used alternately, each free again
+// once the copy recorded by its event has finished.
+constexpr size_t kStageHalf = (size_t)8 << 20;
+struct Stage {
+    unsigned char* host = nullptr;   // [2 * kStageHalf], hipHostMalloc
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+}  // namespace
+
 struct encore_server {
     encore_ctx* ctx = nullptr;
+    hipMemPool_t pool = nullptr;
+    std::vector<Stage> stage;   // one per lane
     Scheduler sch;
     int64_t slice_rows = 0;
     std::mutex mu;
@@ -72,12 +92,13 @@ struct encore_server {
 
 namespace {
 
-void release_job(SrvJob* j)
+// Device memory of a job back to the pool, ordered on stream s (after the job's
+// last use, which every caller has already waited for).
+void release_job(encore_server* S, SrvJob* j, hipStream_t s)
 {
-    if (j->has_grid) grid_free(j->g);
+    if (j->has_grid) grid_free(j->g, s);
     j->has_grid = false;
-    for (void* p : {(void*)j->prim, (void*)j->T, (void*)j->bscale})
-        if (p) (void)hipFree(p);
+    for (void* p : {(void*)j->prim, (void*)j->T, (void*)j->bscale}) dev_free(p, S->pool, s);
     j->prim = nullptr;
     j->T = nullptr;
     j->bscale = nullptr;
@@ -85,40 +106,64 @@ void release_job(SrvJob* j)
     std::vector<double>().swap(j->w);
 }
 
-// Grid, primary list, T and tables of an admitted job, on lane x.
-int setup_job(encore_server* S, SrvJob* j, Exec& x)
+// bytes host -> device through the lane's pinned staging, on stream s
+int stage_upload(Stage& st, hipStream_t s, void* dst, const void* src, size_t bytes)
 {
+    size_t off = 0;
+    int h = 0;
+    while (off < bytes) {
+        const size_t c = std::min(kStageHalf, bytes - off);
+        HIPTRY(hipEventSynchronize(st.ev[h]));   // the half's previous copy is done
+        unsigned char* buf = st.host + (size_t)h * kStageHalf;
+        std::memcpy(buf, (const unsigned char*)src + off, c);
+        HIPTRY(hipMemcpyAsync((unsigned char*)dst + off, buf, c, hipMemcpyHostToDevice, s));
+        HIPTRY(hipEventRecord(st.ev[h], s));
+        off += c;
+        h ^= 1;
+    }
+    return ENCORE_OK;
+}
+
+// Grid, primary list, T and tables of an admitted job, on lane li.
+int setup_job(encore_server* S, SrvJob* j, int li)
+{
+    Exec& x = S->lanes[li];
     const hipStream_t s = x.s;
     int rc;
     if ((rc = get_tables_for(S->ctx, j->pl, &j->tb))) return rc;
     double* d_pos = nullptr;
     double* d_w = nullptr;
-    HIPTRY(hipMalloc(&d_pos, sizeof(double) * 3 * j->n));
-    hipError_t e = hipMalloc(&d_w, sizeof(double) * j->n);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_pos, j->pos.data(), sizeof(double) * 3 * j->n, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_w, j->w.data(), sizeof(double) * j->n, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) {
+    hipError_t e = dev_alloc((void**)&d_pos, sizeof(double) * 3 * j->n, S->pool, s);
+    if (e == hipSuccess) e = dev_alloc((void**)&d_w, sizeof(double) * j->n, S->pool, s);
+    if (e != hipSuccess) {
+        dev_free(d_pos, S->pool, s);
+        return hip_fail(e, "server: catalog staging");
+    }
+    rc = stage_upload(S->stage[li], s, d_pos, j->pos.data(), sizeof(double) * 3 * j->n);
+    if (rc == ENCORE_OK) rc = stage_upload(S->stage[li], s, d_w, j->w.data(), sizeof(double) * j->n);
+    if (rc == ENCORE_OK) {
         double div = 0.0, xsub = 0.0;
         ctx_cells(S->ctx, &div, &xsub);
         rc = build_grid_dev(S->ctx->device, d_pos, d_w, j->n, j->n_data, (j->flags & ENCORE_DMR) != 0,
-                            j->periodic ? j->box : nullptr, j->edges[j->pl.nbins], div, xsub, s, j->g);
+                            j->periodic ? j->box : nullptr, j->edges[j->pl.nbins], div, xsub, s, j->g,
+                            S->pool);
         j->has_grid = rc == ENCORE_OK;
     }
-    if (d_pos) (void)hipFree(d_pos);
-    if (d_w) (void)hipFree(d_w);
-    if (e != hipSuccess) return hip_fail(e, "server: catalog upload");
+    dev_free(d_pos, S->pool, s);   // stream-ordered: after the grid build has read them
+    dev_free(d_w, S->pool, s);
     if (rc) return rc;
     std::vector<double>().swap(j->pos);
     std::vector<double>().swap(j->w);
     const int64_t outs = acc_len(j->pl, j->tb);
-    HIPTRY(hipMalloc(&j->prim, sizeof(int32_t) * j->n));
-    HIPTRY(hipMalloc(&j->T, sizeof(double) * std::max<int64_t>(outs, 1)));
+    HIPTRY(dev_alloc((void**)&j->prim, sizeof(int32_t) * j->n, S->pool, s));
+    HIPTRY(dev_alloc((void**)&j->T, sizeof(double) * std::max<int64_t>(outs, 1), S->pool, s));
     HIPTRY((hipError_t)launch_iota(j->prim, j->n, s));
     HIPTRY((hipError_t)launch_fill(j->T, outs, 0.0, s));
     if (j->flags & ENCORE_NORMALIZE) {
         const std::vector<double> sc = bin_scale(j->pl, j->edges.data(), j->box[0] * j->box[1] * j->box[2]);
-        HIPTRY(hipMalloc(&j->bscale, sizeof(double) * std::max<size_t>(sc.size(), 1)));
+        HIPTRY(dev_alloc((void**)&j->bscale, sizeof(double) * std::max<size_t>(sc.size(), 1), S->pool, s));
         HIPTRY(hipMemcpyAsync(j->bscale, sc.data(), sizeof(double) * sc.size(), hipMemcpyHostToDevice, s));
+        HIPTRY(hipStreamSynchronize(s));   // sc is a local
     }
     HIPTRY(hipStreamSynchronize(s));
     j->sj.split_rows = job_split_rows(j->pl, j->tb, j->n, cap_rows(j->pl));
@@ -153,10 +198,13 @@ void lane_main(encore_server* S, int li)
             std::vector<std::string> errs;
             for (SchedJob* sj : adm) {
                 SrvJob* j = static_cast<SrvJob*>(sj->user);
-                const int rc = setup_job(S, j, x);
+                const int rc = setup_job(S, j, li);
                 rcs.push_back(rc);
                 errs.push_back(rc ? get_error() : "");
-                if (rc) release_job(j);
+                if (rc) {
+                    (void)hipStreamSynchronize(x.s);
+                    release_job(S, j, x.s);
+                }
             }
             lk.lock();
             for (size_t k = 0; k < adm.size(); ++k) {
@@ -225,7 +273,8 @@ void lane_main(encore_server* S, int li)
             if (r == ENCORE_OK) r = finish_job(j, x);
             rcs.push_back(r);
             errs.push_back(r ? (j->rc ? j->err : std::string(get_error())) : "");
-            release_job(j);
+            (void)hipStreamSynchronize(x.s);   // a failed slice may not have synchronised
+            release_job(S, j, x.s);
         }
         lk.lock();
         for (size_t k = 0; k < complete.size(); ++k) {
@@ -270,12 +319,45 @@ int encore_server_create(encore_ctx* ctx, size_t hbm_budget, int n_lanes, int ma
     S->slice_rows = slice_rows;
     S->t0 = Clock::now();
     S->lanes.resize(n_lanes);
+    S->stage.resize(n_lanes);
+    auto undo = [&](int rc) {
+        for (Exec& x : S->lanes) exec_release(x);
+        for (Stage& st : S->stage) {
+            for (hipEvent_t& e : st.ev)
+                if (e) (void)hipEventDestroy(e);
+            if (st.host) (void)hipHostFree(st.host);
+        }
+        if (S->pool) (void)hipMemPoolDestroy(S->pool);
+        delete S;
+        return rc;
+    };
+    // the pool keeps what it has taken from the device until the server ends
+    hipMemPoolProps props;
+    std::memset(&props, 0, sizeof(props));
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = ctx->device;
+    hipError_t e = hipMemPoolCreate(&S->pool, &props);
+    if (e != hipSuccess) {
+        S->pool = nullptr;
+        return undo(hip_fail(e, "hipMemPoolCreate"));
+    }
+    uint64_t keep = UINT64_MAX;
+    e = hipMemPoolSetAttribute(S->pool, hipMemPoolAttrReleaseThreshold, &keep);
+    if (e != hipSuccess) return undo(hip_fail(e, "hipMemPoolSetAttribute"));
     for (int i = 0; i < n_lanes; ++i) {
-        const int rc = exec_init(S->lanes[i]);
-        if (rc) {
-            for (Exec& x : S->lanes) exec_release(x);
-            delete S;
-            return rc;
+        const int rc = exec_init(S->lanes[i], S->pool);
+        if (rc) return undo(rc);
+        Stage& st = S->stage[i];
+        e = hipHostMalloc((void**)&st.host, 2 * kStageHalf, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            st.host = nullptr;
+            return undo(hip_fail(e, "hipHostMalloc(staging)"));
+        }
+        for (hipEvent_t& ev : st.ev) {
+            if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+                return undo(hip_fail(e, "hipEventCreate"));
+            if ((e = hipEventRecord(ev, S->lanes[i].s)) != hipSuccess) return undo(hip_fail(e, "hipEventRecord"));
         }
     }
     for (int i = 0; i < n_lanes; ++i) S->threads.emplace_back(lane_main, S, i);
@@ -414,8 +496,14 @@ int encore_server_destroy(encore_server* S)
     }
     for (std::thread& t : S->threads) t.join();
     (void)hipSetDevice(S->ctx->device);
-    for (auto& kv : S->jobs) release_job(kv.second.get());
-    for (Exec& x : S->lanes) exec_release(x);
+    for (auto& kv : S->jobs) release_job(S, kv.second.get(), S->lanes[0].s);
+    for (Exec& x : S->lanes) exec_release(x);   // synchronises each lane's stream
+    for (Stage& st : S->stage) {
+        for (hipEvent_t& e : st.ev)
+            if (e) (void)hipEventDestroy(e);
+        if (st.host) (void)hipHostFree(st.host);
+    }
+    (void)hipMemPoolDestroy(S->pool);
     delete S;
     return ENCORE_OK;
 }

@@ -47,7 +47,7 @@ SIGNATURES = {
     "encore_free_grid": (_I, [_P]),
     "encore_grid_size": (_I64, [_P]),
     "encore_npcf": (_I, [_P, _P, _I, _I, _I, _P, _U32, _D, _P, _SZ, _P, _I64, _P]),
-    "encore_npcf_batch": (_I, [_P, _P, _I, _I, _I, _I, _P, _U32, _P, _SZ, _P]),
+    "encore_npcf_batch": (_I, [_P, _P, _I, _I, _I, _I, _P, _U32, _P, _SZ, _P, _P, _P]),
     "encore_npcf_splits": (_I, [_P, _P, _P, _I, _I, _I, _I, _P, _U32, _D, _P, _SZ, _P, _SZ, _P]),
     "encore_npcf_simple": (_I, [_P, _P, _I64, _I, _I, _I, _P, _P, _U32, _P, _SZ]),
     "encore_num_multiplets": (_I64, [_I, _I, _U32]),
@@ -325,8 +325,10 @@ class Plan:
 
 
 def npcf_batch(ctx, grids, N, lmax, edges, precision="fp32", allparity=False, normalize=False,
-               stream=None):
-    """encore_npcf_batch: Z for several catalogs, float64 [n_jobs, n_multiplets, n_bin_tuples]."""
+               primaries=None, stream=None):
+    """encore_npcf_batch: Z for several catalogs, float64 [n_jobs, n_multiplets, n_bin_tuples].
+    primaries: None (every point of every catalog), or one entry per job, each None
+    (every point) or an index array of that job's primaries."""
     edges = _f64(edges, (-1,))
     nbins = len(edges) - 1
     flags = PRECISIONS[precision] | (ALLPARITY if allparity else 0) | (NORMALIZE if normalize else 0)
@@ -335,8 +337,26 @@ def npcf_batch(ctx, grids, N, lmax, edges, precision="fp32", allparity=False, no
     nj = len(grids)
     handles = (_P * nj)(*[g.handle.value for g in grids])
     out = np.zeros(max(nj * nlam * nB, 1))
+    subs = counts = None
+    keep = []
+    if primaries is not None:
+        if len(primaries) != nj:
+            raise ValueError("primaries needs one entry per job")
+        subs = (_P * nj)()
+        counts = (ctypes.c_int64 * nj)()
+        for j, p in enumerate(primaries):
+            if p is None:
+                continue
+            a = np.ascontiguousarray(p, dtype=np.int64).reshape(-1)
+            counts[j] = a.size
+            if a.size == 0:
+                a = np.zeros(1, dtype=np.int64)   # a valid pointer for an empty subset
+            keep.append(a)
+            subs[j] = a.ctypes.data
     _check(lib().encore_npcf_batch(ctx.handle, ctypes.cast(handles, _P), nj, int(N), int(lmax), nbins,
-                                   _ptr(edges), flags, _ptr(out), out.size, stream))
+                                   _ptr(edges), flags, _ptr(out), out.size,
+                                   ctypes.cast(subs, _P) if subs is not None else None,
+                                   ctypes.cast(counts, _P) if counts is not None else None, stream))
     return out[:nj * nlam * nB].reshape(nj, nlam, nB)
 
 

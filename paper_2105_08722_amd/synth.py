@@ -21,7 +21,7 @@ import math
 import numpy as np
 
 __all__ = ["uniform_box", "neyman_scott", "survey_wedge", "fkp_weights",
-           "linear_edges", "config"]
+           "linear_edges", "mock_dmr_catalog", "batch_sizes", "config"]
 
 
 def linear_edges(rmin: float, rmax: float, nbins: int) -> np.ndarray:
@@ -121,6 +121,21 @@ def survey_wedge(n_data: int, n_rand: int, seed: int, rmin: float = 600.0,
 
 def fkp_weights(n: int, nbar: float, p0: float = 1e4) -> np.ndarray:
     return np.full(n, 1.0 / (1.0 + nbar * p0))
+
+
+def mock_dmr_catalog(nd: int, box: float, seed: int):
+    """One mock of the batched and served workloads: Neyman-Scott data thinned to
+    nd points plus 3 nd uniform randoms in a periodic cube (input weights 1; the
+    data-minus-randoms weights are formed by the estimator).  Returns (pos, w)."""
+    dpos, dw = neyman_scott(nd, box, seed)
+    rpos, rw = uniform_box(3 * nd, box, seed + 7919)
+    return np.concatenate([dpos, rpos]), np.concatenate([dw, rw])
+
+
+def batch_sizes(njobs: int = 64, seed: int = 4000):
+    """Data counts of the batched workload's mocks, N_D ~ U{50k..400k}; mock k is
+    mock_dmr_catalog(sizes[k], 1000, seed + k)."""
+    return np.random.default_rng(seed).integers(50_000, 400_001, size=njobs)
 
 
 def config(k: int, scale: float = 1.0):

@@ -1,23 +1,16 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Tolerances
+Tolerances (tests/parity_bars.py)
   * FP64 path: the device uses the same FP64 bin decisions as the oracle and FP64
-    arithmetic throughout; differences are rounding-order only.  Bound: 1e-10
-    relative to max|Z| (per multiplet normwise <= 1e-10 where the multiplet is not
-    tiny).
-  * FP32 path: FP32 separations/Y_lm/accumulators in the gather and FP32 products
-    in the coupling with FP64 sums over primaries.  Each a~ carries a relative error
-    of a few 1e-7 for catalogs with positive weights; a product of N-1 of them
-    carries (N-1) times that.  Bound used: 2e-5 normwise per multiplet and 1e-5
-    of max|a~| per harmonic coefficient.
-  * Split-BF16 path: the FP32 gather, then coupling products on the matrix cores
-    with both operands split into bf16 hi + lo and hi*hi + hi*lo + lo*hi summed in
-    FP32 (flushed into FP64 every 256 primaries).  Each product carries at most
-    3 * 2^-18 = 1.1e-5 of its magnitude (two representation errors and the dropped
-    lo*lo term), with random signs across primaries, so the error of a multiplet
-    scales with its conditioning kappa_L = ||sum_i |w_i H_i||| / ||Z_L|| (the oracle
-    returns the sum of magnitudes).  Bound used: 5e-5 of max|Z| and
-    e_L <= 1e-5 max(kappa_L, 1) + 1e-5 for every multiplet.
+    arithmetic throughout; differences are rounding-order only: 1e-10 of max|Z|.
+  * FP32 path: FP32 unit vectors and Y_lm from FP64 separations, compensated FP32
+    accumulators reduced across lanes in FP64, FP32 coupling products, FP64 sums
+    over primaries.  Split-BF16 path: the FP32 gather without compensation, then
+    coupling products on the matrix cores with both operands split into bf16
+    hi + lo and hi*hi + hi*lo + lo*hi summed in FP32 (flushed into FP64 every 256
+    primaries); each product carries at most 3 * 2^-18 = 1.1e-5 of its magnitude.
+    For both, every multiplet meets e_L <= u max(kappa_L, 1) + u with u = 1e-6
+    (FP32) and 1e-5 (split-BF16), kappa_L the conditioning of the sum over primaries.
 """
 import math
 import os
@@ -27,6 +20,7 @@ import numpy as np
 import pytest
 
 import oracle
+import parity_bars as bars
 from paper_2105_08722_amd import encore, synth
 
 pytestmark = pytest.mark.gpu
@@ -84,7 +78,7 @@ def test_alm_fp32_matches_oracle(ctx, lmax):
         ag = encore.debug_alm(ctx, g, lmax, edges, prim, "fp32")
     ao = oracle.alm(pos, w, lmax, edges, box=100.0, primaries=prim)
     for i in range(len(prim)):
-        assert np.max(np.abs(ag[i] - ao[i])) <= 1e-5 * np.max(np.abs(ao[i]))
+        assert np.max(np.abs(ag[i] - ao[i])) <= 1e-6 * np.max(np.abs(ao[i]))
 
 
 def test_alm_clustered_nonperiodic_offset_box(ctx):
@@ -131,19 +125,10 @@ def test_zeta_matches_oracle(ctx, N, lmax, npts, nbins, periodic, allp, precisio
     zo, za = oracle.zeta(pos, w, N, lmax, edges, box=box, parity="all" if allp else "even",
                          return_abs=True)
     assert zg.shape == zo.shape
-    scale = np.max(np.abs(zo))
-    _say("  max|dZ|/max|Z| = %.2e, max e_L = %.2e" % (np.max(np.abs(zg - zo)) / scale,
-                                                       np.max(_normwise(zg, zo))))
+    e, r = bars.check(zg, zo, za, precision, "zeta")
+    _say("  max e_L = %.2e, max e_L/(kappa+1) = %.2e" % (e, r))
     if precision == "fp64":
-        assert np.max(np.abs(zg - zo)) <= 1e-10 * scale
         assert np.max(_normwise(zg, zo)) <= 1e-9
-    elif precision == "fp32":
-        assert np.max(np.abs(zg - zo)) <= 2e-5 * scale
-        assert np.max(_normwise(zg, zo)) <= 5e-4
-    else:
-        kappa = np.linalg.norm(za, axis=1) / np.maximum(np.linalg.norm(zo, axis=1), 1e-300)
-        assert np.max(np.abs(zg - zo)) <= 5e-5 * scale
-        assert np.all(_normwise(zg, zo) <= 1e-5 * np.maximum(kappa, 1.0) + 1e-5)
 
 
 @pytest.mark.parametrize("N,lmax,nbins,npts", [(3, 0, 1, 37), (3, 1, 2, 300), (4, 0, 3, 1), (4, 1, 3, 17)])
@@ -159,12 +144,7 @@ def test_splitbf16_smallest_blocks(ctx, N, lmax, nbins, npts):
         zg = encore.npcf(ctx, g, N, lmax, edges, precision="splitbf16")
     zo, za = oracle.zeta(pos, w, N, lmax, edges, box=L, return_abs=True)
     assert zg.shape == zo.shape
-    if zo.size == 0:
-        return
-    scale = max(np.max(np.abs(zo)), 1e-300)
-    kappa = np.linalg.norm(za, axis=1) / np.maximum(np.linalg.norm(zo, axis=1), 1e-300)
-    assert np.max(np.abs(zg - zo)) <= 5e-5 * scale
-    assert np.all(_normwise(zg, zo) <= 1e-5 * np.maximum(kappa, 1.0) + 1e-5)
+    bars.check(zg, zo, za, "splitbf16", "small blocks")
 
 
 def test_dmr_weights_and_subset(ctx):
@@ -269,9 +249,8 @@ def test_graph_plan_replays_match_eager(ctx, precision):
         with encore.Plan(ctx, g, 4, 3, edges, precision=precision, normalize=True) as plan:
             assert np.array_equal(plan.execute(), zn)
             assert np.array_equal(plan.execute(), zn)
-    zo = oracle.zeta(pos, w, 4, 3, edges, box=60.0)
-    tol = {"fp64": 1e-10, "fp32": 2e-5, "splitbf16": 5e-5}[precision]
-    assert np.max(np.abs(eager - zo)) <= tol * np.max(np.abs(zo))
+    zo, za = oracle.zeta(pos, w, 4, 3, edges, box=60.0, return_abs=True)
+    bars.check(eager, zo, za, precision, "graph plan")
 
 
 def test_autotune_then_parity():
@@ -293,13 +272,14 @@ def test_autotune_then_parity():
                                   n_sample=1000)
             _say("  %s: %s" % (prec, rep))
             assert (rep["cell_divisor"], rep["x_subdivision"]) in [(5, 8), (5, 6), (6, 8), (5, 4), (4, 6), (6, 4), (8, 4), (4, 8)]
-            assert rep["bins_per_item"] in (2, 3)
+            # compiled bins-per-item values at lmax 5: compensated FP32 {2, 1}, FP32 {2, 3}
+            assert rep["bins_per_item"] in ((2, 1) if prec == "fp32" else (2, 3))
             assert 0 < rep["best_ms"] <= rep["default_ms"]
             prim = rng.choice(len(pos), 200, replace=False)
             with encore.build_grid(c, pos, w_in, r_max=edges[-1], box=L, n_data=2500) as g:
                 zg = encore.npcf(c, g, 4, 5, edges, precision=prec, primaries=prim)
-            zo = oracle.zeta(pos, w, 4, 5, edges, box=L, primaries=prim)
-            assert np.max(np.abs(zg - zo)) <= 5e-5 * np.max(np.abs(zo))
+            zo, za = oracle.zeta(pos, w, 4, 5, edges, box=L, primaries=prim, return_abs=True)
+            bars.check(zg, zo, za, prec, "autotuned")
 
 
 # ------------------------------------------------------------------ benchmark workloads
@@ -312,9 +292,10 @@ def test_config1_3pcf_full(ctx):
     with encore.build_grid(ctx, cfg["pos"], cfg["w"], r_max=160.0, box=cfg["box"]) as g:
         zg = encore.npcf(ctx, g, 3, 10, cfg["edges"], precision="fp64")
         zf = encore.npcf(ctx, g, 3, 10, cfg["edges"], precision="fp32")
-    zo = oracle.zeta(cfg["pos"], cfg["w"], 3, 10, cfg["edges"], box=cfg["box"])
-    assert np.max(np.abs(zg - zo)) <= 1e-10 * np.max(np.abs(zo))
-    assert np.max(np.abs(zf - zo)) <= 2e-5 * np.max(np.abs(zo))
+    zo, za = oracle.zeta(cfg["pos"], cfg["w"], 3, 10, cfg["edges"], box=cfg["box"], return_abs=True)
+    bars.check(zg, zo, za, "fp64", "config 1")
+    e, r = bars.check(zf, zo, za, "fp32", "config 1")
+    _say("  fp32: max e_L = %.2e, max e_L/(kappa+1) = %.2e" % (e, r))
 
 
 @pytest.fixture(scope="module")
@@ -336,9 +317,12 @@ def test_config2_alm_full_launch_sampled(ctx, cfg2, precision):
                            n_data=cfg2["n_data"]) as g:
         ag = encore.debug_alm(ctx, g, 5, cfg2["edges"], prim, precision, full_launch=True)
     ao = oracle.alm(cfg2["pos"], w, 5, cfg2["edges"], box=cfg2["box"], primaries=prim)
+    worst = 0.0
     for i in range(len(prim)):
         err = np.max(np.abs(ag[i] - ao[i])) / np.max(np.abs(ao[i]))
-        assert err <= (1e-12 if precision == "fp64" else 1e-5), (i, err)
+        worst = max(worst, err)
+        assert err <= (1e-12 if precision == "fp64" else 1e-6), (i, err)
+    _say("  max |da|/max|a| per row = %.2e" % worst)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "splitbf16"])
@@ -354,16 +338,9 @@ def test_config2_zeta_sampled_primaries(ctx, cfg2, precision):
         zg = encore.npcf(ctx, g, 4, 5, cfg2["edges"], precision=precision, primaries=prim)
     zo, za = oracle.zeta(cfg2["pos"], w, 4, 5, cfg2["edges"], box=cfg2["box"], primaries=prim,
                          return_abs=True)
-    e = _normwise(zg, zo)
-    kappa = np.linalg.norm(za, axis=1) / np.maximum(np.linalg.norm(zo, axis=1), 1e-300)
-    _say("  max e_L = %.3e, median kappa = %.1f" % (e.max(), np.median(kappa)))
-    if precision == "fp64":
-        assert np.max(np.abs(zg - zo)) <= 1e-10 * np.max(np.abs(zo))
-    elif precision == "fp32":
-        # FP32 error grows with the D-R cancellation: e_L <~ few u32 * kappa_L
-        assert np.all(e <= 1e-6 * np.maximum(kappa, 1.0) + 1e-6)
-    else:
-        assert np.all(e <= 1e-5 * np.maximum(kappa, 1.0) + 1e-5)
+    e, r = bars.check(zg, zo, za, precision, "config 2")
+    _say("  max e_L = %.3e, max e_L/(kappa+1) = %.3e, median kappa = %.1f"
+         % (e, r, np.median(bars.kappa(zo, za))))
 
 
 @pytest.fixture(scope="module")
@@ -386,15 +363,13 @@ def test_config3_wedge_sampled_primaries(ctx, cfg3, N, lmax, nprim, precision):
         zg = encore.npcf(ctx, g, N, lmax, cfg3["edges"], precision=precision, primaries=prim)
     zo, za = oracle.zeta(cfg3["pos"], w, N, lmax, cfg3["edges"], primaries=prim, return_abs=True)
     e = _normwise(zg, zo)
-    kappa = np.linalg.norm(za, axis=1) / np.maximum(np.linalg.norm(zo, axis=1), 1e-300)
-    _say("  max e_L = %.3e, median e_L = %.3e, median kappa = %.1f, max e_L/kappa = %.2e"
-         % (e.max(), np.median(e), np.median(kappa), np.max(e / np.maximum(kappa, 1.0))))
-    # The D-R field cancels inside each harmonic coefficient: sum_j |w_j Y_lm| /
-    # |a~_lm| has median ~24 and reaches 1e3..1e5 on this geometry (kappa_L does
-    # not see this), so FP32 accumulation errors are amplified accordingly; the
-    # per-coefficient unit is set from that conditioning.
-    u = 2e-5 if precision == "fp32" else 5e-5
-    assert np.all(e <= u * np.maximum(kappa, 1.0) + u)
+    kappa = bars.kappa(zo, za)
+    _say("  max e_L = %.3e, median e_L = %.3e, median kappa = %.1f, max e_L/(kappa+1) = %.2e"
+         % (e.max(), np.median(e), np.median(kappa), np.max(e / (np.maximum(kappa, 1.0) + 1.0))))
+    # The D-R field cancels inside each harmonic coefficient (sum_j |w_j Y_lm| /
+    # |a~_lm| has median ~24 and reaches 1e3..1e5 on this geometry): the FP32
+    # gather's compensated accumulators keep that from reaching Z.
+    bars.check(zg, zo, za, precision, "wedge")
 
 
 # ------------------------------------------------------------------ batched jobs
@@ -424,13 +399,11 @@ def test_batch_each_job_matches_alone_and_oracle(ctx, precision):
             g.free()
     assert zb.shape[0] == len(grids)
     for j, (pos, w, box) in enumerate(cats):
-        za = alone[j]
-        zo = oracle.zeta(pos, w, N, lmax, edges, box=box)
-        scale = max(np.max(np.abs(zo)), 1e-300)
+        zal = alone[j]
+        zo, zabs = oracle.zeta(pos, w, N, lmax, edges, box=box, return_abs=True)
         # Per-job coupling splits and an in-order reduction: bit-identical to alone.
-        assert np.array_equal(zb[j], za), j
-        tol = {"fp64": 1e-10, "fp32": 2e-5, "splitbf16": 5e-5}[precision]
-        assert np.max(np.abs(zb[j] - zo)) <= tol * scale
+        assert np.array_equal(zb[j], zal), j
+        bars.check(zb[j], zo, zabs, precision, "batched job %d" % j)
     assert np.array_equal(zb[0], zb[-1])
 
 

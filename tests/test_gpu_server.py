@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
+import parity_bars as bars
 from paper_2105_08722_amd import encore
 
 pytestmark = pytest.mark.gpu
@@ -92,9 +93,9 @@ def test_server_mix_equals_alone(ctx, n_lanes):
     assert st["peak_bytes_held"] <= 1 << 30
     # one result of each kind against the oracle
     for sp, jid in list(zip(order, ids))[:3]:
-        zo = oracle.zeta(sp["pos"], sp["w"], sp["N"], sp["lmax"], sp["edges"], box=sp["box"])
-        tol = 1e-10 if sp["precision"] == "fp64" else 2e-5
-        assert np.max(np.abs(results[jid][0] - zo)) <= tol * np.max(np.abs(zo))
+        zo, zabs = oracle.zeta(sp["pos"], sp["w"], sp["N"], sp["lmax"], sp["edges"], box=sp["box"],
+                               return_abs=True)
+        bars.check(results[jid][0], zo, zabs, sp["precision"], "served job")
 
 
 def test_server_admission_budget(ctx):

@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import oracle
+import parity_bars as bars
 from paper_2105_08722_amd import encore, synth
 
 pytestmark = pytest.mark.gpu
@@ -55,15 +56,8 @@ def _free(gd, gs):
 
 
 def _check(zg, zo, za, precision):
-    scale = np.max(np.abs(zo))
-    if precision == "fp64":
-        assert np.max(np.abs(zg - zo)) <= 1e-10 * scale
-    elif precision == "fp32":
-        assert np.max(np.abs(zg - zo)) <= 2e-5 * scale
-    else:
-        kappa = np.linalg.norm(za, axis=1) / np.maximum(np.linalg.norm(zo, axis=1), 1e-300)
-        assert np.max(np.abs(zg - zo)) <= 5e-5 * scale
-        assert np.all(_normwise(zg, zo) <= 1e-5 * np.maximum(kappa, 1.0) + 1e-5)
+    e, r = bars.check(zg, zo, za, precision, "splits")
+    _say("  max e_L = %.2e, max e_L/(kappa+1) = %.2e" % (e, r))
 
 
 CASES = [  # N, lmax, nbins, periodic, allparity, sizes of the random parts
@@ -94,13 +88,13 @@ def test_splits_match_oracle(ctx, monkeypatch, N, lmax, nbins, periodic, allp, s
         _free(gd, gs)
     zo, pero = oracle.split_zeta(dpos, dw, rpos, rw, sizes, N, lmax, edges, box=box, parity=parity)
     assert zg.shape == zo.shape and per.shape == pero.shape
-    # conditioning of each part (sum of magnitudes) for the split-bf16 bar
+    # conditioning of each part (sum of magnitudes) for the reduced-precision bars
     o = 0
     for k, n in enumerate(sizes):
         pos = np.concatenate([dpos, rpos[o:o + n]])
         w = oracle.dmr_weights(dw, rw[o:o + n])
         za = oracle.zeta(pos, w, N, lmax, edges, box=box, parity=parity, return_abs=True)[1] \
-            if precision == "splitbf16" else None
+            if precision != "fp64" else None
         _check(per[k], pero[k], za, precision)
         o += n
     assert np.max(np.abs(zg - per.mean(axis=0))) <= 1e-14 * np.max(np.abs(per))
