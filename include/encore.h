@@ -285,6 +285,29 @@ int encore_autotune(encore_ctx* ctx, const double* pos, const double* w, int64_t
                     const double* box, int npcf, int lmax, int nbins, const double* edges, uint32_t flags,
                     int64_t n_sample, double* report, size_t report_len);
 
+/*
+ * Allocation-free encore_npcf, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Arguments, layout, result and errors as encore_npcf (zeta on the
+ * host; the grid is built beforehand), but the call makes no device allocation and
+ * frees nothing: the coupling tables, the primary list, the per-slice
+ * coefficients and partial sums, the job's sums and zeta all live in one static
+ * scratch array of 256 MiB per device (held from the first encore_create on that
+ * device until the process ends), and slices are sized to fit it.
+ *  - Errors: ESIZE (with the bytes needed) when one slice of at least one coupling
+ *    split no longer fits, e.g. N = 6 at lmax 4 with many bins.
+ *  - Results equal encore_npcf's bit for bit when both run the job as one slice;
+ *    with more slices only the rounding order of the reduced-precision sums
+ *    differs.
+ *  - Every call on a device shares that device's array and leaves its contents
+ *    behind; calls on one context are serialised, calls that overlap on one GPU
+ *    from different contexts or threads race and must not be made.
+ */
+int encore_npcf_noalloc(encore_ctx* ctx, const encore_grid* grid, int npcf, int lmax, int nbins,
+                        const double* edges, uint32_t flags, double volume, double* zeta,
+                        size_t zeta_len, const int64_t* primary_subset, int64_t n_subset,
+                        void* stream);
+
 /* One-shot form: build a grid from host arrays, run encore_npcf, free the grid.
  * r_max = edges[nbins]; box may be NULL for a non-periodic catalog. */
 int encore_npcf_simple(const double* pos, const double* w, int64_t n, int npcf, int lmax,

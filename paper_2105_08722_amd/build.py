@@ -16,7 +16,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libencore.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["gather.hip", "couple.hip", "couple_mfma.hip", "grid.hip", "edge.hip", "engine.cpp", "api.cpp", "server.cpp", "edge.cpp",
+SOURCES = ["gather.hip", "couple.hip", "couple_mfma.hip", "grid.hip", "edge.hip", "noalloc.hip", "engine.cpp", "api.cpp", "server.cpp", "edge.cpp",
            "tables.cpp", "mfma_plan.cpp", "plan.cpp"]
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -18,7 +18,7 @@
 
 using namespace encore;
 
-namespace {
+namespace encore {
 
 // Primaries of one job as cell-sorted indices at dst (device, room for the count):
 // every point (subset NULL) or the subset given in input order.  *np: the count.
@@ -49,6 +49,10 @@ int fill_primaries(Exec& x, const encore_grid* grid, const int64_t* subset, int6
     *np = k;
     return ENCORE_OK;
 }
+
+}  // namespace encore
+
+namespace {
 
 // Primary list of one job into x.prim; returns count in *np.
 int make_primaries(Exec& x, const encore_grid* grid, const int64_t* subset, int64_t k, int64_t* np)
@@ -127,29 +131,18 @@ int check_grids(const encore_grid* const* grids, int njobs, const encore_ctx* ct
 // the data part of a~: measured break-even between 2,000 (0.95x) and 16,000 (1.09x)
 constexpr double kSplitCacheDensity = 6000.0;
 
-struct JobRows {
-    const encore_grid* grid;
-    const int32_t* prim;   // device
-    int64_t nprim;
-    const double4* Pq = nullptr;   // random-split jobs (see Chunk)
-    const void* cache = nullptr;
-};
+}  // namespace
 
-// The hot path over several jobs on the context's main exec (ctx->mu held):
-// slices of at most cap_rows rows, cut only at each job's split boundaries,
-// then one contraction per job; zeta [njobs][nlam][nB] to the host.
-int run_jobs(encore_ctx* ctx, const std::vector<JobRows>& jobs, const NpcfPlan& pl, uint32_t flags,
-             const double* edges, double volume, double* zeta)
+namespace encore {
+
+int run_jobs(encore_ctx* ctx, Exec& x, const DevTables* tb, int64_t cap, const std::vector<JobRows>& jobs,
+             const NpcfPlan& pl, uint32_t flags, const double* edges, double volume, double* zeta)
 {
-    Exec& x = ctx->main;
     const hipStream_t s = x.s;
     const int njobs = (int)jobs.size();
     const size_t need = (size_t)(pl.nlam * pl.nB);
     int rc;
-    DevTables* tb = nullptr;
-    if ((rc = get_tables_for(ctx, pl, &tb))) return rc;
     const int64_t outs = acc_len(pl, tb);
-    const int64_t cap = cap_rows(pl);
     if ((rc = ensure(x.Tjob, sizeof(double) * (size_t)(njobs * outs)))) return rc;
     if ((rc = ensure(x.zeta, sizeof(double) * (size_t)njobs * std::max<size_t>(need, 1)))) return rc;
     if ((rc = ensure(x.misc, 64))) return rc;
@@ -226,6 +219,21 @@ int run_jobs(encore_ctx* ctx, const std::vector<JobRows>& jobs, const NpcfPlan& 
     return ENCORE_OK;
 }
 
+}  // namespace encore
+
+namespace {
+
+// The hot path on the context's main exec, its cached tables and the default
+// slice size (ctx->mu held).
+int run_jobs(encore_ctx* ctx, const std::vector<JobRows>& jobs, const NpcfPlan& pl, uint32_t flags,
+             const double* edges, double volume, double* zeta)
+{
+    DevTables* tb = nullptr;
+    const int rc = get_tables_for(ctx, pl, &tb);
+    if (rc) return rc;
+    return run_jobs(ctx, ctx->main, tb, cap_rows(pl), jobs, pl, flags, edges, volume, zeta);
+}
+
 // Runs f with the main exec on the caller's stream (if any); ctx->mu is held.
 template <typename F>
 int on_stream(encore_ctx* ctx, void* stream, F&& f)
@@ -253,9 +261,11 @@ int encore_create(int hip_device, encore_ctx** out)
     if (hip_device < 0 || hip_device >= ndev)
         return fail(ENCORE_EINVAL, "hip_device out of range (" + std::to_string(ndev) + " devices)");
     HIPTRY(hipSetDevice(hip_device));
+    int rc = noalloc_init(hip_device);   // the scratch address of encore_npcf_noalloc on this device
+    if (rc) return rc;
     auto* c = new encore_ctx();
     c->device = hip_device;
-    const int rc = exec_init(c->main);
+    rc = exec_init(c->main);
     if (rc) {
         exec_release(c->main);
         delete c;

@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 namespace encore {
 
@@ -29,9 +30,27 @@ int hip_fail(hipError_t e, const char* what)
                 std::string(what) + ": " + hipGetErrorString(e));
 }
 
+int arena_take(Arena& A, size_t bytes, void** p)
+{
+    const size_t off = (A.used + 255) / 256 * 256;
+    if (off > A.size || bytes > A.size - off)
+        return fail(ENCORE_ESIZE, "the call needs more than the " + std::to_string(A.size >> 20) +
+                                      " MiB scratch buffer of the allocation-free entry point");
+    *p = A.base + off;
+    A.used = off + bytes;
+    return ENCORE_OK;
+}
+
 int ensure(Buf& b, size_t bytes)
 {
     if (b.n >= bytes && b.p) return ENCORE_OK;
+    if (b.arena) {   // carved from fixed memory: never allocated or freed
+        const size_t want = std::max<size_t>(bytes, 256);
+        const int rc = arena_take(*b.arena, want, &b.p);
+        if (rc) return rc;
+        b.n = want;
+        return ENCORE_OK;
+    }
     dev_free(b.p, b.pool, b.s);
     b.p = nullptr;
     b.n = 0;
@@ -64,10 +83,19 @@ int exec_init(Exec& x, hipMemPool_t pool)
     return ENCORE_OK;
 }
 
+void exec_use_arena(Exec& x, Arena* A)
+{
+    for (int i = 0; Buf* b = exec_bufs(x, i); ++i) {
+        b->arena = A;
+        b->pool = nullptr;
+        b->s = x.s;
+    }
+}
+
 void exec_release(Exec& x)
 {
     for (int i = 0; Buf* b = exec_bufs(x, i); ++i) {
-        dev_free(b->p, b->pool, x.s);
+        if (!b->arena) dev_free(b->p, b->pool, x.s);
         b->p = nullptr;
         b->n = 0;
     }
@@ -163,14 +191,12 @@ static int upload(V*& dst, const std::vector<V>& src)
     return ENCORE_OK;
 }
 
-int get_tables(encore_ctx* ctx, int N, int lmax, bool allparity, int nbins, DevTables** out)
+// Device tables of (N, lmax, parity, nbins) from the host term table; `up(dst,
+// vec)` puts one host vector on the device.
+template <typename Up>
+static int fill_tables(DevTables& d, int N, int lmax, bool allparity, int nbins, Up&& up)
 {
-    std::lock_guard<std::mutex> lock(ctx->tab_mu);
-    auto key = std::make_tuple(N, lmax, allparity, nbins);
-    auto it = ctx->tables.find(key);
-    if (it != ctx->tables.end()) { *out = &it->second; return ENCORE_OK; }
     const TermTable& tt = term_table(N, lmax, allparity);
-    DevTables d;
     d.N = N; d.lmax = lmax; d.nbins = nbins; d.allparity = allparity;
     d.nlam = tt.nlam;
     const int K = N - 1;
@@ -201,11 +227,46 @@ int get_tables(encore_ctx* ctx, int N, int lmax, bool allparity, int nbins, DevT
     std::vector<double> kap(nlm);
     gather_tables(lmax, kap.data());
     int rc;
-    if ((rc = upload(d.tuple_off, toff)) || (rc = upload(d.tuple_flags, tflags)) ||
-        (rc = upload(d.btab, bt)) || (rc = upload(d.term_start, tstart)) ||
-        (rc = upload(d.term_tuple, tt.term_tuple)) || (rc = upload(d.term_coef, tt.coef)) ||
-        (rc = upload(d.kappa, kap)))
+    if ((rc = up(d.tuple_off, toff)) || (rc = up(d.tuple_flags, tflags)) || (rc = up(d.btab, bt)) ||
+        (rc = up(d.term_start, tstart)) || (rc = up(d.term_tuple, tt.term_tuple)) ||
+        (rc = up(d.term_coef, tt.coef)) || (rc = up(d.kappa, kap)))
         return rc;
+    return ENCORE_OK;
+}
+
+// The split-BF16 MFMA plan of the tables' (N, lmax, parity, nbins).
+template <typename Up>
+static int fill_mfma(DevTables& d, const NpcfPlan& pl, Up&& up)
+{
+    const int nent = pl.nbins * (pl.lmax + 1) * (pl.lmax + 2) / 2;
+    if (nent > kMfmaMaxEntries)
+        return fail(ENCORE_EUNSUPPORTED, "ENCORE_PREC_SPLITBF16 needs nbins * (lmax+1)(lmax+2)/2 <= " +
+                                             std::to_string(kMfmaMaxEntries) + " (got " +
+                                             std::to_string(nent) + ")");
+    MfmaPlan P;
+    int rc;
+    if ((rc = build_mfma_plan(pl.N, pl.lmax, pl.allparity, pl.nbins, P))) return rc;
+    if ((rc = up(d.mf_rows, P.rows)) || (rc = up(d.mf_cols, P.cols)) || (rc = up(d.mf_tmap, P.tmap))) return rc;
+    for (int sh = 0; sh < kNumMfmaShapes; ++sh) {
+        if ((rc = up(d.mf_jobs[sh], P.jobs[sh]))) return rc;
+        d.mf_njobs[sh] = (int)(P.jobs[sh].size() / kMfmaJobWidth);
+    }
+    d.mf_KF = P.KF;
+    d.mf_nent = P.nent;
+    d.mf_dense = P.ntiles * 256;
+    d.mf_ready = true;
+    return ENCORE_OK;
+}
+
+int get_tables(encore_ctx* ctx, int N, int lmax, bool allparity, int nbins, DevTables** out)
+{
+    std::lock_guard<std::mutex> lock(ctx->tab_mu);
+    auto key = std::make_tuple(N, lmax, allparity, nbins);
+    auto it = ctx->tables.find(key);
+    if (it != ctx->tables.end()) { *out = &it->second; return ENCORE_OK; }
+    DevTables d;
+    const int rc = fill_tables(d, N, lmax, allparity, nbins, [](auto*& dst, const auto& v) { return upload(dst, v); });
+    if (rc) return rc;
     auto res = ctx->tables.emplace(key, d);
     *out = &res.first->second;
     return ENCORE_OK;
@@ -218,25 +279,25 @@ int get_tables_for(encore_ctx* ctx, const NpcfPlan& pl, DevTables** out)
     DevTables* d = *out;
     std::lock_guard<std::mutex> lock(ctx->tab_mu);
     if (d->mf_ready) return ENCORE_OK;
-    const int nent = pl.nbins * (pl.lmax + 1) * (pl.lmax + 2) / 2;
-    if (nent > kMfmaMaxEntries)
-        return fail(ENCORE_EUNSUPPORTED, "ENCORE_PREC_SPLITBF16 needs nbins * (lmax+1)(lmax+2)/2 <= " +
-                                             std::to_string(kMfmaMaxEntries) + " (got " +
-                                             std::to_string(nent) + ")");
-    MfmaPlan P;
-    if ((rc = build_mfma_plan(pl.N, pl.lmax, pl.allparity, pl.nbins, P))) return rc;
-    if ((rc = upload(d->mf_rows, P.rows)) || (rc = upload(d->mf_cols, P.cols)) ||
-        (rc = upload(d->mf_tmap, P.tmap)))
-        return rc;
-    for (int sh = 0; sh < kNumMfmaShapes; ++sh) {
-        if ((rc = upload(d->mf_jobs[sh], P.jobs[sh]))) return rc;
-        d->mf_njobs[sh] = (int)(P.jobs[sh].size() / kMfmaJobWidth);
-    }
-    d->mf_KF = P.KF;
-    d->mf_nent = P.nent;
-    d->mf_dense = P.ntiles * 256;
-    d->mf_ready = true;
-    return ENCORE_OK;
+    return fill_mfma(*d, pl, [](auto*& dst, const auto& v) { return upload(dst, v); });
+}
+
+int tables_in_arena(Arena& A, hipStream_t s, const NpcfPlan& pl, DevTables& d)
+{
+    auto carve = [&](auto*& dst, const auto& v) -> int {
+        using V = typename std::remove_reference_t<decltype(v)>::value_type;
+        void* p = nullptr;
+        const int rc = arena_take(A, std::max<size_t>(1, v.size()) * sizeof(V), &p);
+        if (rc) return rc;
+        dst = static_cast<V*>(p);
+        // pageable source: the copy has read it when the call returns
+        if (!v.empty()) HIPTRY(hipMemcpyAsync(p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, s));
+        return ENCORE_OK;
+    };
+    int rc = fill_tables(d, pl.N, pl.lmax, pl.allparity, pl.nbins, carve);
+    if (rc == ENCORE_OK && pl.prec == 2) rc = fill_mfma(d, pl, carve);
+    if (rc == ENCORE_OK) HIPTRY(hipStreamSynchronize(s));
+    return rc;
 }
 
 int acc_len_host(const NpcfPlan& pl, int64_t* out)

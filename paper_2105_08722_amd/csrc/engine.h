@@ -47,13 +47,24 @@ struct DevTables {
 };
 
 
+// Fixed device memory handed out front to back (the scratch buffer of the
+// allocation-free entry point): nothing in it is allocated or freed.
+struct Arena {
+    char* base = nullptr;
+    size_t size = 0, used = 0;
+};
+// bytes from the arena (256-byte aligned) or ESIZE
+int arena_take(Arena& A, size_t bytes, void** p);
+
 // A grow-only device buffer.  With a pool it is allocated and freed stream-ordered
-// on stream s (no device-wide synchronisation when it grows).
+// on stream s (no device-wide synchronisation when it grows); with an arena it is
+// carved from it (growing takes new room; nothing is freed).
 struct Buf {
     void* p = nullptr;
     size_t n = 0;
     hipMemPool_t pool = nullptr;
     hipStream_t s = nullptr;
+    Arena* arena = nullptr;
 };
 
 // One stream and the workspaces of the hot path on it.
@@ -66,6 +77,8 @@ struct Exec {
 // pool: null for plain hipMalloc workspaces, else a stream-ordered pool the
 // workspaces come from (on x.s)
 int exec_init(Exec& x, hipMemPool_t pool = nullptr);
+// every workspace of x carved from A instead (x.s must be set)
+void exec_use_arena(Exec& x, Arena* A);
 void exec_release(Exec& x);
 // bytes held by the workspaces
 size_t exec_bytes(const Exec& x);
@@ -196,6 +209,33 @@ struct encore_grid {
 };
 
 namespace encore {
+// Looks up, once per device (the device current), the address of that device's
+// copy of the scratch array of encore_npcf_noalloc.
+int noalloc_init(int device);
+size_t noalloc_scratch_bytes();
+
+// Primaries of one job as cell-sorted indices at dst (device, room for the count):
+// every point (subset NULL) or the subset given in input order (validated; uses
+// x.misc).  *np: the count.
+int fill_primaries(Exec& x, const encore_grid* grid, const int64_t* subset, int64_t k, int32_t* dst,
+                   int64_t* np);
+
+// One job's rows for run_jobs.
+struct JobRows {
+    const encore_grid* grid;
+    const int32_t* prim;   // device
+    int64_t nprim;
+    const double4* Pq = nullptr;   // random-split jobs (see Chunk)
+    const void* cache = nullptr;
+};
+
+// The hot path over several jobs on exec x with tables tb (the caller holds
+// ctx->mu): slices of at most cap rows, cut only at each job's split boundaries,
+// then one contraction per job; zeta [njobs][nlam][nB] to the host; the
+// context's timings are set.
+int run_jobs(encore_ctx* ctx, Exec& x, const DevTables* tb, int64_t cap, const std::vector<JobRows>& jobs,
+             const NpcfPlan& pl, uint32_t flags, const double* edges, double volume, double* zeta);
+
 // tuned bins per work item for a call (0: default); thread-safe
 int ctx_nbg(encore_ctx* ctx, const NpcfPlan& pl);
 void ctx_cells(encore_ctx* ctx, double* div, double* xsub);
@@ -203,4 +243,6 @@ void ctx_cells(encore_ctx* ctx, double* div, double* xsub);
 int get_tables(encore_ctx* ctx, int N, int lmax, bool allparity, int nbins, DevTables** out);
 // tables of the call's precision (the MFMA plan too for split-BF16)
 int get_tables_for(encore_ctx* ctx, const NpcfPlan& pl, DevTables** out);
+// the same tables carved from an arena and copied on stream s (waits for the copies)
+int tables_in_arena(Arena& A, hipStream_t s, const NpcfPlan& pl, DevTables& d);
 }  // namespace encore

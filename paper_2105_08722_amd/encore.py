@@ -47,6 +47,7 @@ SIGNATURES = {
     "encore_free_grid": (_I, [_P]),
     "encore_grid_size": (_I64, [_P]),
     "encore_npcf": (_I, [_P, _P, _I, _I, _I, _P, _U32, _D, _P, _SZ, _P, _I64, _P]),
+    "encore_npcf_noalloc": (_I, [_P, _P, _I, _I, _I, _P, _U32, _D, _P, _SZ, _P, _I64, _P]),
     "encore_npcf_batch": (_I, [_P, _P, _I, _I, _I, _I, _P, _U32, _P, _SZ, _P, _P, _P]),
     "encore_npcf_splits": (_I, [_P, _P, _P, _I, _I, _I, _I, _P, _U32, _D, _P, _SZ, _P, _SZ, _P]),
     "encore_npcf_simple": (_I, [_P, _P, _I64, _I, _I, _I, _P, _P, _U32, _P, _SZ]),
@@ -248,8 +249,9 @@ def build_grid_device(ctx, pos, w, r_max, box=None, n_data=None):
 
 
 def npcf(ctx, grid, N, lmax, edges, precision="fp32", allparity=False, normalize=False, volume=0.0,
-         primaries=None, stream=None):
-    """encore_npcf: Z (or zeta with normalize) as float64 [n_multiplets, n_bin_tuples]."""
+         primaries=None, stream=None, noalloc=False):
+    """encore_npcf: Z (or zeta with normalize) as float64 [n_multiplets, n_bin_tuples].
+    noalloc: call encore_npcf_noalloc instead (no device allocation in the call)."""
     edges = _f64(edges, (-1,))
     nbins = len(edges) - 1
     flags = PRECISIONS[precision] | (ALLPARITY if allparity else 0) | (NORMALIZE if normalize else 0)
@@ -263,8 +265,9 @@ def npcf(ctx, grid, N, lmax, edges, precision="fp32", allparity=False, normalize
         nsub = len(prim)
         if nsub == 0:
             prim = np.zeros(1, dtype=np.int64)
-    _check(lib().encore_npcf(ctx.handle, grid.handle, int(N), int(lmax), nbins, _ptr(edges), flags,
-                             float(volume), _ptr(out), out.size, _ptr(prim), nsub, stream))
+    fn = lib().encore_npcf_noalloc if noalloc else lib().encore_npcf
+    _check(fn(ctx.handle, grid.handle, int(N), int(lmax), nbins, _ptr(edges), flags,
+              float(volume), _ptr(out), out.size, _ptr(prim), nsub, stream))
     return out[:nlam * nB].reshape(nlam, nB)
 
 
