@@ -23,6 +23,11 @@ Functions and the passages they follow
   the mean over the parts.
 * brute_zeta (oracle.brute): O(N_g^N) tuple sum of P*_Lambda, eq.
   brute-force-npcf, with sympy 3j symbols and scipy Y_lm.
+* mesh_alm / mesh_zeta / zeta_from_alm (oracle.mesh): the gridded-data estimator
+  of Section 3.2 (Gridded Data) by its definition -- eq. alm-binned-def as a direct
+  correlation over periodic mesh offsets, cells as primaries weighted by delta, the
+  full M sum -- pinned against the discrete oracle on catalogs moved to their cell
+  centres (tests/test_mesh_oracle.py).
 
 Pins (tests/test_oracle_pins.py): 3j vs sympy; Y_lm vs scipy; the printed
 P_110 value of Section 5.2; the N=3 Legendre closed form (eq. N=3-basis); the
