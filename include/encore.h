@@ -308,6 +308,33 @@ int encore_npcf_noalloc(encore_ctx* ctx, const encore_grid* grid, int npcf, int 
                         size_t zeta_len, const int64_t* primary_subset, int64_t n_subset,
                         void* stream);
 
+/*
+ * Gridded data (Section 3.2, Gridded Data): the multiplets of a density field
+ * given on a periodic mesh, with the harmonic coefficients of every cell from FFTs
+ * (eq. alm-binned-def-fft): a~^b_lm(s) = sum_u delta(s + u) Y_lm(u^) Theta^b(|u|)
+ * over the mesh offsets u (minimum image), computed as batched FP64 complex
+ * transforms, then Z^B_L = sum_s delta(s) sum_M E(L) C^L_M prod_k a~ with every
+ * cell a primary of weight delta(s) (eq. NPCF-mult-binned-estimator, raw: no
+ * 1/V, no 1/v_b), coupled as encore_npcf couples a catalog.  The bin rule is the
+ * discrete one (edges[b]^2 <= |u|^2 < edges[b+1]^2, |u|^2 in FP64), so a catalog
+ * assigned to the mesh cell by cell gives encore_npcf's result for the catalog
+ * moved to its cell centres (h (i + 1/2)).
+ *  delta  device FP64 [nmesh][nmesh][nmesh], delta[(ix * nmesh + iy) * nmesh + iz],
+ *         cell (ix, iy, iz) spanning [ix h, (ix + 1) h) x ..., h = box / nmesh.
+ *  nmesh  2..1024; box > 0 the period; edges[nbins] <= box / 2.
+ *  npcf, lmax, nbins, edges, zeta, zeta_len  as encore_npcf; flags: ENCORE_ALLPARITY
+ *         and one ENCORE_PREC_* (the precision of the coupling; the transforms are
+ *         FP64).  ENCORE_NORMALIZE is EUNSUPPORTED.
+ *  stream hipStream_t (NULL: the context's stream); synchronous.
+ * Device memory: nbins * (lmax+1)(lmax+2)/2 + 1 complex FP64 fields of nmesh^3
+ * cells (kept by the context for later calls) plus the transform's work area.
+ * Timings: [1] the fields, transforms and products, [2] the coupling, [5] 0.
+ * Errors: EINVAL, ESIZE, ENOMEM, EDEVICE, EUNSUPPORTED.
+ */
+int encore_npcf_mesh(encore_ctx* ctx, const double* delta, int nmesh, double box, int npcf, int lmax,
+                     int nbins, const double* edges, uint32_t flags, double* zeta, size_t zeta_len,
+                     void* stream);
+
 /* One-shot form: build a grid from host arrays, run encore_npcf, free the grid.
  * r_max = edges[nbins]; box may be NULL for a non-periodic catalog. */
 int encore_npcf_simple(const double* pos, const double* w, int64_t n, int npcf, int lmax,

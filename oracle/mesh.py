@@ -89,37 +89,44 @@ def mesh_alm(delta, box, lmax, edges, cells):
     return out
 
 
-def zeta_from_alm(a, w, N, lmax, parity="even"):
+def zeta_from_alm(a, w, N, lmax, parity="even", return_abs=False):
     """Z^B_L = sum_i w_i sum_M E(L) C^L_M prod_k a~^{b_k}_{l_k m_k}(i) over every M (full
     sum; a~ of negative m from a~_{l,-m} = (-1)^m conj(a~_{lm}), the weights being
-    real).  a: complex [nprim, nbins, nlm(lmax)].  Re for even, Im for odd multiplets."""
+    real).  a: complex [nprim, nbins, nlm(lmax)].  Re for even, Im for odd multiplets;
+    with return_abs also sum_i |w_i H_i| of the same component (H_i the sum over M
+    of primary i)."""
     a = np.asarray(a)
     w = np.asarray(w, dtype=np.float64)
     nb = a.shape[1]
     lams = multiplets(N, lmax, parity)
     btab = np.array(bin_tuples(N, nb), dtype=np.int64).reshape(-1, N - 1)
-    Z = np.zeros((len(lams), len(btab)), dtype=complex)
-    if len(btab) == 0:
-        return Z.real
-    t_lam, t_l, t_m, t_c = term_arrays(N, lmax, parity)
-
-    def coef(l, m):                                      # [nprim, nbins]
-        v = a[:, :, l * (l + 1) // 2 + abs(m)]
-        return v if m >= 0 else (-1) ** (abs(m) % 2) * np.conj(v)
-
-    for t in range(len(t_lam)):
-        prod = np.full((a.shape[0], len(btab)), t_c[t], dtype=complex)
-        for k in range(N - 1):
-            prod = prod * coef(int(t_l[t, k]), int(t_m[t, k]))[:, btab[:, k]]
-        Z[t_lam[t]] += w @ prod
     odd = np.array([parity_E(N, lam) < 0 for lam in lams], dtype=bool)
-    return np.where(odd[:, None], Z.imag, Z.real)
+    H = np.zeros((len(lams), a.shape[0], len(btab)), dtype=complex)
+    if len(btab) > 0:
+        t_lam, t_l, t_m, t_c = term_arrays(N, lmax, parity)
+
+        def coef(l, m):                                  # [nprim, nbins]
+            v = a[:, :, l * (l + 1) // 2 + abs(m)]
+            return v if m >= 0 else (-1) ** (abs(m) % 2) * np.conj(v)
+
+        for t in range(len(t_lam)):
+            prod = np.full((a.shape[0], len(btab)), t_c[t], dtype=complex)
+            for k in range(N - 1):
+                prod = prod * coef(int(t_l[t, k]), int(t_m[t, k]))[:, btab[:, k]]
+            H[t_lam[t]] += prod
+    wH = H * w[None, :, None]
+    Z = wH.sum(axis=1)
+    z = np.where(odd[:, None], Z.imag, Z.real)
+    if not return_abs:
+        return z
+    comp = np.where(odd[:, None, None], wH.imag, wH.real)
+    return z, np.abs(comp).sum(axis=1)
 
 
-def mesh_zeta(delta, box, N, lmax, edges, parity="even"):
+def mesh_zeta(delta, box, N, lmax, edges, parity="even", return_abs=False):
     """Z of the gridded estimator: every cell with nonzero delta is a primary of
     weight delta(s)."""
     delta = np.asarray(delta, dtype=np.float64)
     cells = np.argwhere(delta != 0.0)
     a = mesh_alm(delta, box, lmax, edges, cells)
-    return zeta_from_alm(a, delta[cells[:, 0], cells[:, 1], cells[:, 2]], N, lmax, parity)
+    return zeta_from_alm(a, delta[cells[:, 0], cells[:, 1], cells[:, 2]], N, lmax, parity, return_abs)

@@ -16,7 +16,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libencore.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["gather.hip", "couple.hip", "couple_mfma.hip", "grid.hip", "edge.hip", "noalloc.hip", "engine.cpp", "api.cpp", "server.cpp", "edge.cpp",
+SOURCES = ["gather.hip", "couple.hip", "couple_mfma.hip", "grid.hip", "edge.hip", "noalloc.hip", "mesh.hip", "engine.cpp", "api.cpp", "server.cpp", "edge.cpp",
            "tables.cpp", "mfma_plan.cpp", "plan.cpp"]
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -40,7 +40,7 @@ def build(verbose=False):
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lhipfft"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (r.stdout, r.stderr))

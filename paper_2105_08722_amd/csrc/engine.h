@@ -72,6 +72,7 @@ struct Exec {
     hipStream_t s = nullptr;
     Buf alm, wprim, T, segs, splits, redp, queues, misc, zeta, bscale, prim, Tjob, almb;
     Buf cache, cmap;   // random splits: the data part of a~ and the row maps
+    Buf mesh, meshd;   // gridded data: the coefficient fields and the transform of delta
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 // pool: null for plain hipMalloc workspaces, else a stream-ordered pool the

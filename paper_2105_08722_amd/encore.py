@@ -48,6 +48,7 @@ SIGNATURES = {
     "encore_grid_size": (_I64, [_P]),
     "encore_npcf": (_I, [_P, _P, _I, _I, _I, _P, _U32, _D, _P, _SZ, _P, _I64, _P]),
     "encore_npcf_noalloc": (_I, [_P, _P, _I, _I, _I, _P, _U32, _D, _P, _SZ, _P, _I64, _P]),
+    "encore_npcf_mesh": (_I, [_P, _P, _I, _D, _I, _I, _I, _P, _U32, _P, _SZ, _P]),
     "encore_npcf_batch": (_I, [_P, _P, _I, _I, _I, _I, _P, _U32, _P, _SZ, _P, _P, _P]),
     "encore_npcf_splits": (_I, [_P, _P, _P, _I, _I, _I, _I, _P, _U32, _D, _P, _SZ, _P, _SZ, _P]),
     "encore_npcf_simple": (_I, [_P, _P, _I64, _I, _I, _I, _P, _P, _U32, _P, _SZ]),
@@ -268,6 +269,28 @@ def npcf(ctx, grid, N, lmax, edges, precision="fp32", allparity=False, normalize
     fn = lib().encore_npcf_noalloc if noalloc else lib().encore_npcf
     _check(fn(ctx.handle, grid.handle, int(N), int(lmax), nbins, _ptr(edges), flags,
               float(volume), _ptr(out), out.size, _ptr(prim), nsub, stream))
+    return out[:nlam * nB].reshape(nlam, nB)
+
+
+def npcf_mesh(ctx, delta, box, N, lmax, edges, precision="fp64", allparity=False, stream=None):
+    """encore_npcf_mesh: Z of a density field on a periodic mesh, float64
+    [n_multiplets, n_bin_tuples].  delta: a float64 CUDA tensor [n, n, n] on the
+    context's device (C order: delta[ix, iy, iz])."""
+    import torch
+    if not (isinstance(delta, torch.Tensor) and delta.is_cuda and delta.dtype == torch.float64):
+        raise TypeError("delta must be a float64 CUDA tensor")
+    if delta.dim() != 3 or not (delta.shape[0] == delta.shape[1] == delta.shape[2]):
+        raise ValueError("delta must be [n, n, n]")
+    delta = delta.contiguous()
+    edges = _f64(edges, (-1,))
+    nbins = len(edges) - 1
+    flags = PRECISIONS[precision] | (ALLPARITY if allparity else 0)
+    nlam = num_multiplets(N, lmax, allparity)
+    nB = num_bin_tuples(N, nbins)
+    out = np.zeros(max(nlam * nB, 1))
+    _check(lib().encore_npcf_mesh(ctx.handle, ctypes.c_void_p(delta.data_ptr()), int(delta.shape[0]),
+                                  float(box), int(N), int(lmax), nbins, _ptr(edges), flags, _ptr(out),
+                                  out.size, stream))
     return out[:nlam * nB].reshape(nlam, nB)
 
 

@@ -21,7 +21,8 @@ import math
 import numpy as np
 
 __all__ = ["uniform_box", "neyman_scott", "survey_wedge", "fkp_weights",
-           "linear_edges", "mock_dmr_catalog", "batch_sizes", "config"]
+           "linear_edges", "mock_dmr_catalog", "batch_sizes", "mesh_counts", "mesh_overdensity",
+           "config"]
 
 
 def linear_edges(rmin: float, rmax: float, nbins: int) -> np.ndarray:
@@ -130,6 +131,23 @@ def mock_dmr_catalog(nd: int, box: float, seed: int):
     dpos, dw = neyman_scott(nd, box, seed)
     rpos, rw = uniform_box(3 * nd, box, seed + 7919)
     return np.concatenate([dpos, rpos]), np.concatenate([dw, rw])
+
+
+def mesh_counts(pos, w, n: int, box: float):
+    """Weights of a catalog summed per cell of a periodic n^3 mesh (cell index
+    floor(x n / box) per axis), C order [ix, iy, iz]: the input field of the gridded
+    workload."""
+    idx = np.floor(np.asarray(pos) / (box / n)).astype(np.int64) % n
+    flat = (idx[:, 0] * n + idx[:, 1]) * n + idx[:, 2]
+    return np.bincount(flat, weights=np.asarray(w, dtype=np.float64), minlength=n ** 3).reshape(n, n, n)
+
+
+def mesh_overdensity(n: int, box: float, npts: int, seed: int):
+    """A clustered overdensity field delta = rho / mean(rho) - 1 on a periodic n^3
+    mesh: a Neyman-Scott catalog of npts points counted per cell."""
+    pos, w = neyman_scott(npts, box, seed)
+    rho = mesh_counts(pos, w, n, box)
+    return rho / rho.mean() - 1.0
 
 
 def batch_sizes(njobs: int = 64, seed: int = 4000):
