@@ -206,6 +206,34 @@ def splits_leg(ctx, edges, precision, nparts, seed=6000):
     return out
 
 
+def mesh_leg(ctx, edges, precision, n=128, box=1000.0):
+    """Gridded data (Section 3.2): a clustered overdensity field (200k Neyman-Scott
+    points counted on a periodic n^3 mesh of the 1000 Mpc/h box, delta = rho/mean - 1,
+    so every cell is a primary), 4PCF lmax=5, 10 bins, through encore_npcf_mesh.  The
+    field stage (kernel fields, forward and inverse FP64 transforms, products) is
+    bounded by HBM: its algorithmic bytes are 7 passes over the nbins*nlm fields of
+    n^3 complex FP64 values (fill; read + write per transform; read + write of the
+    product)."""
+    import torch
+    from paper_2105_08722_amd import encore, synth
+    delta = torch.from_numpy(synth.mesh_overdensity(n, box, 200_000, 7001)).to("cuda:0")
+    encore.npcf_mesh(ctx, delta, box, 4, 5, edges, precision=precision)   # warm: transform plans
+    t0 = time.perf_counter()
+    encore.npcf_mesh(ctx, delta, box, 4, 5, edges, precision=precision)
+    dt = time.perf_counter() - t0
+    tm = ctx.last_timings()
+    nf = (len(edges) - 1) * 21
+    field_bytes = 7.0 * nf * n ** 3 * 16
+    return {"value": n ** 3 / dt, "unit": "cells/s", "seconds": dt, "nmesh": n, "cells": n ** 3,
+            "precision": precision, "field_stage_ms": tm["gather_ms"], "coupling_ms": tm["couple_ms"],
+            "field_stage_roofline": {"bound": "hbm", "unit": "GB/s", "peak": 8000.0,
+                                     "algorithmic_bytes": field_bytes,
+                                     "achieved": field_bytes / (tm["gather_ms"] * 1e-3) / 1e9,
+                                     "frac": field_bytes / (tm["gather_ms"] * 1e-3) / 1e9 / 8000.0},
+            "workload": "gridded 4PCF lmax=5, 10 bins [20,160], %d^3 mesh of a periodic %g Mpc/h box "
+                        "(Neyman-Scott overdensity, every cell a primary)" % (n, box)}
+
+
 def edge_leg(ctx):
     """Edge correction of the paper's analyses (Section 5.4): 4PCF measured at
     lmax = 6 for output lmax = 5, and 5PCF measured at lmax = 4 for output lmax = 3,
@@ -247,6 +275,7 @@ def main():
     ap.add_argument("--precision", default="splitbf16", choices=["fp32", "fp64", "splitbf16"])
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-edge", action="store_true", help="skip the edge-correction leg")
+    ap.add_argument("--no-mesh", action="store_true", help="skip the gridded-data leg")
     ap.add_argument("--split-parts", type=int, default=8, help="random parts of the co-adding leg (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -325,7 +354,7 @@ def main():
     nbg = tuned["bins_per_item"] if tuned else 2
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_ALU_TFLOPS, "traffic": gather_traffic(pairs),
-                "kernel": "k_gather<float,5,%d,0,5> (harmonic-coefficient gather)" % nbg,
+                "kernel": "k_gather<float,5,%d,0,5,false,false> (harmonic-coefficient gather)" % nbg,
                 "launch_ms": g_ms, "pairs_per_launch": pairs,
                 "flops_per_pair": gather_flops_per_pair(L)}
 
@@ -368,6 +397,12 @@ def main():
         extra["random_splits"] = splits_leg(ctx, edges, args.precision, args.split_parts)
         log("random splits: %s" % ", ".join("%s co-added %.3f s vs batch %.3f s" % (k, v["coadded_s"], v["batch_s"])
                                               for k, v in extra["random_splits"].items()))
+    if not args.no_mesh:
+        log("gridded-data leg")
+        extra["gridded"] = mesh_leg(ctx, edges, args.precision)
+        log("gridded: %.1f ms (fields %.1f ms, %.0f GB/s; coupling %.1f ms)"
+            % (extra["gridded"]["seconds"] * 1e3, extra["gridded"]["field_stage_ms"],
+               extra["gridded"]["field_stage_roofline"]["achieved"], extra["gridded"]["coupling_ms"]))
     if not args.no_edge:
         log("edge-correction leg")
         extra["edge_correction"] = edge_leg(ctx)
