@@ -206,6 +206,65 @@ def splits_leg(ctx, edges, precision, nparts, seed=6000):
     return out
 
 
+def mfma_figures(N, L, nbins, nprim, couple_ms):
+    """Matrix-core figures of a split-bf16 coupling from the plan: MFMA flops issued
+    (three 16x16x32 bf16 MFMAs per output tile per 16 primaries) and useful flops
+    (4 per T entry per primary: the real part of a complex product)."""
+    from paper_2105_08722_amd import encore
+    st = encore.mfma_plan_stats(N, L, nbins)
+    raw = st["tiles_per_16"] * 3 * 16 * 16 * 32 * 2 / 16.0 * nprim
+    useful = 4.0 * st["t_entries"] * nprim
+    sec = couple_ms * 1e-3
+    return {"issued_tflops": raw / sec / 1e12, "issued_frac": raw / sec / 1e12 / PEAK_BF16_TFLOPS,
+            "useful_tflops": useful / sec / 1e12,
+            "useful_frac_of_split_peak": useful / sec / 1e12 / (PEAK_BF16_TFLOPS / 3.0),
+            "tiles_per_16_primaries": st["tiles_per_16"], "t_entries_per_primary": st["t_entries"]}
+
+
+def config1_leg(ctx):
+    """The 3PCF workload: 2000 uniform points, periodic 500 Mpc/h, lmax=10, 10 bins
+    [20,160], plain FP64 path, every point a primary (grid build included)."""
+    from paper_2105_08722_amd import encore, synth
+    cfg = synth.config(1)
+    def run():
+        with encore.build_grid(ctx, cfg["pos"], cfg["w"], r_max=160.0, box=cfg["box"]) as g:
+            return encore.npcf(ctx, g, 3, 10, cfg["edges"], precision="fp64")
+    run()
+    t0 = time.perf_counter()
+    run()
+    dt = time.perf_counter() - t0
+    tm = ctx.last_timings()
+    return {"value": 2000 / dt, "unit": "primaries/s", "seconds": dt, "gather_ms": tm["gather_ms"],
+            "couple_ms": tm["couple_ms"], "precision": "fp64", "workload": cfg["name"]}
+
+
+def config3_leg(ctx, precision, n6=200_000):
+    """The survey-wedge workload (500k clustered data + 1.5M randoms, non-periodic
+    wedge with holes, FKP weights, D-R): the 5PCF at lmax=4 over all 2M primaries and
+    the 6PCF at lmax=3 over a seeded subset of n6 primaries (all 2M points are
+    secondaries), with the coupling's matrix-core figures."""
+    import numpy as np
+    from paper_2105_08722_amd import encore, synth
+    cfg = synth.config(3)
+    n = len(cfg["w"])
+    out = {}
+    with encore.build_grid(ctx, cfg["pos"], cfg["w"], r_max=160.0, n_data=cfg["n_data"]) as g:
+        for N, L, prim in [(5, 4, None), (6, 3, np.random.default_rng(6).choice(n, n6, replace=False))]:
+            k = n if prim is None else len(prim)
+            encore.npcf(ctx, g, N, L, cfg["edges"], precision=precision, primaries=prim[:4096] if prim is not None else np.arange(4096))
+            t0 = time.perf_counter()
+            encore.npcf(ctx, g, N, L, cfg["edges"], precision=precision, primaries=prim)
+            dt = time.perf_counter() - t0
+            tm = ctx.last_timings()
+            rec = {"value": k / dt, "unit": "primaries/s", "primaries": k, "seconds": dt,
+                   "gather_ms": tm["gather_ms"], "couple_ms": tm["couple_ms"], "precision": precision}
+            if precision == "splitbf16":
+                rec["coupling_mfma"] = mfma_figures(N, L, len(cfg["edges"]) - 1, k, tm["couple_ms"])
+            out["%dpcf_lmax%d" % (N, L)] = rec
+    out["workload"] = cfg["name"] + "; 5PCF lmax=4 over all primaries, 6PCF lmax=3 over %d seeded primaries" % n6
+    return out
+
+
 def mesh_leg(ctx, edges, precision, n=128, box=1000.0):
     """Gridded data (Section 3.2): a clustered overdensity field (200k Neyman-Scott
     points counted on a periodic n^3 mesh of the 1000 Mpc/h box, delta = rho/mean - 1,
@@ -276,6 +335,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-edge", action="store_true", help="skip the edge-correction leg")
     ap.add_argument("--no-mesh", action="store_true", help="skip the gridded-data leg")
+    ap.add_argument("--no-configs", action="store_true", help="skip the 3PCF (config 1) and survey-wedge legs")
     ap.add_argument("--split-parts", type=int, default=8, help="random parts of the co-adding leg (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -397,6 +457,14 @@ def main():
         extra["random_splits"] = splits_leg(ctx, edges, args.precision, args.split_parts)
         log("random splits: %s" % ", ".join("%s co-added %.3f s vs batch %.3f s" % (k, v["coadded_s"], v["batch_s"])
                                               for k, v in extra["random_splits"].items()))
+    if not args.no_configs:
+        log("3PCF leg")
+        extra["config1_3pcf"] = config1_leg(ctx)
+        log("3PCF: %.3g primaries/s" % extra["config1_3pcf"]["value"])
+        log("survey-wedge leg")
+        extra["config3_wedge"] = config3_leg(ctx, args.precision)
+        log("wedge: 5PCF %.3g primaries/s, 6PCF %.3g primaries/s"
+            % (extra["config3_wedge"]["5pcf_lmax4"]["value"], extra["config3_wedge"]["6pcf_lmax3"]["value"]))
     if not args.no_mesh:
         log("gridded-data leg")
         extra["gridded"] = mesh_leg(ctx, edges, args.precision)

@@ -14,10 +14,9 @@
 //     coefficients over cells (eq. NPCF-mult-binned-estimator, sum over cells for
 //     the integral over s).
 //
-// Layout: delta[(ix * n + iy) * n + iz]; the fields are interleaved per cell,
-// F[cell][b][lm] (complex FP64), so the batched transforms run with element stride
-// nbins * nlm and the inverse transform leaves each cell's coefficients as one
-// contiguous row -- the row layout the coupling reads.
+// Layout: delta[(ix * n + iy) * n + iz]; the fields are contiguous, F[b][lm][cell]
+// (complex FP64), one batched transform over all of them; each slice of cells is
+// transposed through LDS into the coupling's rows [cell][b][lm].
 #include <hip/hip_runtime.h>
 #include <hipfft/hipfft.h>
 
@@ -53,14 +52,14 @@ __device__ __forceinline__ double mesh_dist2(double dx, double dy, double dz)
 
 __device__ __forceinline__ int min_image(int i, int n) { return 2 * i < n ? i : i - n; }
 
-// One thread per (cell offset, field f = b * nlm + lm): K^b_lm at that offset.
-__global__ void __launch_bounds__(kMeshBlock) k_mesh_kernels(MeshKernelArgs a, double2* __restrict__ F, int64_t total)
+// One thread per (field f = b * nlm + lm, cell offset): K^b_lm at that offset.
+__global__ void __launch_bounds__(kMeshBlock) k_mesh_kernels(MeshKernelArgs a, double2* __restrict__ F, int64_t total,
+                                                   int64_t ncell)
 {
     const int64_t e = (int64_t)blockIdx.x * kMeshBlock + threadIdx.x;
     if (e >= total) return;
-    const int nf = a.nbins * a.nlm;
-    const int64_t c = e / nf;
-    const int f = (int)(e - c * nf);
+    const int f = (int)(e / ncell);
+    const int64_t c = e - (int64_t)f * ncell;
     const int b = f / a.nlm, lm = f - b * a.nlm;
     const int n = a.n;
     const int iz = (int)(c % n), iy = (int)((c / n) % n), ix = (int)(c / ((int64_t)n * n));
@@ -97,37 +96,55 @@ __global__ void __launch_bounds__(kMeshBlock) k_mesh_complex(const double* __res
     if (c < ncell) D[c] = make_double2(d[c], 0.0);
 }
 
-// F[cell][f] <- (-1)^l(f) F[delta](cell) F[cell][f] / n^3   (k-space, in place)
+// F[f][k] <- (-1)^l(f) F[delta](k) F[f][k] / n^3   (k-space, in place)
 __global__ void __launch_bounds__(kMeshBlock) k_mesh_product(const double2* __restrict__ D, double2* __restrict__ F,
-                                                   int64_t total, int nf, int nlm, uint64_t odd_mask_lo,
+                                                   int64_t total, int64_t ncell, int nlm, uint64_t odd_mask_lo,
                                                    uint64_t odd_mask_hi, double scale)
 {
     const int64_t e = (int64_t)blockIdx.x * kMeshBlock + threadIdx.x;
     if (e >= total) return;
-    const int64_t c = e / nf;
-    const int lm = (int)(e - c * nf) % nlm;
+    const int f = (int)(e / ncell);
+    const int64_t c = e - (int64_t)f * ncell;
+    const int lm = f % nlm;
     const bool odd = lm < 64 ? ((odd_mask_lo >> lm) & 1) : ((odd_mask_hi >> (lm - 64)) & 1);
     const double s = odd ? -scale : scale;
-    const double2 d = D[c], f = F[e];
-    F[e] = make_double2(s * (d.x * f.x - d.y * f.y), s * (d.x * f.y + d.y * f.x));
+    const double2 d = D[c], v = F[e];
+    F[e] = make_double2(s * (d.x * v.x - d.y * v.y), s * (d.x * v.y + d.y * v.x));
 }
 
 // Rows [0, rows) of a slice: row r is cell prim[r]; its coefficients (FP64, or FP32
-// for the FP32 and split-bf16 couplings) and weight delta(cell).
+// for the FP32 and split-bf16 couplings) and weight delta(cell).  A block moves a
+// tile of kRowTile rows x kFieldTile fields through LDS: reads along the cells of a
+// field, writes along the fields of a row.
+constexpr int kRowTile = 64, kFieldTile = 16;
 template <typename T>
 __global__ void __launch_bounds__(kMeshBlock) k_mesh_rows(const double2* __restrict__ F, const double* __restrict__ delta,
                                                 const int32_t* __restrict__ prim, int64_t rows, int nf,
-                                                T* __restrict__ alm, double* __restrict__ wprim)
+                                                int64_t ncell, T* __restrict__ alm, double* __restrict__ wprim)
 {
-    const int64_t e = (int64_t)blockIdx.x * kMeshBlock + threadIdx.x;
-    if (e >= rows * nf) return;
-    const int64_t r = e / nf;
-    const int f = (int)(e - r * nf);
-    const int64_t c = prim[r];
-    const double2 v = F[c * nf + f];
-    alm[2 * e] = (T)v.x;
-    alm[2 * e + 1] = (T)v.y;
-    if (f == 0) wprim[r] = delta[c];
+    __shared__ double2 tile[kFieldTile][kRowTile + 1];
+    const int64_t r0 = (int64_t)blockIdx.x * kRowTile;
+    const int f0 = blockIdx.y * kFieldTile;
+    for (int i = threadIdx.x; i < kFieldTile * kRowTile; i += kMeshBlock) {
+        const int fi = i / kRowTile, ri = i - fi * kRowTile;
+        const int64_t r = r0 + ri;
+        const int f = f0 + fi;
+        tile[fi][ri] = (r < rows && f < nf) ? F[(int64_t)f * ncell + prim[r]] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kFieldTile * kRowTile; i += kMeshBlock) {
+        const int ri = i / kFieldTile, fi = i - ri * kFieldTile;
+        const int64_t r = r0 + ri;
+        const int f = f0 + fi;
+        if (r < rows && f < nf) {
+            const double2 v = tile[fi][ri];
+            alm[2 * (r * nf + f)] = (T)v.x;
+            alm[2 * (r * nf + f) + 1] = (T)v.y;
+        }
+    }
+    if (blockIdx.y == 0)
+        for (int ri = threadIdx.x; ri < kRowTile; ri += kMeshBlock)
+            if (r0 + ri < rows) wprim[r0 + ri] = delta[prim[r0 + ri]];
 }
 
 unsigned nblk(int64_t n) { return (unsigned)((n + kMeshBlock - 1) / kMeshBlock); }
@@ -245,10 +262,10 @@ extern "C" int encore_npcf_mesh(encore_ctx* ctx, const double* delta, int nmesh,
         have_plan = true;
         FFTTRY(hipfftSetStream(plan, s));
         size_t work = 0;
-        FFTTRY(hipfftMakePlanMany(plan, 3, dims, dims, nf, 1, dims, nf, 1, HIPFFT_Z2Z, nf, &work));
+        FFTTRY(hipfftMakePlanMany(plan, 3, dims, dims, 1, (int)ncell, dims, 1, (int)ncell, HIPFFT_Z2Z, nf, &work));
         hipfftHandle plan1 = 0;
         HIPTRY_DONE(hipEventRecord(x.ev[0], s));
-        hipLaunchKernelGGL(k_mesh_kernels, dim3(nblk(total)), dim3(kMeshBlock), 0, s, ka, F, total);
+        hipLaunchKernelGGL(k_mesh_kernels, dim3(nblk(total)), dim3(kMeshBlock), 0, s, ka, F, total, ncell);
         HIPTRY_DONE(hipGetLastError());
         hipLaunchKernelGGL(k_mesh_complex, dim3(nblk(ncell)), dim3(kMeshBlock), 0, s, delta, D, ncell);
         HIPTRY_DONE(hipGetLastError());
@@ -260,7 +277,7 @@ extern "C" int encore_npcf_mesh(encore_ctx* ctx, const double* delta, int nmesh,
             FFTTRY(fr);
         }
         FFTTRY(hipfftExecZ2Z(plan, (hipfftDoubleComplex*)F, (hipfftDoubleComplex*)F, HIPFFT_FORWARD));
-        hipLaunchKernelGGL(k_mesh_product, dim3(nblk(total)), dim3(kMeshBlock), 0, s, D, F, total, nf, nlm, odd_lo,
+        hipLaunchKernelGGL(k_mesh_product, dim3(nblk(total)), dim3(kMeshBlock), 0, s, D, F, total, ncell, nlm, odd_lo,
                            odd_hi, 1.0 / (double)ncell);
         HIPTRY_DONE(hipGetLastError());
         FFTTRY(hipfftExecZ2Z(plan, (hipfftDoubleComplex*)F, (hipfftDoubleComplex*)F, HIPFFT_BACKWARD));
@@ -287,12 +304,15 @@ extern "C" int encore_npcf_mesh(encore_ctx* ctx, const double* delta, int nmesh,
             if (rc) break;
             hipError_t e = hipEventRecord(x.ev[2], s);
             if (e == hipSuccess) {
+                const dim3 grid((unsigned)((take + kRowTile - 1) / kRowTile), (unsigned)((nf + kFieldTile - 1) / kFieldTile));
                 if (pl.prec == 0)
-                    hipLaunchKernelGGL(k_mesh_rows<double>, dim3(nblk(take * nf)), dim3(kMeshBlock), 0, s, F, delta,
-                                       (const int32_t*)x.prim.p + r0, take, nf, (double*)x.alm.p, (double*)x.wprim.p);
+                    hipLaunchKernelGGL(k_mesh_rows<double>, grid, dim3(kMeshBlock), 0, s, F, delta,
+                                       (const int32_t*)x.prim.p + r0, take, nf, ncell, (double*)x.alm.p,
+                                       (double*)x.wprim.p);
                 else
-                    hipLaunchKernelGGL(k_mesh_rows<float>, dim3(nblk(take * nf)), dim3(kMeshBlock), 0, s, F, delta,
-                                       (const int32_t*)x.prim.p + r0, take, nf, (float*)x.alm.p, (double*)x.wprim.p);
+                    hipLaunchKernelGGL(k_mesh_rows<float>, grid, dim3(kMeshBlock), 0, s, F, delta,
+                                       (const int32_t*)x.prim.p + r0, take, nf, ncell, (float*)x.alm.p,
+                                       (double*)x.wprim.p);
                 e = hipGetLastError();
             }
             if (e == hipSuccess) rc = launch_slice_couple(L, pl, tb, s);
