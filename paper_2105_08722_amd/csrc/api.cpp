@@ -636,8 +636,20 @@ int encore_mfma_plan_stats(int npcf, int lmax, int nbins, uint32_t flags, int64_
     if (nbins < 1 || nbins > kMaxBins) return fail(ENCORE_EINVAL, "nbins out of range");
     if (nbins * (lmax + 1) * (lmax + 2) / 2 > kMfmaMaxEntries)
         return fail(ENCORE_EUNSUPPORTED, "too many coefficients per primary for the MFMA coupling");
-    MfmaPlan P;
     int rc;
+    if (use_gemm_coupling(npcf)) {
+        GemmPlan G;
+        if ((rc = build_gemm_plan(npcf, lmax, flags & ENCORE_ALLPARITY, nbins, gemm_split(npcf), G))) return rc;
+        int64_t ops = 0;
+        for (size_t m = 0; m < G.macros.size() / kGemmMacroWidth; ++m)
+            ops += G.macros[m * kGemmMacroWidth + 2] + G.macros[m * kGemmMacroWidth + 3];
+        out[0] = G.ntiles;
+        out[1] = ops;
+        out[2] = (int64_t)G.tmap.size();
+        out[3] = G.ntiles * 256;
+        return ENCORE_OK;
+    }
+    MfmaPlan P;
     if ((rc = build_mfma_plan(npcf, lmax, flags & ENCORE_ALLPARITY, nbins, P))) return rc;
     int64_t tiles = 0, rts = 0;
     for (int sh = 0; sh < kNumMfmaShapes; ++sh)

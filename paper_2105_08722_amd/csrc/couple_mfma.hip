@@ -21,6 +21,9 @@
 // w_p a~ of its columns (B), both split into bf16 hi + lo.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "device.h"
 
 namespace encore {
@@ -303,6 +306,270 @@ int launch_shape(const MfmaArgs& a, hipStream_t stream)
     return (int)hipGetLastError();
 }
 
+// ---------------------------------------------------------------- macro-tiled GEMM
+// One workgroup per (split, macro tile) of the GEMM plan (mfma_plan.h): per K block
+// of 16 primaries, waves 0..7 form the macro tile's row operand tiles (products of
+// the first KL factors, Re or Im part) and waves 8..15 its column operand tiles (w
+// times the products of the other KR factors), split into bf16 hi + lo and stored in
+// LDS in the MFMA lane order; after a barrier every wave computes its 2 x 2 block of
+// the macro tile's output tiles from those shared operands (three MFMAs each).  A
+// formed operand tile thus feeds up to 8 output tiles instead of at most 4.
+constexpr int kGmWaves = 2 * kGemmMaxTiles;
+constexpr int kGmThreads = kGmWaves * kWave;
+constexpr int kOpBytes = 2 * kWave * 16;      // one operand tile: hi and lo, 16 bytes per lane each
+
+// The product of NF factors for this lane's 4 primaries (4g .. 4g+3) from a staged K
+// block, conjugating the factors flagged in fl.
+template <int NF>
+__device__ __forceinline__ void gemm_product(const unsigned char* stg, const int (&off)[NF], unsigned fl, float (&pr)[4],
+                                             float (&pi)[4])
+{
+    {
+        const float4 v0 = *reinterpret_cast<const float4*>(stg + off[0]);
+        const float4 v1 = *reinterpret_cast<const float4*>(stg + off[0] + 16);
+        const float s = (fl & 1u) ? -1.f : 1.f;
+        pr[0] = v0.x; pi[0] = s * v0.y; pr[1] = v0.z; pi[1] = s * v0.w;
+        pr[2] = v1.x; pi[2] = s * v1.y; pr[3] = v1.z; pi[3] = s * v1.w;
+    }
+#pragma unroll
+    for (int k = 1; k < NF; ++k) {
+        const float4 v0 = *reinterpret_cast<const float4*>(stg + off[k]);
+        const float4 v1 = *reinterpret_cast<const float4*>(stg + off[k] + 16);
+        const float s = ((fl >> k) & 1u) ? -1.f : 1.f;
+        const float ur[4] = {v0.x, v0.z, v1.x, v1.z};
+        const float ui[4] = {s * v0.y, s * v0.w, s * v1.y, s * v1.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float nr = pr[q] * ur[q] - pi[q] * ui[q];
+            const float ni = pr[q] * ui[q] + pi[q] * ur[q];
+            pr[q] = nr; pi[q] = ni;
+        }
+    }
+}
+
+template <int KL, int KR, bool ODD, int ST>
+__global__ void __launch_bounds__(kGmThreads) k_couple_gemm(MfmaArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int blk_b = a.ent_blk * kEntBytes;      // bytes of one K block
+    const int units = (blk_b + 1023) >> 10;       // 1 KiB copy units (64 lanes x 16 bytes)
+    const int stage_b = units << 10;
+    unsigned char* opnd = smem + (size_t)ST * stage_b;
+
+    // blocks of one split run on one XCD (block b is placed on XCD b % 8)
+    const int nmacro = a.njobs;
+    const int li = blockIdx.x >> 3;
+    const int split = (blockIdx.x & 7) + 8 * (li / nmacro);
+    const int mac = li % nmacro;
+    if (split >= a.nsplit) return;          // uniform over the block, before any barrier
+
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int g = lane >> 4, c16 = lane & 15;
+    const int32_t* M = a.jobs + (size_t)mac * kGemmMacroWidth;
+    const int row_start = M[0], col_start = M[1], MR = M[2], MC = M[3], tile_base = M[4];
+
+    // formation role: wave w < 8 forms row tile w, wave w >= 8 column tile w - 8
+    const bool is_col = wid >= kGemmMaxTiles;
+    const int ot = is_col ? wid - kGemmMaxTiles : wid;
+    const bool forms = ot < (is_col ? MC : MR);
+    int roff[KL], coff[KR];
+    unsigned fl = 0;
+#pragma unroll
+    for (int k = 0; k < KL; ++k) roff[k] = 32 * g;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) coff[k] = 32 * g;
+    if (forms) {
+        if (is_col) {
+            const int32_t* c = a.cols + (size_t)(col_start + 16 * ot + c16) * (KR + 1);
+#pragma unroll
+            for (int k = 0; k < KR; ++k) coff[k] = c[k] * kEntBytes + 32 * g;
+            fl = (unsigned)c[KR];
+        } else {
+            const int32_t* r = a.rows + (size_t)(row_start + 16 * ot + c16) * (KL + 1);
+#pragma unroll
+            for (int k = 0; k < KL; ++k) roff[k] = r[k] * kEntBytes + 32 * g;
+            fl = (unsigned)r[KL];
+        }
+    }
+    const bool real = (fl >> 9) & 1u;       // not a padding row / column
+    // output role: tiles (tr0 + i, tc0 + j), i, j in {0, 1}
+    const int tr0 = 2 * (wid >> 2), tc0 = 2 * (wid & 3);
+
+    f32x4 acc[2][2];
+    double acc64[2][2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
+        }
+
+    const int p_lo = a.split_lo[split], p_hi = a.split_hi[split];
+    const int kb0 = p_lo / kBlkRows, kb1 = (p_hi + kBlkRows - 1) / kBlkRows;
+    const int nstep = p_hi > p_lo ? kb1 - kb0 : 0;
+
+    // Copies as in k_couple_mfma: wave wid moves units wid, wid + 16, ..., the same
+    // number (ncp) for every K block, ST - 1 blocks ahead of the one in use.
+    const int ncp = units > wid ? (units - wid + kGmWaves - 1) / kGmWaves : 0;
+    const unsigned char* gsrc = reinterpret_cast<const unsigned char*>(a.alm);
+    auto copy_block = [&](int st) {
+        const int kb = kb0 + (st < nstep ? st : nstep - 1);
+        const unsigned char* src = gsrc + (size_t)kb * blk_b + lane * 16;
+        unsigned char* dst = smem + (size_t)(st % ST) * stage_b;
+        for (int i = 0; i < ncp; ++i) {
+            const int u = wid + kGmWaves * i;
+            const unsigned m0 = (unsigned)(size_t)(dst + (u << 10));
+            asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                         :
+                         : "s"(m0), "v"(src + (u << 10))
+                         : "memory", "m0");
+        }
+    };
+    auto wait_copies = [&]() {
+        // vmcnt <= (ST - 2) * ncp: the copies of this K block have landed (ncp <= 3)
+        static_assert(ST == 3 || ST == 4, "copy wait counts assume 3 or 4 stages");
+        if constexpr (ST == 4) {
+            switch (ncp) {
+            case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+            case 1: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
+            case 2: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+            default: asm volatile("s_waitcnt vmcnt(6)" ::: "memory"); break;
+            }
+        } else {
+            switch (ncp) {
+            case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+            case 1: asm volatile("s_waitcnt vmcnt(1)" ::: "memory"); break;
+            case 2: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
+            default: asm volatile("s_waitcnt vmcnt(3)" ::: "memory"); break;
+            }
+        }
+    };
+
+    if (nstep > 0)
+        for (int st = 0; st < ST - 1; ++st) copy_block(st);
+    for (int st = 0; st < nstep; ++st) {
+        // this wave's copies of K block st have landed; after the barrier every
+        // wave's have, and every wave is done with K block st - 1 (its staged block
+        // and the operands formed from it)
+        wait_copies();
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        copy_block(st + ST - 1);
+        const unsigned char* stg = smem + (size_t)(st % ST) * stage_b;
+        if (forms) {
+            float pr[4], pi[4];
+            u32x4 hi, lo;
+            if (is_col) {
+                gemm_product<KR>(stg, coff, fl, pr, pi);
+                // weights of this lane's primaries 4g .. 4g+3 (padding of entry g); 0
+                // for primaries of a boundary block outside the split
+                float4 w4 = *reinterpret_cast<const float4*>(stg + g * kEntBytes + 128);
+                const int pb = (kb0 + st) * kBlkRows;
+                if (pb < p_lo || pb + kBlkRows > p_hi) {
+                    const int p = pb + 4 * g;
+                    w4.x = (p + 0 >= p_lo && p + 0 < p_hi) ? w4.x : 0.f;
+                    w4.y = (p + 1 >= p_lo && p + 1 < p_hi) ? w4.y : 0.f;
+                    w4.z = (p + 2 >= p_lo && p + 2 < p_hi) ? w4.z : 0.f;
+                    w4.w = (p + 3 >= p_lo && p + 3 < p_hi) ? w4.w : 0.f;
+                }
+                const float ww[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    unsigned h, l;
+                    split2(ww[q] * pr[q], ww[q] * pi[q], h, l);
+                    hi[q] = real ? h : 0u;
+                    lo[q] = real ? l : 0u;
+                }
+            } else {
+                gemm_product<KL>(stg, roff, fl, pr, pi);
+                const bool im = ODD && ((fl >> 8) & 1u);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float x0 = ODD ? (im ? pi[q] : pr[q]) : pr[q];
+                    const float x1 = ODD ? (im ? pr[q] : -pi[q]) : -pi[q];
+                    unsigned h, l;
+                    split2(x0, x1, h, l);
+                    hi[q] = real ? h : 0u;
+                    lo[q] = real ? l : 0u;
+                }
+            }
+            unsigned char* o = opnd + (size_t)wid * kOpBytes + lane * 16;
+            *reinterpret_cast<u32x4*>(o) = hi;
+            *reinterpret_cast<u32x4*>(o + kWave * 16) = lo;
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int tr = tr0 + i;
+            if (tr >= MR) continue;                       // wave-uniform
+            const unsigned char* ar = opnd + (size_t)tr * kOpBytes + lane * 16;
+            const u32x4 ah = *reinterpret_cast<const u32x4*>(ar);
+            const u32x4 al = *reinterpret_cast<const u32x4*>(ar + kWave * 16);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int tc = tc0 + j;
+                if (tc >= MC) continue;
+                const unsigned char* bc = opnd + (size_t)(kGemmMaxTiles + tc) * kOpBytes + lane * 16;
+                const u32x4 bh = *reinterpret_cast<const u32x4*>(bc);
+                const u32x4 bl = *reinterpret_cast<const u32x4*>(bc + kWave * 16);
+                acc[i][j] = mfma(ah, bh, acc[i][j]);
+                acc[i][j] = mfma(ah, bl, acc[i][j]);
+                acc[i][j] = mfma(al, bh, acc[i][j]);
+            }
+        }
+        if ((st + 1) % kFlushSteps == 0 || st + 1 == nstep) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
+                    acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+                }
+        }
+    }
+    // no copy may still be writing LDS when the block ends
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // output tile layout of the 16x16 MFMA: lane holds column c16, rows 4g .. 4g+3
+    double* D = a.D + (size_t)split * a.dense;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int tr = tr0 + i, tc = tc0 + j;
+            if (tr >= MR || tc >= MC) continue;
+            double* t = D + (size_t)(tile_base + tr * MC + tc) * 256;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) t[(4 * g + r) * 16 + c16] = acc64[i][j][r];
+        }
+}
+
+template <int KL, int KR, bool ODD>
+int launch_gemm_shape(const MfmaArgs& a, hipStream_t stream)
+{
+    const int64_t groups = (a.nsplit + 7) / 8;
+    const int64_t blocks = groups * 8 * a.njobs;
+    if (blocks > INT32_MAX) return (int)hipErrorInvalidValue;
+    const size_t stage_b = (blk_bytes(a.nent) + 1023) / 1024 * 1024;
+    const size_t opnd_b = (size_t)kGmWaves * kOpBytes;
+    // four stages while they fit next to the operands in the 160 KiB of LDS, else three
+    const bool four = 4 * stage_b + opnd_b <= (size_t)160 * 1024;
+    const void* fn = four ? reinterpret_cast<const void*>(&k_couple_gemm<KL, KR, ODD, 4>)
+                          : reinterpret_cast<const void*>(&k_couple_gemm<KL, KR, ODD, 3>);
+    const size_t lds = (four ? 4 : 3) * stage_b + opnd_b;
+    static thread_local std::vector<const void*> raised;
+    if (std::find(raised.begin(), raised.end(), fn) == raised.end()) {
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return (int)e;
+        raised.push_back(fn);
+    }
+    MfmaArgs args = a;
+    void* kargs[] = {&args};
+    return (int)hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(kGmThreads), kargs, lds, stream);
+}
+
 // One workgroup per 16-row block: the block's rows are read along the entries
 // (coalesced), transposed through LDS and written as one contiguous block.
 constexpr int kToBlkThreads = 256;
@@ -376,6 +643,21 @@ int launch_to_blocked(const float2* alm, const double* wprim, const GatherSeg* s
     return (int)hipGetLastError();
 }
 
+int launch_couple_gemm(const MfmaArgs& a, int KL, int KR, hipStream_t stream)
+{
+    if (a.njobs == 0 || a.nsplit == 0) return (int)hipSuccess;
+    if (a.nent < 1 || a.nent > kMfmaMaxEntries || a.ent_blk != blk_entries(a.nent))
+        return (int)hipErrorInvalidValue;
+    const bool odd = a.any_odd != 0;
+    switch (KL * 10 + KR) {
+    case 11: return odd ? launch_gemm_shape<1, 1, true>(a, stream) : launch_gemm_shape<1, 1, false>(a, stream);
+    case 21: return odd ? launch_gemm_shape<2, 1, true>(a, stream) : launch_gemm_shape<2, 1, false>(a, stream);
+    case 22: return odd ? launch_gemm_shape<2, 2, true>(a, stream) : launch_gemm_shape<2, 2, false>(a, stream);
+    case 23: return odd ? launch_gemm_shape<2, 3, true>(a, stream) : launch_gemm_shape<2, 3, false>(a, stream);
+    }
+    return (int)hipErrorInvalidValue;
+}
+
 int launch_couple_mfma(const MfmaArgs& a, int KF, int shape, hipStream_t stream)
 {
     if (a.njobs == 0 || a.nsplit == 0) return (int)hipSuccess;
@@ -386,10 +668,6 @@ int launch_couple_mfma(const MfmaArgs& a, int KF, int shape, hipStream_t stream)
     case 3: return launch_kf<1, true>(a, shape, stream);
     case 4: return launch_kf<2, false>(a, shape, stream);
     case 5: return launch_kf<2, true>(a, shape, stream);
-    case 6: return launch_kf<3, false>(a, shape, stream);
-    case 7: return launch_kf<3, true>(a, shape, stream);
-    case 8: return launch_kf<4, false>(a, shape, stream);
-    case 9: return launch_kf<4, true>(a, shape, stream);
     }
     return (int)hipErrorInvalidValue;
 }

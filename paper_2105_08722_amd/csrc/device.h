@@ -172,6 +172,9 @@ struct MfmaArgs {
     int any_odd;              // some rows take the Im part (all-parity multiplets)
 };
 int launch_couple_mfma(const MfmaArgs& a, int KF, int shape, hipStream_t stream);
+// The macro-tiled GEMM of a GemmPlan (mfma_plan.h): rows / cols hold the plan's rows
+// and columns, jobs its macro tiles (njobs of them), KL + KR factors.
+int launch_couple_gemm(const MfmaArgs& a, int KL, int KR, hipStream_t stream);
 
 // Edge correction (one workgroup per bin tuple B): builds the coupling matrix from
 // the Gaunt terms and the random multiplets, solves for zeta (NaN for B with R_0 = 0

@@ -235,6 +235,14 @@ static int fill_tables(DevTables& d, int N, int lmax, bool allparity, int nbins,
     return ENCORE_OK;
 }
 
+bool use_gemm_coupling(int N)
+{
+    // Measured on the survey wedge (200k primaries, 10 bins): 5PCF lmax 4 31 ms
+    // against 80 ms for the per-wave jobs, 6PCF lmax 3 132 ms against 458 ms; the
+    // 4PCF lmax 5 (800k primaries) 44 ms against 14.5 ms: its blocks are too thin.
+    return N >= 5;
+}
+
 // The split-BF16 MFMA plan of the tables' (N, lmax, parity, nbins).
 template <typename Up>
 static int fill_mfma(DevTables& d, const NpcfPlan& pl, Up&& up)
@@ -244,8 +252,24 @@ static int fill_mfma(DevTables& d, const NpcfPlan& pl, Up&& up)
         return fail(ENCORE_EUNSUPPORTED, "ENCORE_PREC_SPLITBF16 needs nbins * (lmax+1)(lmax+2)/2 <= " +
                                              std::to_string(kMfmaMaxEntries) + " (got " +
                                              std::to_string(nent) + ")");
-    MfmaPlan P;
     int rc;
+    if (use_gemm_coupling(pl.N)) {
+        GemmPlan G;
+        if ((rc = build_gemm_plan(pl.N, pl.lmax, pl.allparity, pl.nbins, gemm_split(pl.N), G))) return rc;
+        if ((rc = up(d.mf_rows, G.rows)) || (rc = up(d.mf_cols, G.cols)) || (rc = up(d.mf_tmap, G.tmap)) ||
+            (rc = up(d.mf_macros, G.macros)))
+            return rc;
+        d.mf_gemm = true;
+        d.mf_KL = G.KL;
+        d.mf_KR = G.KR;
+        d.mf_nmacro = (int)(G.macros.size() / kGemmMacroWidth);
+        d.mf_any_odd = G.any_odd;
+        d.mf_nent = G.nent;
+        d.mf_dense = G.ntiles * 256;
+        d.mf_ready = true;
+        return ENCORE_OK;
+    }
+    MfmaPlan P;
     if ((rc = build_mfma_plan(pl.N, pl.lmax, pl.allparity, pl.nbins, P))) return rc;
     if ((rc = up(d.mf_rows, P.rows)) || (rc = up(d.mf_cols, P.cols)) || (rc = up(d.mf_tmap, P.tmap))) return rc;
     for (int sh = 0; sh < kNumMfmaShapes; ++sh) {
@@ -316,10 +340,19 @@ int acc_len_host(const NpcfPlan& pl, int64_t* out)
         if (pl.nbins * (pl.lmax + 1) * (pl.lmax + 2) / 2 > kMfmaMaxEntries)
             return fail(ENCORE_EUNSUPPORTED, "ENCORE_PREC_SPLITBF16 needs nbins * (lmax+1)(lmax+2)/2 <= " +
                                                  std::to_string(kMfmaMaxEntries));
-        MfmaPlan P;
-        const int rc = build_mfma_plan(pl.N, pl.lmax, pl.allparity, pl.nbins, P);
-        if (rc) return rc;
-        it = cache.emplace(key, P.ntiles * 256).first;
+        int64_t dense = 0;
+        if (use_gemm_coupling(pl.N)) {
+            GemmPlan G;
+            const int rc = build_gemm_plan(pl.N, pl.lmax, pl.allparity, pl.nbins, gemm_split(pl.N), G);
+            if (rc) return rc;
+            dense = G.ntiles * 256;
+        } else {
+            MfmaPlan P;
+            const int rc = build_mfma_plan(pl.N, pl.lmax, pl.allparity, pl.nbins, P);
+            if (rc) return rc;
+            dense = P.ntiles * 256;
+        }
+        it = cache.emplace(key, dense).first;
     }
     *out = it->second;
     return ENCORE_OK;
@@ -351,11 +384,19 @@ int64_t cap_rows(const NpcfPlan& pl)
 int64_t job_split_rows(const NpcfPlan& pl, const DevTables* tb, int64_t nprim, int64_t cap)
 {
     if (pl.prec == 2) {
-        // MFMA coupling: one block per (split, 16 wave jobs); aim at ~2048 blocks
+        // MFMA coupling: one block per (split, 16 wave jobs or one macro tile); aim
+        // at ~2048 blocks
         int64_t nbj = 0;
-        for (int sh = 0; sh < kNumMfmaShapes; ++sh) nbj += (tb->mf_njobs[sh] + 15) / 16;
-        const int64_t ns = std::max<int64_t>(1, std::min<int64_t>(1024, 2048 / std::max<int64_t>(nbj, 1)));
-        int64_t rows = std::max<int64_t>(256, (std::max<int64_t>(nprim, 1) + ns - 1) / ns);
+        if (tb->mf_gemm) nbj = tb->mf_nmacro;
+        else
+            for (int sh = 0; sh < kNumMfmaShapes; ++sh) nbj += (tb->mf_njobs[sh] + 15) / 16;
+        // The launch puts split s on XCD s % 8 (its blocks share the split's
+        // coefficients through that XCD's L2), so the count is a multiple of 8: with
+        // fewer splits whole XCDs would idle however many macro tiles there are.
+        const int64_t want = std::max<int64_t>(1, 2048 / std::max<int64_t>(nbj, 1));
+        const int64_t ns = std::min<int64_t>(1024, (want + 7) / 8 * 8);
+        int64_t rows = (std::max<int64_t>(nprim, 1) + ns - 1) / ns;
+        rows = std::max<int64_t>(256, (rows + kBlkRows - 1) / kBlkRows * kBlkRows);
         rows = std::min<int64_t>(cap, rows);
         return std::max<int64_t>(kBlkRows, rows / kBlkRows * kBlkRows);   // whole K blocks
     }
@@ -481,6 +522,11 @@ int prepare_slice(Exec& x, Buf& segs, Buf& splits, Buf& redp, const NpcfPlan& pl
     ma.D = (double*)x.T.p;
     ma.dense = tb->mf_dense;
     ma.any_odd = pl.allparity ? 1 : 0;
+    if (tb->mf_gemm) {
+        ma.jobs = tb->mf_macros;
+        ma.njobs = tb->mf_nmacro;
+        ma.any_odd = tb->mf_any_odd ? 1 : 0;
+    }
 
     ReduceArgs& ra = L.ra;
     ra.T = (const double*)x.T.p;
@@ -509,11 +555,15 @@ int launch_slice_couple(const SliceLaunch& L, const NpcfPlan& pl, const DevTable
     if (pl.prec == 2) {
         HIPTRY((hipError_t)launch_to_blocked((const float2*)L.ga.alm, L.ga.wprim, L.ga.segs, L.ga.nseg,
                                              (int)L.rows, L.ma.nent, (float*)L.ma.alm, s));
-        MfmaArgs ma = L.ma;
-        for (int sh = 0; sh < kNumMfmaShapes; ++sh) {
-            ma.jobs = tb->mf_jobs[sh];
-            ma.njobs = tb->mf_njobs[sh];
-            HIPTRY((hipError_t)launch_couple_mfma(ma, tb->mf_KF, sh, s));
+        if (tb->mf_gemm) {
+            HIPTRY((hipError_t)launch_couple_gemm(L.ma, tb->mf_KL, tb->mf_KR, s));
+        } else {
+            MfmaArgs ma = L.ma;
+            for (int sh = 0; sh < kNumMfmaShapes; ++sh) {
+                ma.jobs = tb->mf_jobs[sh];
+                ma.njobs = tb->mf_njobs[sh];
+                HIPTRY((hipError_t)launch_couple_mfma(ma, tb->mf_KF, sh, s));
+            }
         }
     } else {
         HIPTRY((hipError_t)launch_couple(L.ca, pl.prec, s));

@@ -44,7 +44,15 @@ struct DevTables {
     int32_t* mf_jobs[kNumMfmaShapes] = {nullptr, nullptr, nullptr, nullptr};
     int mf_njobs[kNumMfmaShapes] = {0, 0, 0, 0};
     int32_t* mf_tmap = nullptr;
+    // macro-tiled GEMM plan (used instead of the wave jobs when mf_gemm): mf_rows /
+    // mf_cols hold its rows and columns, mf_macros its macro tiles
+    bool mf_gemm = false;
+    int mf_KL = 0, mf_KR = 0, mf_nmacro = 0;
+    bool mf_any_odd = false;
+    int32_t* mf_macros = nullptr;
 };
+// whether the split-BF16 coupling of N runs as the macro-tiled GEMM
+bool use_gemm_coupling(int N);
 
 
 // Fixed device memory handed out front to back (the scratch buffer of the

@@ -212,4 +212,153 @@ int build_mfma_plan(int N, int lmax, bool allparity, int nbins, MfmaPlan& P)
     return ENCORE_OK;
 }
 
+int gemm_split(int N) { return N == 3 ? 1 : 2; }
+
+int build_gemm_plan(int N, int lmax, bool allparity, int nbins, int KL, GemmPlan& P)
+{
+    const TermTable& tt = term_table(N, lmax, allparity);
+    const int K = N - 1;
+    if (KL < 1 || KL >= K) return fail(ENCORE_EINVAL, "gemm split out of range");
+    const int KR = K - KL;
+    const int nlm = (lmax + 1) * (lmax + 2) / 2;
+    P = GemmPlan();
+    P.K = K; P.KL = KL; P.KR = KR; P.nlm = nlm; P.nbins = nbins; P.nent = nbins * nlm;
+
+    // row keys (l, m of the first KL factors, Im part) and column keys (l, m of the
+    // rest) by the m-sum s of the row factors
+    std::map<int, std::map<std::vector<int>, int>> rkeys, ckeys;
+    auto rkey = [&](int64_t t) {
+        std::vector<int> k;
+        for (int f = 0; f < KL; ++f) { k.push_back(tt.tuple_l[t * K + f]); k.push_back(tt.tuple_m[t * K + f]); }
+        k.push_back(tt.tuple_odd[t]);
+        return k;
+    };
+    auto ckey = [&](int64_t t) {
+        std::vector<int> k;
+        for (int f = KL; f < K; ++f) { k.push_back(tt.tuple_l[t * K + f]); k.push_back(tt.tuple_m[t * K + f]); }
+        return k;
+    };
+    auto msum = [&](int64_t t) {
+        int s = 0;
+        for (int f = 0; f < KL; ++f) s += tt.tuple_m[t * K + f];
+        return s;
+    };
+    for (int64_t t = 0; t < tt.ntuple; ++t) {
+        rkeys[msum(t)][rkey(t)] = 0;
+        ckeys[msum(t)][ckey(t)] = 0;
+        if (tt.tuple_odd[t]) P.any_odd = true;
+    }
+    for (auto& kv : rkeys) { int i = 0; for (auto& e : kv.second) e.second = i++; }
+    for (auto& kv : ckeys) { int i = 0; for (auto& e : kv.second) e.second = i++; }
+
+    struct Block {
+        int64_t row0 = 0, col0 = 0;   // first row / column (multiples of 16)
+        int nrho = 0, nsig = 0;
+        std::map<std::vector<int>, int> pre, suf;   // prefix / suffix bin tuples -> index
+        int64_t macro0 = 0;   // first macro tile
+        int nmr = 0, nmc = 0; // macro tiles along rows / columns
+    };
+    std::map<std::pair<int, int>, Block> blocks;
+    const int RW = KL + 1, CW = KR + 1;
+    int64_t ntiles = 0;
+    for (auto& kv : rkeys) {
+        const int s = kv.first;
+        if (!ckeys.count(s)) continue;
+        const auto& rk = kv.second;
+        const auto& ck = ckeys[s];
+        for (int beta = KL - 1; beta <= nbins - 1 - KR; ++beta) {
+            const std::vector<std::vector<int>> pres = combos(beta, KL - 1);
+            std::vector<std::vector<int>> sufs = combos(nbins - 1 - beta, KR);
+            for (auto& x : sufs)
+                for (int& b : x) b += beta + 1;
+            const int64_t nrow = (int64_t)pres.size() * rk.size();
+            const int64_t ncol = (int64_t)sufs.size() * ck.size();
+            if (nrow == 0 || ncol == 0) continue;
+            Block B;
+            B.nrho = (int)rk.size();
+            B.nsig = (int)ck.size();
+            for (size_t i = 0; i < pres.size(); ++i) B.pre[pres[i]] = (int)i;
+            for (size_t i = 0; i < sufs.size(); ++i) B.suf[sufs[i]] = (int)i;
+            B.row0 = (int64_t)P.rows.size() / RW;
+            B.col0 = (int64_t)P.cols.size() / CW;
+            // rows: key outer, prefix bins inner; padded to a multiple of 16
+            for (const auto& e : rk)
+                for (const auto& pre : pres) {
+                    int flags = 1 << 9;
+                    for (int f = 0; f < KL; ++f) {
+                        const int l = e.first[2 * f], m = e.first[2 * f + 1];
+                        const int bin = f < KL - 1 ? pre[f] : beta;
+                        P.rows.push_back(bin * nlm + lm_of(l, std::abs(m)));
+                        if (m < 0) flags |= 1 << f;
+                    }
+                    if (e.first[2 * KL]) flags |= 1 << 8;
+                    P.rows.push_back(flags);
+                }
+            for (int64_t r = nrow; r % 16; ++r)
+                for (int c = 0; c < RW; ++c) P.rows.push_back(0);
+            // columns: key outer, suffix bins inner
+            for (const auto& e : ck)
+                for (const auto& suf : sufs) {
+                    int flags = 1 << 9;
+                    for (int f = 0; f < KR; ++f) {
+                        const int l = e.first[2 * f], m = e.first[2 * f + 1];
+                        P.cols.push_back(suf[f] * nlm + lm_of(l, std::abs(m)));
+                        if (m < 0) flags |= 1 << f;
+                    }
+                    P.cols.push_back(flags);
+                }
+            for (int64_t c = ncol; c % 16; ++c)
+                for (int k = 0; k < CW; ++k) P.cols.push_back(0);
+            const int nrt = (int)((nrow + 15) / 16), nct = (int)((ncol + 15) / 16);
+            B.nmr = (nrt + kGemmMaxTiles - 1) / kGemmMaxTiles;
+            B.nmc = (nct + kGemmMaxTiles - 1) / kGemmMaxTiles;
+            B.macro0 = (int64_t)P.macros.size() / kGemmMacroWidth;
+            for (int mi = 0; mi < B.nmr; ++mi)
+                for (int mj = 0; mj < B.nmc; ++mj) {
+                    const int MR = std::min(kGemmMaxTiles, nrt - mi * kGemmMaxTiles);
+                    const int MC = std::min(kGemmMaxTiles, nct - mj * kGemmMaxTiles);
+                    P.macros.push_back((int32_t)(B.row0 + (int64_t)mi * kGemmMaxTiles * 16));
+                    P.macros.push_back((int32_t)(B.col0 + (int64_t)mj * kGemmMaxTiles * 16));
+                    P.macros.push_back(MR);
+                    P.macros.push_back(MC);
+                    P.macros.push_back((int32_t)ntiles);
+                    ntiles += (int64_t)MR * MC;
+                }
+            blocks[{s, beta}] = std::move(B);
+        }
+    }
+    if ((int64_t)P.rows.size() / RW > INT32_MAX || (int64_t)P.cols.size() / CW > INT32_MAX ||
+        ntiles * 256 > INT32_MAX)
+        return fail(ENCORE_EUNSUPPORTED, "split-bf16 coupling plan too large for this (N, lmax, nbins)");
+    P.ntiles = ntiles;
+
+    // (t, B) -> dense index; bit 31: (-1)^(sum of |m| over the factors with m < 0)
+    const std::vector<int32_t> bt = enumerate_bin_tuples(N, nbins);
+    const int64_t nB = (int64_t)bt.size() / K;
+    P.tmap.assign((size_t)(tt.ntuple * nB), 0);
+    for (int64_t t = 0; t < tt.ntuple; ++t) {
+        const int s = msum(t);
+        const int rho = rkeys[s][rkey(t)], sig = ckeys[s][ckey(t)];
+        int neg = 0;
+        for (int f = 0; f < K; ++f) {
+            const int m = tt.tuple_m[t * K + f];
+            if (m < 0 && (std::abs(m) & 1)) neg ^= 1;
+        }
+        for (int64_t b = 0; b < nB; ++b) {
+            const int32_t* Bt = &bt[b * K];
+            const Block& B = blocks.at({s, Bt[KL - 1]});
+            const std::vector<int> pre(Bt, Bt + KL - 1), suf(Bt + KL, Bt + K);
+            const int64_t row = (int64_t)rho * (int64_t)B.pre.size() + B.pre.at(pre);
+            const int64_t col = (int64_t)sig * (int64_t)B.suf.size() + B.suf.at(suf);
+            const int64_t rt = row / 16, ct = col / 16;
+            const int mi = (int)(rt / kGemmMaxTiles), mj = (int)(ct / kGemmMaxTiles);
+            const int32_t* M = &P.macros[(B.macro0 + (int64_t)mi * B.nmc + mj) * kGemmMacroWidth];
+            const int64_t tile = M[4] + (rt % kGemmMaxTiles) * M[3] + (ct % kGemmMaxTiles);
+            const int64_t dense = tile * 256 + (row % 16) * 16 + (col % 16);
+            P.tmap[(size_t)(t * nB + b)] = (int32_t)dense | (neg ? (int32_t)0x80000000 : 0);
+        }
+    }
+    return ENCORE_OK;
+}
+
 }  // namespace encore

@@ -29,6 +29,32 @@ struct MfmaPlan {
 };
 int build_mfma_plan(int N, int lmax, bool allparity, int nbins, MfmaPlan& P);
 
+// Plan of the macro-tiled coupling GEMM.  The K = N-1 factors of a tuple are split
+// after the first KL: rows are the products of the first KL factors (their (l, m),
+// the Re or Im part, the bins b_1 < .. < b_KL), columns w times the products of
+// the other KR = K - KL factors (their (l, m), bins b_KL < b_{KL+1} < .. < b_K).
+// Rows and columns are grouped in blocks of fixed (sum of the row factors' m, b_KL):
+// a tuple's row and column meet only inside its block.  Each block is cut into
+// macro tiles of at most kGemmMaxTiles x kGemmMaxTiles 16 x 16 output tiles; one
+// workgroup forms a macro tile's row and column operands once per 16 primaries and
+// computes all its output tiles from them.
+constexpr int kGemmMaxTiles = 8;
+constexpr int kGemmMacroWidth = 5;   // row_start, col_start, row tiles, column tiles, tile_base
+struct GemmPlan {
+    int K = 0, KL = 0, KR = 0, nlm = 0, nbins = 0, nent = 0;
+    bool any_odd = false;
+    std::vector<int32_t> rows;     // [nrow][KL + 1]: entries (bin * nlm + lm of |m|), flags
+    std::vector<int32_t> cols;     // [ncol][KR + 1]: entries, flags
+    std::vector<int32_t> macros;   // [nmacro][kGemmMacroWidth]
+    int64_t ntiles = 0;
+    std::vector<int32_t> tmap;     // [ntuple * nB], as MfmaPlan::tmap
+};
+// flags of a row or column: bit k = factor k has m < 0 (conjugated), bit 8 = the Im
+// part (rows only), bit 9 = a real row or column (not padding)
+int build_gemm_plan(int N, int lmax, bool allparity, int nbins, int KL, GemmPlan& P);
+// the split used for N (rows from the first KL factors)
+int gemm_split(int N);
+
 int fail(int code, const std::string& msg);
 
 }  // namespace encore
