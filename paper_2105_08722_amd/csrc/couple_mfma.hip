@@ -307,16 +307,19 @@ int launch_shape(const MfmaArgs& a, hipStream_t stream)
 }
 
 // ---------------------------------------------------------------- macro-tiled GEMM
-// One workgroup per (split, macro tile) of the GEMM plan (mfma_plan.h): per K block
-// of 16 primaries, waves 0..7 form the macro tile's row operand tiles (products of
-// the first KL factors, Re or Im part) and waves 8..15 its column operand tiles (w
-// times the products of the other KR factors), split into bf16 hi + lo and stored in
-// LDS in the MFMA lane order; after a barrier every wave computes its 2 x 2 block of
-// the macro tile's output tiles from those shared operands (three MFMAs each).  A
-// formed operand tile thus feeds up to 8 output tiles instead of at most 4.
-constexpr int kGmWaves = 2 * kGemmMaxTiles;
+// One workgroup per (split, macro tile) of the GEMM plan (mfma_plan.h).  Wave k
+// forms operand tile k of the macro tile (its row tiles first: products of the
+// first KL factors, Re or Im part; then its column tiles: w times the products of
+// the other KR factors), split into bf16 hi + lo and stored in LDS in the MFMA lane
+// order; wave w computes output tiles w, w + 16, .. (three MFMAs each) from the
+// shared operands.  The two are pipelined over two operand buffers: in one step a
+// wave issues the MFMAs of K block st and forms its operand of K block st + 1, so
+// one barrier per K block separates them.
+constexpr int kGmWaves = kGemmMaxOps;
 constexpr int kGmThreads = kGmWaves * kWave;
-constexpr int kOpBytes = 2 * kWave * 16;      // one operand tile: hi and lo, 16 bytes per lane each
+constexpr int kOpBytes = 2 * kWave * 16;           // one operand tile: hi and lo, 16 bytes per lane each
+constexpr int kGmOpnd = kGemmMaxOps * kOpBytes;    // one operand buffer
+constexpr int kGmOutPerWave = kGemmMaxOut / kGmWaves;
 
 // The product of NF factors for this lane's 4 primaries (4g .. 4g+3) from a staged K
 // block, conjugating the factors flagged in fl.
@@ -354,7 +357,7 @@ __global__ void __launch_bounds__(kGmThreads) k_couple_gemm(MfmaArgs a)
     const int blk_b = a.ent_blk * kEntBytes;      // bytes of one K block
     const int units = (blk_b + 1023) >> 10;       // 1 KiB copy units (64 lanes x 16 bytes)
     const int stage_b = units << 10;
-    unsigned char* opnd = smem + (size_t)ST * stage_b;
+    unsigned char* opnd = smem + (size_t)ST * stage_b;   // two operand buffers of kGmOpnd bytes
 
     // blocks of one split run on one XCD (block b is placed on XCD b % 8)
     const int nmacro = a.njobs;
@@ -369,10 +372,10 @@ __global__ void __launch_bounds__(kGmThreads) k_couple_gemm(MfmaArgs a)
     const int32_t* M = a.jobs + (size_t)mac * kGemmMacroWidth;
     const int row_start = M[0], col_start = M[1], MR = M[2], MC = M[3], tile_base = M[4];
 
-    // formation role: wave w < 8 forms row tile w, wave w >= 8 column tile w - 8
-    const bool is_col = wid >= kGemmMaxTiles;
-    const int ot = is_col ? wid - kGemmMaxTiles : wid;
-    const bool forms = ot < (is_col ? MC : MR);
+    // formation role: operand tile wid (row tile wid, or column tile wid - MR).
+    // Padding rows and columns read real entries; their outputs are never mapped.
+    const bool forms = wid < MR + MC;
+    const bool is_col = wid >= MR;
     int roff[KL], coff[KR];
     unsigned fl = 0;
 #pragma unroll
@@ -381,38 +384,45 @@ __global__ void __launch_bounds__(kGmThreads) k_couple_gemm(MfmaArgs a)
     for (int k = 0; k < KR; ++k) coff[k] = 32 * g;
     if (forms) {
         if (is_col) {
-            const int32_t* c = a.cols + (size_t)(col_start + 16 * ot + c16) * (KR + 1);
+            const int32_t* c = a.cols + (size_t)(col_start + 16 * (wid - MR) + c16) * (KR + 1);
 #pragma unroll
             for (int k = 0; k < KR; ++k) coff[k] = c[k] * kEntBytes + 32 * g;
             fl = (unsigned)c[KR];
         } else {
-            const int32_t* r = a.rows + (size_t)(row_start + 16 * ot + c16) * (KL + 1);
+            const int32_t* r = a.rows + (size_t)(row_start + 16 * wid + c16) * (KL + 1);
 #pragma unroll
             for (int k = 0; k < KL; ++k) roff[k] = r[k] * kEntBytes + 32 * g;
             fl = (unsigned)r[KL];
         }
     }
-    const bool real = (fl >> 9) & 1u;       // not a padding row / column
-    // output role: tiles (tr0 + i, tc0 + j), i, j in {0, 1}
-    const int tr0 = 2 * (wid >> 2), tc0 = 2 * (wid & 3);
+    // output role: tiles wid + 16 j, j < nt (wave-uniform)
+    const int nout = MR * MC;
+    const int nt = nout > wid ? (nout - wid + kGmWaves - 1) / kGmWaves : 0;
+    int aslot[kGmOutPerWave], bslot[kGmOutPerWave];
+#pragma unroll
+    for (int j = 0; j < kGmOutPerWave; ++j) {
+        const int t = wid + kGmWaves * j;
+        aslot[j] = (t / MC) * kOpBytes + lane * 16;
+        bslot[j] = (MR + t % MC) * kOpBytes + lane * 16;
+    }
 
-    f32x4 acc[2][2];
-    double acc64[2][2][4];
+    f32x4 acc[kGmOutPerWave];
+    double acc64[kGmOutPerWave][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < kGmOutPerWave; ++j) {
+        acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
-        }
+        for (int r = 0; r < 4; ++r) acc64[j][r] = 0.0;
+    }
 
     const int p_lo = a.split_lo[split], p_hi = a.split_hi[split];
     const int kb0 = p_lo / kBlkRows, kb1 = (p_hi + kBlkRows - 1) / kBlkRows;
     const int nstep = p_hi > p_lo ? kb1 - kb0 : 0;
 
     // Copies as in k_couple_mfma: wave wid moves units wid, wid + 16, ..., the same
-    // number (ncp) for every K block, ST - 1 blocks ahead of the one in use.
+    // number (ncp <= 3) for every K block.  K block st sits in stage st % ST; past
+    // the last block the last one is copied again (into a stage nobody reads), which
+    // keeps the count of copies per block.
     const int ncp = units > wid ? (units - wid + kGmWaves - 1) / kGmWaves : 0;
     const unsigned char* gsrc = reinterpret_cast<const unsigned char*>(a.alm);
     auto copy_block = [&](int st) {
@@ -428,122 +438,111 @@ __global__ void __launch_bounds__(kGmThreads) k_couple_gemm(MfmaArgs a)
                          : "memory", "m0");
         }
     };
-    auto wait_copies = [&]() {
-        // vmcnt <= (ST - 2) * ncp: the copies of this K block have landed (ncp <= 3)
-        static_assert(ST == 3 || ST == 4, "copy wait counts assume 3 or 4 stages");
-        if constexpr (ST == 4) {
-            switch (ncp) {
-            case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
-            case 1: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
-            case 2: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
-            default: asm volatile("s_waitcnt vmcnt(6)" ::: "memory"); break;
-            }
-        } else {
-            switch (ncp) {
-            case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
-            case 1: asm volatile("s_waitcnt vmcnt(1)" ::: "memory"); break;
-            case 2: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
-            default: asm volatile("s_waitcnt vmcnt(3)" ::: "memory"); break;
-            }
+    // this wave's copies of all but the last `behind` K blocks issued have landed
+    auto wait_copies = [&](int behind) {
+        switch (behind * ncp) {
+        case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+        case 1: asm volatile("s_waitcnt vmcnt(1)" ::: "memory"); break;
+        case 2: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
+        case 3: asm volatile("s_waitcnt vmcnt(3)" ::: "memory"); break;
+        case 4: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+        case 5: asm volatile("s_waitcnt vmcnt(5)" ::: "memory"); break;
+        default: asm volatile("s_waitcnt vmcnt(6)" ::: "memory"); break;
         }
     };
+    static_assert(ST == 2 || ST == 3, "copy wait counts assume 2 or 3 stages");
 
-    if (nstep > 0)
-        for (int st = 0; st < ST - 1; ++st) copy_block(st);
-    for (int st = 0; st < nstep; ++st) {
-        // this wave's copies of K block st have landed; after the barrier every
-        // wave's have, and every wave is done with K block st - 1 (its staged block
-        // and the operands formed from it)
-        wait_copies();
-        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-        copy_block(st + ST - 1);
+    // forms this wave's operand of K block st (staged) into operand buffer st & 1
+    auto form = [&](int st) {
         const unsigned char* stg = smem + (size_t)(st % ST) * stage_b;
-        if (forms) {
-            float pr[4], pi[4];
-            u32x4 hi, lo;
-            if (is_col) {
-                gemm_product<KR>(stg, coff, fl, pr, pi);
-                // weights of this lane's primaries 4g .. 4g+3 (padding of entry g); 0
-                // for primaries of a boundary block outside the split
-                float4 w4 = *reinterpret_cast<const float4*>(stg + g * kEntBytes + 128);
-                const int pb = (kb0 + st) * kBlkRows;
-                if (pb < p_lo || pb + kBlkRows > p_hi) {
-                    const int p = pb + 4 * g;
-                    w4.x = (p + 0 >= p_lo && p + 0 < p_hi) ? w4.x : 0.f;
-                    w4.y = (p + 1 >= p_lo && p + 1 < p_hi) ? w4.y : 0.f;
-                    w4.z = (p + 2 >= p_lo && p + 2 < p_hi) ? w4.z : 0.f;
-                    w4.w = (p + 3 >= p_lo && p + 3 < p_hi) ? w4.w : 0.f;
-                }
-                const float ww[4] = {w4.x, w4.y, w4.z, w4.w};
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    unsigned h, l;
-                    split2(ww[q] * pr[q], ww[q] * pi[q], h, l);
-                    hi[q] = real ? h : 0u;
-                    lo[q] = real ? l : 0u;
-                }
-            } else {
-                gemm_product<KL>(stg, roff, fl, pr, pi);
-                const bool im = ODD && ((fl >> 8) & 1u);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float x0 = ODD ? (im ? pi[q] : pr[q]) : pr[q];
-                    const float x1 = ODD ? (im ? pr[q] : -pi[q]) : -pi[q];
-                    unsigned h, l;
-                    split2(x0, x1, h, l);
-                    hi[q] = real ? h : 0u;
-                    lo[q] = real ? l : 0u;
-                }
+        float pr[4], pi[4];
+        u32x4 hi, lo;
+        if (is_col) {
+            gemm_product<KR>(stg, coff, fl, pr, pi);
+            // weights of this lane's primaries 4g .. 4g+3 (padding of entry g); 0
+            // for primaries of a boundary block outside the split
+            float4 w4 = *reinterpret_cast<const float4*>(stg + g * kEntBytes + 128);
+            const int pb = (kb0 + st) * kBlkRows;
+            if (pb < p_lo || pb + kBlkRows > p_hi) {
+                const int p = pb + 4 * g;
+                w4.x = (p + 0 >= p_lo && p + 0 < p_hi) ? w4.x : 0.f;
+                w4.y = (p + 1 >= p_lo && p + 1 < p_hi) ? w4.y : 0.f;
+                w4.z = (p + 2 >= p_lo && p + 2 < p_hi) ? w4.z : 0.f;
+                w4.w = (p + 3 >= p_lo && p + 3 < p_hi) ? w4.w : 0.f;
             }
-            unsigned char* o = opnd + (size_t)wid * kOpBytes + lane * 16;
-            *reinterpret_cast<u32x4*>(o) = hi;
-            *reinterpret_cast<u32x4*>(o + kWave * 16) = lo;
+            const float ww[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                unsigned h, l;
+                split2(ww[q] * pr[q], ww[q] * pi[q], h, l);
+                hi[q] = h;
+                lo[q] = l;
+            }
+        } else {
+            gemm_product<KL>(stg, roff, fl, pr, pi);
+            const bool im = ODD && ((fl >> 8) & 1u);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float x0 = ODD ? (im ? pi[q] : pr[q]) : pr[q];
+                const float x1 = ODD ? (im ? pr[q] : -pi[q]) : -pi[q];
+                unsigned h, l;
+                split2(x0, x1, h, l);
+                hi[q] = h;
+                lo[q] = l;
+            }
         }
+        unsigned char* o = opnd + (size_t)(st & 1) * kGmOpnd + (size_t)wid * kOpBytes + lane * 16;
+        *reinterpret_cast<u32x4*>(o) = hi;
+        *reinterpret_cast<u32x4*>(o + kWave * 16) = lo;
+    };
+
+    if (nstep > 0) {
+        for (int st = 0; st < ST; ++st) copy_block(st);
+        wait_copies(ST - 1);
+        asm volatile("s_barrier" ::: "memory");
+        if (forms) form(0);
+    }
+    for (int st = 0; st < nstep; ++st) {
+        // After the barrier: every wave's operands of K block st are in buffer st & 1,
+        // K block st + 1 is staged, and every wave is done with step st - 1 (its
+        // MFMA reads of buffer (st + 1) & 1 and its reads of K block st's stage,
+        // which the next copy overwrites).
+        wait_copies(ST - 2);
         asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        copy_block(st + ST);
+        const unsigned char* ob = opnd + (size_t)(st & 1) * kGmOpnd;
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int tr = tr0 + i;
-            if (tr >= MR) continue;                       // wave-uniform
-            const unsigned char* ar = opnd + (size_t)tr * kOpBytes + lane * 16;
-            const u32x4 ah = *reinterpret_cast<const u32x4*>(ar);
-            const u32x4 al = *reinterpret_cast<const u32x4*>(ar + kWave * 16);
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int tc = tc0 + j;
-                if (tc >= MC) continue;
-                const unsigned char* bc = opnd + (size_t)(kGemmMaxTiles + tc) * kOpBytes + lane * 16;
-                const u32x4 bh = *reinterpret_cast<const u32x4*>(bc);
-                const u32x4 bl = *reinterpret_cast<const u32x4*>(bc + kWave * 16);
-                acc[i][j] = mfma(ah, bh, acc[i][j]);
-                acc[i][j] = mfma(ah, bl, acc[i][j]);
-                acc[i][j] = mfma(al, bh, acc[i][j]);
-            }
+        for (int j = 0; j < kGmOutPerWave; ++j) {
+            if (j >= nt) break;                           // wave-uniform
+            const u32x4 ah = *reinterpret_cast<const u32x4*>(ob + aslot[j]);
+            const u32x4 al = *reinterpret_cast<const u32x4*>(ob + aslot[j] + kWave * 16);
+            const u32x4 bh = *reinterpret_cast<const u32x4*>(ob + bslot[j]);
+            const u32x4 bl = *reinterpret_cast<const u32x4*>(ob + bslot[j] + kWave * 16);
+            acc[j] = mfma(ah, bh, acc[j]);
+            acc[j] = mfma(ah, bl, acc[j]);
+            acc[j] = mfma(al, bh, acc[j]);
         }
+        if (forms && st + 1 < nstep) form(st + 1);
         if ((st + 1) % kFlushSteps == 0 || st + 1 == nstep) {
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < kGmOutPerWave; ++j) {
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
-                    acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-                }
+                for (int r = 0; r < 4; ++r) acc64[j][r] += (double)acc[j][r];
+                acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
         }
     }
     // no copy may still be writing LDS when the block ends
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     // output tile layout of the 16x16 MFMA: lane holds column c16, rows 4g .. 4g+3
-    double* D = a.D + (size_t)split * a.dense;
+    double* D = a.D + (size_t)split * a.dense + (size_t)tile_base * 256;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < kGmOutPerWave; ++j) {
+        if (j >= nt) break;
+        double* t = D + (size_t)(wid + kGmWaves * j) * 256;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int tr = tr0 + i, tc = tc0 + j;
-            if (tr >= MR || tc >= MC) continue;
-            double* t = D + (size_t)(tile_base + tr * MC + tc) * 256;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) t[(4 * g + r) * 16 + c16] = acc64[i][j][r];
-        }
+        for (int r = 0; r < 4; ++r) t[(4 * g + r) * 16 + c16] = acc64[j][r];
+    }
 }
 
 template <int KL, int KR, bool ODD>
@@ -553,12 +552,14 @@ int launch_gemm_shape(const MfmaArgs& a, hipStream_t stream)
     const int64_t blocks = groups * 8 * a.njobs;
     if (blocks > INT32_MAX) return (int)hipErrorInvalidValue;
     const size_t stage_b = (blk_bytes(a.nent) + 1023) / 1024 * 1024;
-    const size_t opnd_b = (size_t)kGmWaves * kOpBytes;
-    // four stages while they fit next to the operands in the 160 KiB of LDS, else three
-    const bool four = 4 * stage_b + opnd_b <= (size_t)160 * 1024;
-    const void* fn = four ? reinterpret_cast<const void*>(&k_couple_gemm<KL, KR, ODD, 4>)
-                          : reinterpret_cast<const void*>(&k_couple_gemm<KL, KR, ODD, 3>);
-    const size_t lds = (four ? 4 : 3) * stage_b + opnd_b;
+    const size_t opnd_b = 2 * (size_t)kGmOpnd;
+    // three stages while they fit next to the two operand buffers in the 160 KiB of
+    // LDS, else two (blocks of <= 256 entries: 37 KiB)
+    const bool three = 3 * stage_b + opnd_b <= (size_t)160 * 1024;
+    if (!three && 2 * stage_b + opnd_b > (size_t)160 * 1024) return (int)hipErrorInvalidValue;
+    const void* fn = three ? reinterpret_cast<const void*>(&k_couple_gemm<KL, KR, ODD, 3>)
+                           : reinterpret_cast<const void*>(&k_couple_gemm<KL, KR, ODD, 2>);
+    const size_t lds = (three ? 3 : 2) * stage_b + opnd_b;
     static thread_local std::vector<const void*> raised;
     if (std::find(raised.begin(), raised.end(), fn) == raised.end()) {
         const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -650,10 +651,9 @@ int launch_couple_gemm(const MfmaArgs& a, int KL, int KR, hipStream_t stream)
         return (int)hipErrorInvalidValue;
     const bool odd = a.any_odd != 0;
     switch (KL * 10 + KR) {
-    case 11: return odd ? launch_gemm_shape<1, 1, true>(a, stream) : launch_gemm_shape<1, 1, false>(a, stream);
-    case 21: return odd ? launch_gemm_shape<2, 1, true>(a, stream) : launch_gemm_shape<2, 1, false>(a, stream);
     case 22: return odd ? launch_gemm_shape<2, 2, true>(a, stream) : launch_gemm_shape<2, 2, false>(a, stream);
     case 23: return odd ? launch_gemm_shape<2, 3, true>(a, stream) : launch_gemm_shape<2, 3, false>(a, stream);
+    case 32: return odd ? launch_gemm_shape<3, 2, true>(a, stream) : launch_gemm_shape<3, 2, false>(a, stream);
     }
     return (int)hipErrorInvalidValue;
 }

@@ -212,7 +212,36 @@ int build_mfma_plan(int N, int lmax, bool allparity, int nbins, MfmaPlan& P)
     return ENCORE_OK;
 }
 
-int gemm_split(int N) { return N == 3 ? 1 : 2; }
+int gemm_split(int N) { return N == 3 ? 1 : (N == 6 ? 3 : 2); }
+
+// Cost of one K block of an MR x MC macro tile in CU cycles, a model of the
+// kernel: each operand tile takes ~320 SIMD cycles of VALU to form (products,
+// weights, bf16 hi + lo split), each output tile three 16-cycle MFMAs; both are
+// spread over the 4 SIMDs and mostly overlap; ~400 more for the K block's copy
+// and the barrier.
+static double macro_cost(int MR, int MC)
+{
+    const double F = 320.0 * ((MR + MC + 3) / 4), M = 48.0 * ((MR * MC + 3) / 4);
+    return std::max(F, M) + 0.25 * std::min(F, M) + 400.0;
+}
+
+void gemm_macro_shape(int nrt, int nct, int* mr, int* mc)
+{
+    double best = 0.0;
+    *mr = *mc = 1;
+    for (int r = 1; r <= std::min(nrt, kGemmMaxOps - 1); ++r) {
+        const int c = std::min(kGemmMaxOps - r, kGemmMaxOut / r);
+        const int nr = (nrt + r - 1) / r, nc = (nct + c - 1) / c;
+        double cost = 0.0;
+        for (int i = 0; i < nr; ++i)
+            for (int j = 0; j < nc; ++j) cost += macro_cost(std::min(r, nrt - i * r), std::min(c, nct - j * c));
+        if (r == 1 || cost < best) {
+            best = cost;
+            *mr = r;
+            *mc = c;
+        }
+    }
+}
 
 int build_gemm_plan(int N, int lmax, bool allparity, int nbins, int KL, GemmPlan& P)
 {
@@ -256,7 +285,8 @@ int build_gemm_plan(int N, int lmax, bool allparity, int nbins, int KL, GemmPlan
         int nrho = 0, nsig = 0;
         std::map<std::vector<int>, int> pre, suf;   // prefix / suffix bin tuples -> index
         int64_t macro0 = 0;   // first macro tile
-        int nmr = 0, nmc = 0; // macro tiles along rows / columns
+        int mr = 0, mc = 0;   // macro tile shape (row tiles, column tiles)
+        int nmc = 0;          // macro tiles along the columns
     };
     std::map<std::pair<int, int>, Block> blocks;
     const int RW = KL + 1, CW = KR + 1;
@@ -310,15 +340,16 @@ int build_gemm_plan(int N, int lmax, bool allparity, int nbins, int KL, GemmPlan
             for (int64_t c = ncol; c % 16; ++c)
                 for (int k = 0; k < CW; ++k) P.cols.push_back(0);
             const int nrt = (int)((nrow + 15) / 16), nct = (int)((ncol + 15) / 16);
-            B.nmr = (nrt + kGemmMaxTiles - 1) / kGemmMaxTiles;
-            B.nmc = (nct + kGemmMaxTiles - 1) / kGemmMaxTiles;
+            P.blocks.push_back(nrt);
+            P.blocks.push_back(nct);
+            gemm_macro_shape(nrt, nct, &B.mr, &B.mc);
+            B.nmc = (nct + B.mc - 1) / B.mc;
             B.macro0 = (int64_t)P.macros.size() / kGemmMacroWidth;
-            for (int mi = 0; mi < B.nmr; ++mi)
-                for (int mj = 0; mj < B.nmc; ++mj) {
-                    const int MR = std::min(kGemmMaxTiles, nrt - mi * kGemmMaxTiles);
-                    const int MC = std::min(kGemmMaxTiles, nct - mj * kGemmMaxTiles);
-                    P.macros.push_back((int32_t)(B.row0 + (int64_t)mi * kGemmMaxTiles * 16));
-                    P.macros.push_back((int32_t)(B.col0 + (int64_t)mj * kGemmMaxTiles * 16));
+            for (int r0 = 0; r0 < nrt; r0 += B.mr)
+                for (int c0 = 0; c0 < nct; c0 += B.mc) {
+                    const int MR = std::min(B.mr, nrt - r0), MC = std::min(B.mc, nct - c0);
+                    P.macros.push_back((int32_t)(B.row0 + (int64_t)r0 * 16));
+                    P.macros.push_back((int32_t)(B.col0 + (int64_t)c0 * 16));
                     P.macros.push_back(MR);
                     P.macros.push_back(MC);
                     P.macros.push_back((int32_t)ntiles);
@@ -351,9 +382,9 @@ int build_gemm_plan(int N, int lmax, bool allparity, int nbins, int KL, GemmPlan
             const int64_t row = (int64_t)rho * (int64_t)B.pre.size() + B.pre.at(pre);
             const int64_t col = (int64_t)sig * (int64_t)B.suf.size() + B.suf.at(suf);
             const int64_t rt = row / 16, ct = col / 16;
-            const int mi = (int)(rt / kGemmMaxTiles), mj = (int)(ct / kGemmMaxTiles);
+            const int mi = (int)(rt / B.mr), mj = (int)(ct / B.mc);
             const int32_t* M = &P.macros[(B.macro0 + (int64_t)mi * B.nmc + mj) * kGemmMacroWidth];
-            const int64_t tile = M[4] + (rt % kGemmMaxTiles) * M[3] + (ct % kGemmMaxTiles);
+            const int64_t tile = M[4] + (rt % B.mr) * M[3] + (ct % B.mc);
             const int64_t dense = tile * 256 + (row % 16) * 16 + (col % 16);
             P.tmap[(size_t)(t * nB + b)] = (int32_t)dense | (neg ? (int32_t)0x80000000 : 0);
         }

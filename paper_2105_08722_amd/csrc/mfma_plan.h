@@ -35,10 +35,13 @@ int build_mfma_plan(int N, int lmax, bool allparity, int nbins, MfmaPlan& P);
 // the other KR = K - KL factors (their (l, m), bins b_KL < b_{KL+1} < .. < b_K).
 // Rows and columns are grouped in blocks of fixed (sum of the row factors' m, b_KL):
 // a tuple's row and column meet only inside its block.  Each block is cut into
-// macro tiles of at most kGemmMaxTiles x kGemmMaxTiles 16 x 16 output tiles; one
-// workgroup forms a macro tile's row and column operands once per 16 primaries and
-// computes all its output tiles from them.
-constexpr int kGemmMaxTiles = 8;
+// macro tiles of MR x MC 16 x 16 output tiles, MR + MC <= kGemmMaxOps and MR * MC <=
+// kGemmMaxOut; one workgroup forms a macro tile's MR + MC operand tiles once per 16
+// primaries and computes all its output tiles from them.  The shape is chosen per
+// block: thin blocks (few row tiles) take long macro tiles, so that their row
+// operands are formed fewer times.
+constexpr int kGemmMaxOps = 16;      // operand tiles of a macro tile (one per wave)
+constexpr int kGemmMaxOut = 64;      // output tiles of a macro tile (four per wave)
 constexpr int kGemmMacroWidth = 5;   // row_start, col_start, row tiles, column tiles, tile_base
 struct GemmPlan {
     int K = 0, KL = 0, KR = 0, nlm = 0, nbins = 0, nent = 0;
@@ -46,6 +49,7 @@ struct GemmPlan {
     std::vector<int32_t> rows;     // [nrow][KL + 1]: entries (bin * nlm + lm of |m|), flags
     std::vector<int32_t> cols;     // [ncol][KR + 1]: entries, flags
     std::vector<int32_t> macros;   // [nmacro][kGemmMacroWidth]
+    std::vector<int32_t> blocks;   // [nblock][2]: row tiles, column tiles of each block
     int64_t ntiles = 0;
     std::vector<int32_t> tmap;     // [ntuple * nB], as MfmaPlan::tmap
 };
@@ -54,6 +58,8 @@ struct GemmPlan {
 int build_gemm_plan(int N, int lmax, bool allparity, int nbins, int KL, GemmPlan& P);
 // the split used for N (rows from the first KL factors)
 int gemm_split(int N);
+// macro tile shape (row tiles, column tiles) for a block of nrt x nct output tiles
+void gemm_macro_shape(int nrt, int nct, int* mr, int* mc);
 
 int fail(int code, const std::string& msg);
 

@@ -64,7 +64,7 @@ static void check_case(int N, int L, bool allp, int nbins, int KL, int nprim, un
     const size_t nmacro = P.macros.size() / kGemmMacroWidth;
     for (size_t mc = 0; mc < nmacro; ++mc) {
         const int32_t* M = &P.macros[mc * kGemmMacroWidth];
-        if (M[2] < 1 || M[2] > kGemmMaxTiles || M[3] < 1 || M[3] > kGemmMaxTiles) {
+        if (M[2] < 1 || M[3] < 1 || M[2] + M[3] > kGemmMaxOps || M[2] * M[3] > kGemmMaxOut) {
             std::printf("FAIL N=%d L=%d: macro shape %d x %d\n", N, L, M[2], M[3]);
             ++failures;
             return;
@@ -77,7 +77,7 @@ static void check_case(int N, int L, bool allp, int nbins, int KL, int nprim, un
                         const int32_t* col = &P.cols[(size_t)(M[1] + tc * 16 + j) * (KR + 1)];
                         double s = 0.0;
                         for (int p = 0; p < nprim; ++p) {
-                            // padding rows / columns form zero operands
+                            // padding rows / columns: their outputs are never mapped
                             const cd pl = (row[KL] & (1 << 9)) ? prod_of(row, KL, row[KL], p) : cd(0.0);
                             const cd pr = (col[KR] & (1 << 9)) ? w[p] * prod_of(col, KR, col[KR], p) : cd(0.0);
                             const bool im = row[KL] & (1 << 8);
@@ -138,6 +138,8 @@ int main()
     check_case(6, 2, false, 6, 2, 2, 8);
     check_case(6, 1, true, 6, 2, 2, 9);
     check_case(6, 2, false, 6, 3, 2, 10);
+    check_case(6, 2, true, 7, 3, 2, 12);
+    check_case(5, 2, false, 10, 2, 1, 13);   // long thin blocks
     check_case(4, 3, false, 2, 2, 2, 11);   // nbins < N-1: no bin tuples
     if (failures) {
         std::printf("%d failures\n", failures);
