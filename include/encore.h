@@ -133,9 +133,11 @@ int64_t encore_grid_size(const encore_grid* grid);
  *          i restricted; secondaries are always the whole catalog).
  *  stream  hipStream_t (NULL: the context's stream).  Synchronous: returns once zeta
  *          is on the host.
- * Errors: EINVAL, ESIZE, ENOMEM, EDEVICE, EUNSUPPORTED (ENCORE_PREC_SPLITBF16 with
- * nbins * (lmax+1)(lmax+2)/2 > 256: the coefficients of one primary must fit the
- * coupling kernel's LDS stage).
+ * Errors: EINVAL, ESIZE, ENOMEM, EDEVICE, EUNSUPPORTED (ENCORE_PREC_SPLITBF16 when
+ * the coupling's output tiles outnumber its 32-bit index, e.g. the 6PCF at lmax 4
+ * with 16 bins).  The split-bf16 coupling stages each 16-primary block of
+ * coefficients in LDS up to 256 coefficients per primary and reads larger blocks
+ * (up to 16 bins x 66 coefficients) in global memory.
  *
  * Precision modes (the precision of the harmonic coefficients, the coupling
  * products and the sum over primaries): FP64 / FP64 / FP64 (plain path); FP32 /

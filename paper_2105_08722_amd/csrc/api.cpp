@@ -634,7 +634,7 @@ int encore_mfma_plan_stats(int npcf, int lmax, int nbins, uint32_t flags, int64_
     if (npcf < 3 || npcf > 6) return fail(ENCORE_EINVAL, "npcf must be 3..6");
     if (!valid_lmax(npcf, lmax)) return fail(ENCORE_EINVAL, "lmax out of range for this N");
     if (nbins < 1 || nbins > kMaxBins) return fail(ENCORE_EINVAL, "nbins out of range");
-    if (nbins * (lmax + 1) * (lmax + 2) / 2 > kMfmaMaxEntries)
+    if (nbins * (lmax + 1) * (lmax + 2) / 2 > kMfmaMaxAllEntries)
         return fail(ENCORE_EUNSUPPORTED, "too many coefficients per primary for the MFMA coupling");
     int rc;
     if (use_gemm_coupling(npcf)) {

@@ -64,8 +64,11 @@ __device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c)
 }
 
 // ODD: some rows take the Im part (all-parity multiplets); otherwise every row
-// takes the Re part and no per-row select is needed.
-template <int KF, int RT, int NC, bool ODD>
+// takes the Re part and no per-row select is needed.  GL: the K blocks are read
+// where they lie in global memory (through the L2) instead of being staged in LDS,
+// for blocks too large for the stages (more than kMfmaMaxEntries coefficients per
+// primary).
+template <int KF, int RT, int NC, bool ODD, bool GL>
 __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -94,11 +97,16 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
         tile_base = a.jobs[job * kMfmaJobWidth + 2];
     }
     // this lane's row of each row tile: byte offsets of its factor entries in a K
-    // block (entries are below kMfmaMaxEntries, offsets fit 16 bits, two per word)
-    // and flags (conjugate bits 0..3, bit 4 = Im part), 5 flag bits per row tile;
-    // padded rows and columns read entry 0, their outputs are never mapped
-    constexpr int KW = (KF + 1) / 2;
+    // block (staged blocks have at most kMfmaMaxEntries entries, so the offsets fit
+    // 16 bits, two per word; GL keeps them whole) and flags (conjugate bits 0..3,
+    // bit 4 = Im part), 5 flag bits per row tile; padded rows and columns read entry
+    // 0, their outputs are never mapped
+    constexpr int KW = GL ? KF : (KF + 1) / 2;
     unsigned roff[RT][KW], rfl = 0;
+    auto row_off = [&](int rt, int k) -> unsigned {
+        if constexpr (GL) return roff[rt][k];
+        else return (roff[rt][k / 2] >> (16 * (k & 1))) & 0xffffu;
+    };
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const int r = row_base + rt * 16 + c16;
@@ -107,7 +115,8 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
 #pragma unroll
         for (int k = 0; k < KF; ++k) {
             const unsigned e = active ? (unsigned)a.rows[r * (KF + 1) + k] : 0u;
-            roff[rt][k / 2] |= (e * kEntBytes + 32 * g) << (16 * (k & 1));
+            if constexpr (GL) roff[rt][k] = e * kEntBytes + 32 * g;
+            else roff[rt][k / 2] |= (e * kEntBytes + 32 * g) << (16 * (k & 1));
         }
         const unsigned f = active ? (unsigned)a.rows[r * (KF + 1) + KF] : 0u;
         rfl |= ((f & 15u) | (((f >> 8) & 1u) << 4)) << (5 * rt);
@@ -172,17 +181,20 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
         }
     };
 
-    if (nstep > 0)
+    if (!GL && nstep > 0)
         for (int st = 0; st < kStages - 1; ++st) copy_block(st);
     for (int st = 0; st < nstep; ++st) {
         // this wave's copies of K block st have landed; after the barrier every
         // wave's have, and every wave has finished K block st - 1, whose stage the
         // next copy overwrites
-        wait_copies();
-        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-        copy_block(st + kStages - 1);
+        if constexpr (!GL) {
+            wait_copies();
+            asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+            copy_block(st + kStages - 1);
+        }
         if (active) {
-            const unsigned char* stg = smem + (size_t)(st % kStages) * stage_b;
+            const unsigned char* stg = GL ? gsrc + (size_t)(kb0 + st) * blk_b
+                                          : smem + (size_t)(st % kStages) * stage_b;
             // weights of this lane's primaries 4g .. 4g+3 (padding of entry g)
             float4 w4 = *reinterpret_cast<const float4*>(stg + g * kEntBytes + 128);
             const int pb = (kb0 + st) * kBlkRows;
@@ -216,7 +228,7 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
                 float pr[4], pi[4];
                 const unsigned fl = rfl >> (5 * rt);
                 {
-                    const float2* src = reinterpret_cast<const float2*>(A + (roff[rt][0] & 0xffffu));
+                    const float2* src = reinterpret_cast<const float2*>(A + row_off(rt, 0));
                     const float4 v0 = *reinterpret_cast<const float4*>(src);
                     const float4 v1 = *reinterpret_cast<const float4*>(src + 2);
                     const float s = (fl & 1u) ? -1.f : 1.f;
@@ -225,8 +237,7 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
                 }
 #pragma unroll
                 for (int k = 1; k < KF; ++k) {
-                    const float2* src = reinterpret_cast<const float2*>(
-                        A + ((roff[rt][k / 2] >> (16 * (k & 1))) & 0xffffu));
+                    const float2* src = reinterpret_cast<const float2*>(A + row_off(rt, k));
                     const float4 v0 = *reinterpret_cast<const float4*>(src);
                     const float4 v1 = *reinterpret_cast<const float4*>(src + 2);
                     const float s = ((fl >> k) & 1u) ? -1.f : 1.f;
@@ -291,9 +302,13 @@ int launch_shape(const MfmaArgs& a, hipStream_t stream)
     const int64_t groups = (a.nsplit + 7) / 8;
     const int64_t blocks = groups * 8 * nbj;
     if (blocks > INT32_MAX) return (int)hipErrorInvalidValue;
+    if (a.nent > kMfmaMaxEntries) {
+        k_couple_mfma<KF, RT, NC, ODD, true><<<dim3((unsigned)blocks), dim3(kMfThreads), 0, stream>>>(a);
+        return (int)hipGetLastError();
+    }
     const size_t stage_b = (blk_bytes(a.nent) + 1023) / 1024 * 1024;
     const size_t lds = kStages * stage_b;
-    auto fn = k_couple_mfma<KF, RT, NC, ODD>;
+    auto fn = k_couple_mfma<KF, RT, NC, ODD, false>;
     static bool attr_set = false;
     if (!attr_set) {
         const size_t max_lds = kStages * ((blk_bytes(kMfmaMaxEntries) + 1023) / 1024 * 1024);
@@ -350,14 +365,15 @@ __device__ __forceinline__ void gemm_product(const unsigned char* stg, const int
     }
 }
 
-template <int KL, int KR, bool ODD, int ST>
+// GL: K blocks read in global memory, not staged (as for k_couple_mfma).
+template <int KL, int KR, bool ODD, int ST, bool GL>
 __global__ void __launch_bounds__(kGmThreads) k_couple_gemm(MfmaArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int blk_b = a.ent_blk * kEntBytes;      // bytes of one K block
     const int units = (blk_b + 1023) >> 10;       // 1 KiB copy units (64 lanes x 16 bytes)
     const int stage_b = units << 10;
-    unsigned char* opnd = smem + (size_t)ST * stage_b;   // two operand buffers of kGmOpnd bytes
+    unsigned char* opnd = smem + (GL ? 0 : (size_t)ST * stage_b);   // two operand buffers of kGmOpnd bytes
 
     // blocks of one split run on one XCD (block b is placed on XCD b % 8)
     const int nmacro = a.njobs;
@@ -454,7 +470,7 @@ __global__ void __launch_bounds__(kGmThreads) k_couple_gemm(MfmaArgs a)
 
     // forms this wave's operand of K block st (staged) into operand buffer st & 1
     auto form = [&](int st) {
-        const unsigned char* stg = smem + (size_t)(st % ST) * stage_b;
+        const unsigned char* stg = GL ? gsrc + (size_t)(kb0 + st) * blk_b : smem + (size_t)(st % ST) * stage_b;
         float pr[4], pi[4];
         u32x4 hi, lo;
         if (is_col) {
@@ -497,9 +513,11 @@ __global__ void __launch_bounds__(kGmThreads) k_couple_gemm(MfmaArgs a)
     };
 
     if (nstep > 0) {
-        for (int st = 0; st < ST; ++st) copy_block(st);
-        wait_copies(ST - 1);
-        asm volatile("s_barrier" ::: "memory");
+        if constexpr (!GL) {
+            for (int st = 0; st < ST; ++st) copy_block(st);
+            wait_copies(ST - 1);
+            asm volatile("s_barrier" ::: "memory");
+        }
         if (forms) form(0);
     }
     for (int st = 0; st < nstep; ++st) {
@@ -507,9 +525,9 @@ __global__ void __launch_bounds__(kGmThreads) k_couple_gemm(MfmaArgs a)
         // K block st + 1 is staged, and every wave is done with step st - 1 (its
         // MFMA reads of buffer (st + 1) & 1 and its reads of K block st's stage,
         // which the next copy overwrites).
-        wait_copies(ST - 2);
+        if constexpr (!GL) wait_copies(ST - 2);
         asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-        copy_block(st + ST);
+        if constexpr (!GL) copy_block(st + ST);
         const unsigned char* ob = opnd + (size_t)(st & 1) * kGmOpnd;
 #pragma unroll
         for (int j = 0; j < kGmOutPerWave; ++j) {
@@ -554,12 +572,15 @@ int launch_gemm_shape(const MfmaArgs& a, hipStream_t stream)
     const size_t stage_b = (blk_bytes(a.nent) + 1023) / 1024 * 1024;
     const size_t opnd_b = 2 * (size_t)kGmOpnd;
     // three stages while they fit next to the two operand buffers in the 160 KiB of
-    // LDS, else two (blocks of <= 256 entries: 37 KiB)
-    const bool three = 3 * stage_b + opnd_b <= (size_t)160 * 1024;
-    if (!three && 2 * stage_b + opnd_b > (size_t)160 * 1024) return (int)hipErrorInvalidValue;
-    const void* fn = three ? reinterpret_cast<const void*>(&k_couple_gemm<KL, KR, ODD, 3>)
-                           : reinterpret_cast<const void*>(&k_couple_gemm<KL, KR, ODD, 2>);
-    const size_t lds = (three ? 3 : 2) * stage_b + opnd_b;
+    // LDS, else two (blocks of <= kMfmaMaxEntries entries: 37 KiB); larger blocks
+    // are read in global memory
+    const bool gl = a.nent > kMfmaMaxEntries;
+    const bool three = !gl && 3 * stage_b + opnd_b <= (size_t)160 * 1024;
+    if (!gl && !three && 2 * stage_b + opnd_b > (size_t)160 * 1024) return (int)hipErrorInvalidValue;
+    const void* fn = gl      ? reinterpret_cast<const void*>(&k_couple_gemm<KL, KR, ODD, 2, true>)
+                     : three ? reinterpret_cast<const void*>(&k_couple_gemm<KL, KR, ODD, 3, false>)
+                             : reinterpret_cast<const void*>(&k_couple_gemm<KL, KR, ODD, 2, false>);
+    const size_t lds = (gl ? 0 : (three ? 3 : 2) * stage_b) + opnd_b;
     static thread_local std::vector<const void*> raised;
     if (std::find(raised.begin(), raised.end(), fn) == raised.end()) {
         const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -572,14 +593,16 @@ int launch_gemm_shape(const MfmaArgs& a, hipStream_t stream)
 }
 
 // One workgroup per 16-row block: the block's rows are read along the entries
-// (coalesced), transposed through LDS and written as one contiguous block.
+// (coalesced), transposed through LDS in chunks of kToBlkChunk entries and written
+// as one contiguous block.
 constexpr int kToBlkThreads = 256;
+constexpr int kToBlkChunk = 256;
 __global__ void __launch_bounds__(kToBlkThreads) k_to_blocked(const float2* __restrict__ alm,
                                                               const double* __restrict__ wprim,
                                                               const GatherSeg* __restrict__ segs, int nseg,
                                                               int nrows, int nent, int ent_blk, float* out)
 {
-    __shared__ float2 tile[kBlkRows][kMfmaMaxEntries + 1];
+    __shared__ float2 tile[kBlkRows][kToBlkChunk + 1];
     __shared__ int valid[kBlkRows];
     const int r0 = blockIdx.x * kBlkRows;
     if (threadIdx.x < kBlkRows) {
@@ -597,25 +620,27 @@ __global__ void __launch_bounds__(kToBlkThreads) k_to_blocked(const float2* __re
         valid[threadIdx.x] = ok;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kBlkRows * nent; i += kToBlkThreads) {
-        const int r = i / nent, e = i - r * nent;
-        tile[r][e] = valid[r] ? alm[(size_t)(r0 + r) * nent + e] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
     float* ob = out + (size_t)blockIdx.x * ent_blk * kBlkEntFloats;
-    for (int i = threadIdx.x; i < ent_blk * kBlkEntFloats; i += kToBlkThreads) {
-        const int e = i / kBlkEntFloats, f = i - e * kBlkEntFloats;
-        float v = 0.f;
-        if (f < 2 * kBlkRows) {
-            if (e < nent) {
+    for (int e0 = 0; e0 < ent_blk; e0 += kToBlkChunk) {
+        const int ne = min(kToBlkChunk, ent_blk - e0);
+        for (int i = threadIdx.x; i < kBlkRows * ne; i += kToBlkThreads) {
+            const int r = i / ne, e = i - r * ne;
+            tile[r][e] = (valid[r] && e0 + e < nent) ? alm[(size_t)(r0 + r) * nent + e0 + e] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < ne * kBlkEntFloats; i += kToBlkThreads) {
+            const int e = i / kBlkEntFloats, f = i - e * kBlkEntFloats;
+            float v = 0.f;
+            if (f < 2 * kBlkRows) {
                 const float2 c = tile[f >> 1][e];
                 v = (f & 1) ? c.y : c.x;
+            } else if (e0 + e < kBlkRows / 4) {
+                const int r = 4 * (e0 + e) + (f - 2 * kBlkRows);
+                v = valid[r] ? (float)wprim[r0 + r] : 0.f;
             }
-        } else if (e < kBlkRows / 4) {
-            const int r = 4 * e + (f - 2 * kBlkRows);
-            v = valid[r] ? (float)wprim[r0 + r] : 0.f;
+            ob[(size_t)e0 * kBlkEntFloats + i] = v;
         }
-        ob[i] = v;
+        __syncthreads();
     }
 }
 
@@ -637,7 +662,7 @@ int launch_to_blocked(const float2* alm, const double* wprim, const GatherSeg* s
                       int nent, float* out, hipStream_t stream)
 {
     if (nrows <= 0) return (int)hipSuccess;
-    if (nent < 1 || nent > kMfmaMaxEntries || nseg < 1) return (int)hipErrorInvalidValue;
+    if (nent < 1 || nent > kMfmaMaxAllEntries || nseg < 1) return (int)hipErrorInvalidValue;
     const int nblk = (nrows + kBlkRows - 1) / kBlkRows;
     k_to_blocked<<<dim3((unsigned)nblk), dim3(kToBlkThreads), 0, stream>>>(alm, wprim, segs, nseg, nrows, nent,
                                                                            blk_entries(nent), out);
@@ -647,7 +672,7 @@ int launch_to_blocked(const float2* alm, const double* wprim, const GatherSeg* s
 int launch_couple_gemm(const MfmaArgs& a, int KL, int KR, hipStream_t stream)
 {
     if (a.njobs == 0 || a.nsplit == 0) return (int)hipSuccess;
-    if (a.nent < 1 || a.nent > kMfmaMaxEntries || a.ent_blk != blk_entries(a.nent))
+    if (a.nent < 1 || a.nent > kMfmaMaxAllEntries || a.ent_blk != blk_entries(a.nent))
         return (int)hipErrorInvalidValue;
     const bool odd = a.any_odd != 0;
     switch (KL * 10 + KR) {
@@ -661,7 +686,7 @@ int launch_couple_gemm(const MfmaArgs& a, int KL, int KR, hipStream_t stream)
 int launch_couple_mfma(const MfmaArgs& a, int KF, int shape, hipStream_t stream)
 {
     if (a.njobs == 0 || a.nsplit == 0) return (int)hipSuccess;
-    if (a.nent < 1 || a.nent > kMfmaMaxEntries || a.ent_blk != blk_entries(a.nent))
+    if (a.nent < 1 || a.nent > kMfmaMaxAllEntries || a.ent_blk != blk_entries(a.nent))
         return (int)hipErrorInvalidValue;
     switch (KF * 2 + (a.any_odd ? 1 : 0)) {
     case 2: return launch_kf<1, false>(a, shape, stream);

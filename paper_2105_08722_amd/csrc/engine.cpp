@@ -248,9 +248,9 @@ template <typename Up>
 static int fill_mfma(DevTables& d, const NpcfPlan& pl, Up&& up)
 {
     const int nent = pl.nbins * (pl.lmax + 1) * (pl.lmax + 2) / 2;
-    if (nent > kMfmaMaxEntries)
+    if (nent > kMfmaMaxAllEntries)
         return fail(ENCORE_EUNSUPPORTED, "ENCORE_PREC_SPLITBF16 needs nbins * (lmax+1)(lmax+2)/2 <= " +
-                                             std::to_string(kMfmaMaxEntries) + " (got " +
+                                             std::to_string(kMfmaMaxAllEntries) + " (got " +
                                              std::to_string(nent) + ")");
     int rc;
     if (use_gemm_coupling(pl.N)) {
@@ -337,9 +337,9 @@ int acc_len_host(const NpcfPlan& pl, int64_t* out)
     const auto key = std::make_tuple(pl.N, pl.lmax, pl.allparity, pl.nbins);
     auto it = cache.find(key);
     if (it == cache.end()) {
-        if (pl.nbins * (pl.lmax + 1) * (pl.lmax + 2) / 2 > kMfmaMaxEntries)
+        if (pl.nbins * (pl.lmax + 1) * (pl.lmax + 2) / 2 > kMfmaMaxAllEntries)
             return fail(ENCORE_EUNSUPPORTED, "ENCORE_PREC_SPLITBF16 needs nbins * (lmax+1)(lmax+2)/2 <= " +
-                                                 std::to_string(kMfmaMaxEntries));
+                                                 std::to_string(kMfmaMaxAllEntries));
         int64_t dense = 0;
         if (use_gemm_coupling(pl.N)) {
             GemmPlan G;

@@ -8,7 +8,8 @@
 
 namespace encore {
 
-constexpr int kMfmaMaxEntries = 256;   // nbins * (lmax+1)(lmax+2)/2 staged per primary
+constexpr int kMfmaMaxEntries = 256;      // coefficients per primary of a K block staged in LDS
+constexpr int kMfmaMaxAllEntries = 1056;  // any call: 16 bins x 66 coefficients (lmax 10)
 constexpr int kNumMfmaShapes = 4;
 constexpr int kMfmaJobWidth = 4;       // row_base, col_base, tile_base, valid row tiles
 struct MfmaShape { int RT, NC; };      // row tiles x column tiles of one wave job

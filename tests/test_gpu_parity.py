@@ -193,9 +193,10 @@ def test_degenerate_inputs(ctx):
             encore.npcf(ctx, g, 3, 2, np.array([2.0, 20.0]))     # beyond r_max
         with pytest.raises(encore.EncoreError):
             encore.npcf(ctx, g, 3, 2, edges, primaries=np.array([5, 200]))  # index out of range
-        # split-bf16 stages at most 256 coefficients per primary in LDS
+        # the split-bf16 6PCF at lmax 4 with 16 bins has more output tiles than its
+        # 32-bit dense index can address
         with pytest.raises(encore.EncoreError) as e:
-            encore.npcf(ctx, g, 3, 10, np.linspace(1.0, 10.0, 11), precision="splitbf16")
+            encore.npcf(ctx, g, 6, 4, np.linspace(1.0, 10.0, 17), precision="splitbf16")
         assert e.value.code == encore.EUNSUPPORTED
     # one point: no pairs at all
     with encore.build_grid(ctx, np.array([[1.0, 2.0, 3.0]]), np.array([2.0]), r_max=10.0) as g:
@@ -341,6 +342,25 @@ def test_config2_zeta_sampled_primaries(ctx, cfg2, precision):
     e, r = bars.check(zg, zo, za, precision, "config 2")
     _say("  max e_L = %.3e, max e_L/(kappa+1) = %.3e, median kappa = %.1f"
          % (e, r, np.median(bars.kappa(zo, za))))
+
+
+@pytest.mark.parametrize("N,lmax,nbins,nprim", [(3, 10, 10, None), (4, 6, 12, None), (4, 10, 8, 40),
+                                                (5, 5, 13, 4)])
+def test_splitbf16_unstaged_blocks(ctx, N, lmax, nbins, nprim):
+    """More than 256 coefficients per primary (the paper's lmax = 10 4PCF, the 3PCF at
+    lmax = 10, the 5PCF at lmax = 5 with 13 bins): the split-bf16 coupling reads its
+    K blocks in global memory instead of staging them in LDS; vs the oracle."""
+    nent = nbins * (lmax + 1) * (lmax + 2) // 2
+    assert nent > 256
+    _say("unstaged split-bf16 N=%d lmax=%d nbins=%d (%d coefficients per primary)" % (N, lmax, nbins, nent))
+    pos, w = _uniform(700, 60.0, 40 + N)
+    edges = np.linspace(3.0, 26.0, nbins + 1)
+    prim = None if nprim is None else np.random.default_rng(N).choice(len(w), nprim, replace=False)
+    with encore.build_grid(ctx, pos, w, r_max=edges[-1], box=60.0) as g:
+        zg = encore.npcf(ctx, g, N, lmax, edges, precision="splitbf16", primaries=prim)
+    zo, za = oracle.zeta(pos, w, N, lmax, edges, box=60.0, primaries=prim, return_abs=True)
+    e, r = bars.check(zg, zo, za, "splitbf16", "unstaged")
+    _say("  max e_L = %.2e, max e_L/(kappa+1) = %.2e" % (e, r))
 
 
 @pytest.fixture(scope="module")
