@@ -390,7 +390,9 @@ int encore_debug_alm(encore_ctx* ctx, const encore_grid* grid, int lmax, int nbi
  * builds per bin tuple B the coupling matrix
  *     M_{L L''}(B) = sum_{L'} (R_{L'}^B / R_0^B) s(L, L') E(L'') G^{L L' L''}
  * with the generalized Gaunt integrals G of eq. generalized-gaunt-def (closed forms
- * of Appendix A: N = 3, 4, 5), and solves N_{L''}^B / R_0^B = sum_L zeta_L^B M_{L L''}
+ * of Appendix A for N = 3, 4, 5; for N = 6 the same construction with one 9j
+ * symbol per node of the coupling tree), built once per (npcf, lmax, parity) on
+ * the host and kept, and solves N_{L''}^B / R_0^B = sum_L zeta_L^B M_{L L''}
  * for zeta on the device (FP64, Gaussian elimination with partial pivoting and back substitution).
  * The paper's equations are written for the complex multiplets; odd multiplets are
  * imaginary and are passed and returned as their imaginary parts, which gives the
@@ -405,7 +407,7 @@ int encore_debug_alm(encore_ctx* ctx, const encore_grid* grid, int lmax, int nbi
  *  coupling      NULL or host FP64 [nB][nlam][nlam]: M[B][L][L''].
  *  n_singular    NULL or the number of B without a solution.
  * Errors: EINVAL, ESIZE (a buffer too small; the message gives the size),
- * EUNSUPPORTED (npcf = 6), ENOMEM, EDEVICE.
+ * EUNSUPPORTED (more than 4096 multiplets, e.g. npcf = 6 at lmax 4), ENOMEM, EDEVICE.
  */
 int encore_edge_correct(encore_ctx* ctx, int npcf, int lmax, int nbins, uint32_t flags,
                         const double* nmult, const double* rmult, size_t mult_len, int lmax_out,

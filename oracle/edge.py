@@ -8,7 +8,10 @@ Follows Section 3.2 (Edge Correction) of the paper:
   the N-1 directions into ordinary Gaunt integrals of three spherical harmonics,
   int Y Y Y = sqrt((2a+1)(2b+1)(2c+1)/(4 pi)) (a b c; 0 0 0)(a b c; m m' m'').
   `gaunt_closed` is the closed form of Appendix A for N = 3, 4, 5 (3j and 9j
-  symbols); the two are pinned against each other in tests/test_edge_oracle.py.
+  symbols), extended to N = 6 the way the appendix builds the lower orders: one 9j
+  symbol per node of the coupling tree (l1 l2 -> l12, l12 l3 -> l123, l123 l4 ->
+  l5) and sqrt((2x+1)(2x'+1)(2x''+1)) per intermediate x, over (4 pi)^{5/2}.  The
+  two are pinned against each other in tests/test_edge_oracle.py (N = 6 included).
 * coupling matrix M_{L L''}(B) = sum_{L'} f_{L'}(B) E(L'') G^{L L' L''} with
   f_{L'} = R_{L'} / R_0 (eq. edge-correction-matrix).  The paper writes it for the
   complex multiplets; odd multiplets are imaginary (Section 3.1) and are carried
@@ -125,7 +128,7 @@ def gaunt_definition(N, lam, lamp, lampp) -> float:
 
 
 def gaunt_closed(N, lam, lamp, lampp) -> float:
-    """Appendix A closed forms for N = 3, 4, 5."""
+    """Appendix A closed forms for N = 3, 4, 5, and the same construction for N = 6."""
     l, lp, lpp = principal(N, lam), principal(N, lamp), principal(N, lampp)
     prod3 = 1.0
     for i in range(N - 1):
@@ -145,7 +148,16 @@ def gaunt_closed(N, lam, lamp, lampp) -> float:
         return (prod3 / (4 * pi) ** 2 * sqrt((2 * l12 + 1) * (2 * l12p + 1) * (2 * l12pp + 1))
                 * wigner9j(l[0], l[1], l12, lp[0], lp[1], l12p, lpp[0], lpp[1], l12pp)
                 * wigner9j(l12, l[2], l[3], l12p, lp[2], lp[3], l12pp, lpp[2], lpp[3]))
-    raise ValueError("closed forms are given for N = 3, 4, 5")
+    if N == 6:
+        x12, x12p, x12pp = lam[2], lamp[2], lampp[2]
+        x123, x123p, x123pp = lam[4], lamp[4], lampp[4]
+        return (prod3 / (4 * pi) ** 2.5
+                * sqrt((2 * x12 + 1) * (2 * x12p + 1) * (2 * x12pp + 1))
+                * sqrt((2 * x123 + 1) * (2 * x123p + 1) * (2 * x123pp + 1))
+                * wigner9j(l[0], l[1], x12, lp[0], lp[1], x12p, lpp[0], lpp[1], x12pp)
+                * wigner9j(x12, l[2], x123, x12p, lp[2], x123p, x12pp, lpp[2], x123pp)
+                * wigner9j(x123, l[3], l[4], x123p, lp[3], lp[4], x123pp, lpp[3], lpp[4]))
+    raise ValueError("closed forms are given for N = 3..6")
 
 
 @lru_cache(maxsize=None)

@@ -179,6 +179,8 @@ int launch_couple_gemm(const MfmaArgs& a, int KL, int KR, hipStream_t stream);
 // Edge correction (one workgroup per bin tuple B): builds the coupling matrix from
 // the Gaunt terms and the random multiplets, solves for zeta (NaN for B with R_0 = 0
 // or a singular matrix, counted in *nbad).
+// Largest multiplet count of the edge-correction solve (its factor column sits in LDS).
+constexpr int kEdgeMaxMultiplets = 4096;
 struct EdgeArgs {
     int nlam, nB, nout;
     const double* nmult;        // [nlam][nB] data-minus-random multiplets

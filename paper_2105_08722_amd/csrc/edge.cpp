@@ -2,12 +2,16 @@
 // edge-corrected-NPCF): host side.
 //
 // The generalized Gaunt integrals G^{L L' L''} (eq. generalized-gaunt-def) come
-// from the closed forms of Appendix A (N = 3, 4, 5): products over the N-1
-// directions of sqrt((2l+1)(2l'+1)(2l''+1)) (l l' l''; 0 0 0), times one 9j symbol
-// for N = 4 and two (with the sqrt((2l12+1)(2l12'+1)(2l12''+1)) factor of the
-// intermediates) for N = 5, over (4 pi)^{(N-1)/2}; for N = 3 the single 3j symbol is
-// squared over 4 pi.  6j symbols by Racah's single sum (DLMF 34.4.3) and 9j symbols
-// by the sum of 6j products (DLMF 34.6.2), in long double.
+// from closed forms in the manner of Appendix A: products over the N-1 directions
+// of sqrt((2l+1)(2l'+1)(2l''+1)) (l l' l''; 0 0 0) over (4 pi)^{(N-1)/2}, times one
+// 9j symbol per node of the multiplet's coupling tree (l1 l2 -> l12, l12 l3 -> l123,
+// ..., the last node coupling to the last principal ell) and, for every
+// intermediate x, sqrt((2x+1)(2x'+1)(2x''+1)): one 9j for N = 4, two for N = 5,
+// three for N = 6 (the paper writes N = 3, 4, 5 and notes that higher orders follow
+// the same construction; the N = 6 form is checked against the integral's
+// definition).  For N = 3 the single 3j symbol is squared over 4 pi.  6j symbols by
+// Racah's single sum (DLMF 34.4.3) and 9j symbols by the sum of 6j products (DLMF
+// 34.6.2), in long double.
 //
 // The device builds M_{L L''}(B) = sum_{L'} f_{L'}(B) s(L, L') E(L'') G^{L L' L''} from
 // a list of the nonzero (L, L'') x L' terms grouped by (L, L'') (so each entry is a
@@ -22,6 +26,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -87,7 +92,7 @@ long double ninej(int j1, int j2, int j3, int j4, int j5, int j6, int j7, int j8
 struct GauntEval {
     int N;
     int np;                               // principal ells per multiplet
-    std::vector<int> pl, l12;             // [n][np], [n] (N = 5)
+    std::vector<int> pl, l12, l123;       // [n][np], [n] (N >= 5), [n] (N = 6)
     std::vector<long double> w0;          // (a b c; 0 0 0), index (a * D + b) * D + c
     int D;
     std::unordered_map<uint64_t, long double> memo;
@@ -96,10 +101,12 @@ struct GauntEval {
     {
         pl.resize((size_t)n * np);
         l12.assign(n, 0);
+        l123.assign(n, 0);
         int lmx = 0;
         for (int i = 0; i < n; ++i) {
             principal_of(N, &lam[(size_t)i * W], &pl[(size_t)i * np]);
-            if (N == 5) l12[i] = lam[(size_t)i * W + 2];
+            if (N >= 5) l12[i] = lam[(size_t)i * W + 2];
+            if (N == 6) l123[i] = lam[(size_t)i * W + 4];
             for (int k = 0; k < np; ++k) lmx = std::max(lmx, pl[(size_t)i * np + k]);
         }
         D = lmx + 1;
@@ -142,13 +149,21 @@ struct GauntEval {
         if (N == 4)
             return (double)(p / std::pow(fourpi, 1.5L) *
                             nine(la[0], lb[0], lc[0], la[1], lb[1], lc[1], la[2], lb[2], lc[2]));
-        // N == 5: intermediates l12
+        // N = 5, 6: intermediates l12 (and l123)
         const int a12 = l12[a], b12 = l12[b], c12 = l12[c];
         if (!tri(a12, b12, c12)) return 0.0;
-        return (double)(p / (fourpi * fourpi) *
-                        std::sqrt((long double)(2 * a12 + 1) * (2 * b12 + 1) * (2 * c12 + 1)) *
+        const long double s12 = std::sqrt((long double)(2 * a12 + 1) * (2 * b12 + 1) * (2 * c12 + 1));
+        if (N == 5)
+            return (double)(p / (fourpi * fourpi) * s12 *
+                            nine(la[0], la[1], a12, lb[0], lb[1], b12, lc[0], lc[1], c12) *
+                            nine(a12, la[2], la[3], b12, lb[2], lb[3], c12, lc[2], lc[3]));
+        const int a123 = l123[a], b123 = l123[b], c123 = l123[c];
+        if (!tri(a123, b123, c123)) return 0.0;
+        const long double s123 = std::sqrt((long double)(2 * a123 + 1) * (2 * b123 + 1) * (2 * c123 + 1));
+        return (double)(p / (fourpi * fourpi * std::sqrt(fourpi)) * s12 * s123 *
                         nine(la[0], la[1], a12, lb[0], lb[1], b12, lc[0], lc[1], c12) *
-                        nine(a12, la[2], la[3], b12, lb[2], lb[3], c12, lc[2], lc[3]));
+                        nine(a12, la[2], a123, b12, lb[2], b123, c12, lc[2], c123) *
+                        nine(a123, la[3], la[4], b123, lb[3], lb[4], c123, lc[3], lc[4]));
     }
 };
 
@@ -176,6 +191,16 @@ const GauntTable& gaunt_table(int N, int lmax, bool allparity)
         for (int k = 0; k < N - 1; ++k) s += ls[k];
         E[i] = (s & 1) ? -1 : 1;
     }
+    // multiplets by their principal ells: G vanishes unless every direction's
+    // (l, l', l'') satisfies the triangle rule with an even sum, so for (L, L'') only
+    // the L' whose principal ells lie in those ranges are evaluated
+    const int np = N - 1;
+    std::map<std::vector<int>, std::vector<int32_t>> by_principal;
+    std::vector<int> pls((size_t)n * np);
+    for (int i = 0; i < n; ++i) {
+        principal_of(N, &lam[(size_t)i * W], &pls[(size_t)i * np]);
+        by_principal[std::vector<int>(&pls[(size_t)i * np], &pls[(size_t)i * np] + np)].push_back(i);
+    }
     // entry (L = a, L'' = c) -> terms over L' = b, in increasing b; rows of a are
     // evaluated on several threads and joined in order
     const int nth = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
@@ -185,17 +210,38 @@ const GauntTable& gaunt_table(int N, int lmax, bool allparity)
     std::atomic<int> next{0};
     auto worker = [&]() {
         GauntEval ge(N, lam, W, n);
+        std::vector<int> cur(np);
+        std::vector<std::pair<int32_t, double>> terms;
         for (int a = next++; a < n; a = next++) {
             cnt[a].assign(n, 0);
-            for (int c = 0; c < n; ++c)
-                for (int b = 0; b < n; ++b) {
-                    const double g = ge(a, b, c);
-                    if (g != 0.0) {
-                        lp[a].push_back(b);
-                        val[a].push_back((E[a] < 0 && E[b] < 0 ? -1.0 : 1.0) * E[c] * g);
-                        ++cnt[a][c];
+            const int* la = &pls[(size_t)a * np];
+            for (int c = 0; c < n; ++c) {
+                const int* lc = &pls[(size_t)c * np];
+                terms.clear();
+                // every principal tuple of L' allowed by (L, L'')
+                std::function<void(int)> walk = [&](int k) {
+                    if (k == np) {
+                        auto it = by_principal.find(cur);
+                        if (it == by_principal.end()) return;
+                        for (const int32_t b : it->second) {
+                            const double g = ge(a, b, c);
+                            if (g != 0.0) terms.emplace_back(b, (E[a] < 0 && E[b] < 0 ? -1.0 : 1.0) * E[c] * g);
+                        }
+                        return;
                     }
+                    for (int l = std::abs(la[k] - lc[k]); l <= la[k] + lc[k] && l <= lmax; l += 2) {
+                        cur[k] = l;
+                        walk(k + 1);
+                    }
+                };
+                walk(0);
+                std::sort(terms.begin(), terms.end());
+                for (const auto& t : terms) {
+                    lp[a].push_back(t.first);
+                    val[a].push_back(t.second);
                 }
+                cnt[a][c] = (int64_t)terms.size();
+            }
         }
     };
     std::vector<std::thread> th;
@@ -246,13 +292,16 @@ extern "C" int encore_edge_correct(encore_ctx* ctx, int npcf, int lmax, int nbin
 {
     if (!ctx) return fail(ENCORE_EINVAL, "ctx is NULL");
     if (npcf < 3 || npcf > 6) return fail(ENCORE_EINVAL, "npcf must be 3..6");
-    if (npcf == 6)
-        return fail(ENCORE_EUNSUPPORTED, "edge correction: generalized Gaunt integrals are built for N = 3, 4, 5");
     if (lmax < 0 || lmax > kMaxLmax) return fail(ENCORE_EINVAL, "lmax must be 0..10");
     if (lmax_out < 0 || lmax_out > lmax) return fail(ENCORE_EINVAL, "lmax_out must be 0..lmax");
     if (nbins < 1 || nbins > kMaxBins) return fail(ENCORE_EINVAL, "nbins must be 1..16");
     if (!nmult || !rmult || !zeta) return fail(ENCORE_EINVAL, "NULL multiplets or zeta");
     const bool allp = flags & ENCORE_ALLPARITY;
+    const int64_t nlam = (int64_t)enumerate_multiplets(npcf, lmax, allp).size() / multiplet_width(npcf);
+    if (nlam > kEdgeMaxMultiplets)
+        return fail(ENCORE_EUNSUPPORTED, "edge correction solves systems of at most " +
+                                             std::to_string(kEdgeMaxMultiplets) + " multiplets (got " +
+                                             std::to_string(nlam) + ")");
     const GauntTable& gt = gaunt_table(npcf, lmax, allp);
     const int n = gt.nlam;
     const int64_t nB = binomial(nbins, npcf - 1);

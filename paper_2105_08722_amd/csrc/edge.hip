@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(kEdgeThreads) k_edge_solve(EdgeArgs a)
 int launch_edge(const EdgeArgs& a, hipStream_t stream)
 {
     if (a.nB == 0 || a.nlam == 0) return (int)hipSuccess;
-    if (a.nlam > 4096) return (int)hipErrorInvalidValue;
+    if (a.nlam > kEdgeMaxMultiplets) return (int)hipErrorInvalidValue;
     const size_t lds_m = sizeof(double) * (size_t)a.nlam;
     k_edge_matrix<<<dim3((unsigned)a.nB), dim3(kEdgeThreads), lds_m, stream>>>(a);
     hipError_t e = hipGetLastError();

@@ -40,7 +40,41 @@ def test_closed_forms_match_definition(N, lmax, parity):
     assert worst < 1e-13
 
 
-@pytest.mark.parametrize("N,lmax,parity", [(3, 3, "even"), (4, 2, "all"), (5, 1, "even")])
+def test_closed_form_n6_matches_definition():
+    """The N = 6 closed form (three 9j symbols, two intermediates) against the
+    definition: every triple at lmax = 1 (both parities), and 1500 triples at lmax
+    = 2 that pass the per-direction triangle rules (the others vanish on both
+    sides)."""
+    lams = multiplets(6, 1, "all")
+    worst, nonzero = 0.0, 0
+    for a in lams:
+        for b in lams:
+            for c in lams:
+                g = edge.gaunt_closed(6, a, b, c)
+                la, lb, lc = principal(6, a), principal(6, b), principal(6, c)
+                if not all(abs(x - y) <= z <= x + y and (x + y + z) % 2 == 0 for x, y, z in zip(la, lb, lc)):
+                    assert g == 0.0
+                    continue
+                d = edge.gaunt_definition(6, a, b, c)
+                nonzero += abs(d) > 1e-12
+                worst = max(worst, abs(g - d))
+    assert nonzero > 1000 and worst < 1e-13
+    rng = np.random.default_rng(6)
+    lams = multiplets(6, 2, "all")
+    n, worst, nonzero = 0, 0.0, 0
+    while n < 1500:
+        a, b, c = (lams[i] for i in rng.integers(0, len(lams), 3))
+        la, lb, lc = principal(6, a), principal(6, b), principal(6, c)
+        if not all(abs(x - y) <= z <= x + y and (x + y + z) % 2 == 0 for x, y, z in zip(la, lb, lc)):
+            continue
+        n += 1
+        d = edge.gaunt_definition(6, a, b, c)
+        nonzero += abs(d) > 1e-12
+        worst = max(worst, abs(edge.gaunt_closed(6, a, b, c) - d))
+    assert nonzero > 500 and worst < 1e-13
+
+
+@pytest.mark.parametrize("N,lmax,parity", [(3, 3, "even"), (4, 2, "all"), (5, 1, "even"), (6, 1, "all")])
 def test_periodic_window_gives_scaled_identity(N, lmax, parity):
     """Only R_0 nonzero (uniform periodic geometry): M = (4 pi)^{-(N-1)/2} I."""
     n = len(multiplets(N, lmax, parity))
@@ -65,7 +99,7 @@ def test_gaunt_selection_rules():
                     assert G[i, j, k] == 0.0
 
 
-@pytest.mark.parametrize("N,lmax", [(3, 3), (4, 2)])
+@pytest.mark.parametrize("N,lmax", [(3, 3), (4, 2), (6, 1)])
 def test_solution_recovers_known_zeta(N, lmax):
     """Closed loop: N'' = R_0 sum_L zeta_L M_{L L''} for a known zeta and a
     non-trivial window; the edge correction returns that zeta."""

@@ -43,7 +43,8 @@ def _window_multiplets(N, lmax, nB, parity, seed):
 
 
 @pytest.mark.parametrize("N,lmax,nbins,allp", [(3, 4, 4, False), (3, 3, 4, True), (4, 3, 5, False),
-                                               (4, 2, 4, True), (5, 2, 5, False), (5, 1, 5, True)])
+                                               (4, 2, 4, True), (5, 2, 5, False), (5, 1, 5, True),
+                                               (6, 1, 6, False), (6, 1, 6, True)])
 def test_edge_matches_oracle(ctx, N, lmax, nbins, allp):
     _say("edge correction N=%d lmax=%d nbins=%d allparity=%s" % (N, lmax, nbins, allp))
     parity = "all" if allp else "even"
@@ -82,8 +83,8 @@ def test_edge_periodic_window_is_scaled_identity(ctx):
 
 
 def test_edge_singular_bins_and_errors(ctx):
-    """B with R_0 = 0 get NaN and are counted; the others are solved; N = 6 and
-    short buffers are refused."""
+    """B with R_0 = 0 get NaN and are counted; the others are solved; systems of
+    more than 4096 multiplets and short buffers are refused."""
     _say("edge correction, singular bins and errors")
     N, lmax, nbins = 3, 3, 4
     nB = encore.num_bin_tuples(N, nbins)
@@ -96,9 +97,9 @@ def test_edge_singular_bins_and_errors(ctx):
     zo = oedge.edge_correct(N, lmax, Nm[:, ok], R[:, ok])
     assert np.max(np.abs(z[:, ok] - zo)) <= 1e-11 * np.max(np.abs(zo))
     with pytest.raises(encore.EncoreError) as e:
-        n6 = encore.num_multiplets(6, 1)
+        n6 = encore.num_multiplets(6, 4)          # 10113 multiplets
         nB6 = encore.num_bin_tuples(6, 6)
-        encore.edge_correct(ctx, 6, 1, 6, np.ones((n6, nB6)), np.ones((n6, nB6)))
+        encore.edge_correct(ctx, 6, 4, 6, np.ones((n6, nB6)), np.ones((n6, nB6)))
     assert e.value.code == encore.EUNSUPPORTED
 
 
