@@ -16,7 +16,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libencore.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["gather.hip", "couple.hip", "couple_mfma.hip", "grid.hip", "edge.hip", "noalloc.hip", "mesh.hip", "engine.cpp", "api.cpp", "server.cpp", "edge.cpp",
+SOURCES = ["gather.hip", "couple.hip", "couple_mfma.hip", "grid.hip", "edge.hip", "noalloc.hip", "mesh.hip", "engine.cpp", "api.cpp", "server.cpp", "edge.cpp", "gaunt.cpp",
            "tables.cpp", "mfma_plan.cpp", "plan.cpp"]
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -26,7 +26,7 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC",
 def _compile(src):
     obj = os.path.join(BUILD, src + ".o")
     cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
-    if src == "tables.cpp":
+    if src in ("tables.cpp", "gaunt.cpp"):
         cmd = [HIPCC, "-x", "c++", "-O2", "-std=c++20", "-fPIC", "-c",
                os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)

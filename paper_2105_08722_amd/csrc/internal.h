@@ -49,7 +49,7 @@ struct TermTable {
 };
 const TermTable& term_table(int N, int lmax, bool allparity);
 
-// Generalized Gaunt integrals of the multiplet list (N, lmax, allparity), N = 3..5,
+// Generalized Gaunt integrals of the multiplet list (N, lmax, allparity), N = 3..6,
 // as the terms of the edge-correction matrix: entry (L, L'') = a * nlam + c holds
 // terms [row_start[e], row_start[e+1]) of (L' = term_lp, E(L'') G^{L L' L''} = term_val).
 struct GauntTable {
