@@ -63,6 +63,26 @@ __device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c)
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
+// Block -> (split, job group) of a coupling launch of nsplit x nper blocks.  Splits
+// in whole groups of 8 run one per XCD (block b is placed on XCD b % 8), so that the
+// blocks of a split share its coefficients through that XCD's L2; the splits past
+// the last whole group spread their blocks over all XCDs, so that a slice with
+// fewer than 8 splits still fills the chip.
+__device__ __forceinline__ void split_of_block(int nsplit, int nper, int& split, int& job)
+{
+    const int full = nsplit & ~7;
+    const long long b = blockIdx.x, nfull = (long long)full * nper;
+    if (b < nfull) {
+        const int li = (int)(b >> 3);
+        split = (int)(b & 7) + 8 * (li / nper);
+        job = li % nper;
+    } else {
+        const long long r = b - nfull;
+        split = full + (int)(r / nper);
+        job = (int)(r % nper);
+    }
+}
+
 // ODD: some rows take the Im part (all-parity multiplets); otherwise every row
 // takes the Re part and no per-row select is needed.  GL: the K blocks are read
 // where they lie in global memory (through the L2) instead of being staged in LDS,
@@ -76,13 +96,9 @@ __global__ void __launch_bounds__(kMfThreads) k_couple_mfma(MfmaArgs a)
     const int units = (blk_b + 1023) >> 10;       // 1 KiB copy units (64 lanes x 16 bytes)
     const int stage_b = units << 10;
 
-    // blocks of one split run on one XCD (block b is placed on XCD b % 8), so the
-    // split's coefficients are shared through that XCD's L2
     const int nbj = (a.njobs + kMfWaves - 1) / kMfWaves;
-    const int li = blockIdx.x >> 3;
-    const int split = (blockIdx.x & 7) + 8 * (li / nbj);
-    const int bj = li % nbj;
-    if (split >= a.nsplit) return;          // uniform over the block, before any barrier
+    int split, bj;
+    split_of_block(a.nsplit, nbj, split, bj);
 
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // uniform per wave
     const int lane = threadIdx.x & (kWave - 1);
@@ -299,8 +315,7 @@ template <int KF, int RT, int NC, bool ODD>
 int launch_shape(const MfmaArgs& a, hipStream_t stream)
 {
     const int nbj = (a.njobs + kMfWaves - 1) / kMfWaves;
-    const int64_t groups = (a.nsplit + 7) / 8;
-    const int64_t blocks = groups * 8 * nbj;
+    const int64_t blocks = (int64_t)a.nsplit * nbj;
     if (blocks > INT32_MAX) return (int)hipErrorInvalidValue;
     if (a.nent > kMfmaMaxEntries) {
         k_couple_mfma<KF, RT, NC, ODD, true><<<dim3((unsigned)blocks), dim3(kMfThreads), 0, stream>>>(a);
@@ -375,12 +390,8 @@ __global__ void __launch_bounds__(kGmThreads) k_couple_gemm(MfmaArgs a)
     const int stage_b = units << 10;
     unsigned char* opnd = smem + (GL ? 0 : (size_t)ST * stage_b);   // two operand buffers of kGmOpnd bytes
 
-    // blocks of one split run on one XCD (block b is placed on XCD b % 8)
-    const int nmacro = a.njobs;
-    const int li = blockIdx.x >> 3;
-    const int split = (blockIdx.x & 7) + 8 * (li / nmacro);
-    const int mac = li % nmacro;
-    if (split >= a.nsplit) return;          // uniform over the block, before any barrier
+    int split, mac;
+    split_of_block(a.nsplit, a.njobs, split, mac);
 
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x & (kWave - 1);
@@ -566,8 +577,7 @@ __global__ void __launch_bounds__(kGmThreads) k_couple_gemm(MfmaArgs a)
 template <int KL, int KR, bool ODD>
 int launch_gemm_shape(const MfmaArgs& a, hipStream_t stream)
 {
-    const int64_t groups = (a.nsplit + 7) / 8;
-    const int64_t blocks = groups * 8 * a.njobs;
+    const int64_t blocks = (int64_t)a.nsplit * a.njobs;
     if (blocks > INT32_MAX) return (int)hipErrorInvalidValue;
     const size_t stage_b = (blk_bytes(a.nent) + 1023) / 1024 * 1024;
     const size_t opnd_b = 2 * (size_t)kGmOpnd;

@@ -390,9 +390,10 @@ int64_t job_split_rows(const NpcfPlan& pl, const DevTables* tb, int64_t nprim, i
         if (tb->mf_gemm) nbj = tb->mf_nmacro;
         else
             for (int sh = 0; sh < kNumMfmaShapes; ++sh) nbj += (tb->mf_njobs[sh] + 15) / 16;
-        // The launch puts split s on XCD s % 8 (its blocks share the split's
-        // coefficients through that XCD's L2), so the count is a multiple of 8: with
-        // fewer splits whole XCDs would idle however many macro tiles there are.
+        // The launch runs splits in whole groups of 8 one per XCD (the blocks of a
+        // split share its coefficients through that XCD's L2), so the count is a
+        // multiple of 8; leftover splits (the last slice of a job) spread their
+        // blocks over all XCDs instead.
         const int64_t want = std::max<int64_t>(1, 2048 / std::max<int64_t>(nbj, 1));
         const int64_t ns = std::min<int64_t>(1024, (want + 7) / 8 * 8);
         int64_t rows = (std::max<int64_t>(nprim, 1) + ns - 1) / ns;
