@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "device.h"
@@ -341,15 +342,15 @@ int launch_shape(const MfmaArgs& a, hipStream_t stream)
 // forms operand tile k of the macro tile (its row tiles first: products of the
 // first KL factors, Re or Im part; then its column tiles: w times the products of
 // the other KR factors), split into bf16 hi + lo and stored in LDS in the MFMA lane
-// order; wave w computes output tiles w, w + 16, .. (three MFMAs each) from the
-// shared operands.  The two are pipelined over two operand buffers: in one step a
+// order; wave w computes one 2 x 2 block of output tiles (three MFMAs each) from
+// the shared operands, reading each of its two row and two column operand tiles
+// once per K block.  The two are pipelined over two operand buffers: in one step a
 // wave issues the MFMAs of K block st and forms its operand of K block st + 1, so
 // one barrier per K block separates them.
 constexpr int kGmWaves = kGemmMaxOps;
 constexpr int kGmThreads = kGmWaves * kWave;
 constexpr int kOpBytes = 2 * kWave * 16;           // one operand tile: hi and lo, 16 bytes per lane each
 constexpr int kGmOpnd = kGemmMaxOps * kOpBytes;    // one operand buffer
-constexpr int kGmOutPerWave = kGemmMaxOut / kGmWaves;
 
 // The product of NF factors for this lane's 4 primaries (4g .. 4g+3) from a staged K
 // block, conjugating the factors flagged in fl.
@@ -422,25 +423,30 @@ __global__ void __launch_bounds__(kGmThreads) k_couple_gemm(MfmaArgs a)
             fl = (unsigned)r[KL];
         }
     }
-    // output role: tiles wid + 16 j, j < nt (wave-uniform)
-    const int nout = MR * MC;
-    const int nt = nout > wid ? (nout - wid + kGmWaves - 1) / kGmWaves : 0;
-    int aslot[kGmOutPerWave], bslot[kGmOutPerWave];
-#pragma unroll
-    for (int j = 0; j < kGmOutPerWave; ++j) {
-        const int t = wid + kGmWaves * j;
-        aslot[j] = (t / MC) * kOpBytes + lane * 16;
-        bslot[j] = (MR + t % MC) * kOpBytes + lane * 16;
-    }
+    // output role: the 2 x 2 block (bi, bj) of output tiles, rows tr0, tr0 + 1 and
+    // columns tc0, tc0 + 1 of the macro tile, those inside it (wave-uniform)
+    const int nbc = (MC + 1) / 2;
+    const int bi = wid / nbc, bj = wid - bi * nbc;
+    const int tr0 = 2 * bi, tc0 = 2 * bj;
+    const int nr = bi < (MR + 1) / 2 ? min(2, MR - tr0) : 0;   // 0: no block for this wave
+    const int nc = min(2, MC - tc0);
+    // operand slots of the block's rows and columns; a row or column outside the
+    // macro tile (and every operand of a wave without a block) reads a real operand
+    // tile, and the tiles it feeds are never written
+    const int r0 = nr > 0 ? tr0 : 0, c0 = nr > 0 ? tc0 : 0;
+    const int aslot[2] = {r0 * kOpBytes + lane * 16, (nr == 2 ? r0 + 1 : r0) * kOpBytes + lane * 16};
+    const int bslot[2] = {(MR + c0) * kOpBytes + lane * 16, (MR + (nc == 2 ? c0 + 1 : c0)) * kOpBytes + lane * 16};
 
-    f32x4 acc[kGmOutPerWave];
-    double acc64[kGmOutPerWave][4];
+    f32x4 acc[2][2];
+    double acc64[2][2][4];
 #pragma unroll
-    for (int j = 0; j < kGmOutPerWave; ++j) {
-        acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc64[j][r] = 0.0;
-    }
+        for (int j = 0; j < 2; ++j) {
+            acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
+        }
 
     const int p_lo = a.split_lo[split], p_hi = a.split_hi[split];
     const int kb0 = p_lo / kBlkRows, kb1 = (p_hi + kBlkRows - 1) / kBlkRows;
@@ -479,8 +485,12 @@ __global__ void __launch_bounds__(kGmThreads) k_couple_gemm(MfmaArgs a)
     };
     static_assert(ST == 2 || ST == 3, "copy wait counts assume 2 or 3 stages");
 
-    // forms this wave's operand of K block st (staged) into operand buffer st & 1
-    auto form = [&](int st) {
+    // forms this wave's operand of K block st (staged) into operand buffer st & 1;
+    // EDGE: the split's first or last K block, whose primaries outside the split get
+    // weight 0 (a block inside the split needs no such check, and its code is then
+    // one basic block with the MFMAs of the step)
+    auto form = [&](int st, auto edge) {
+        constexpr bool EDGE = decltype(edge)::value;
         const unsigned char* stg = GL ? gsrc + (size_t)(kb0 + st) * blk_b : smem + (size_t)(st % ST) * stage_b;
         float pr[4], pi[4];
         u32x4 hi, lo;
@@ -490,7 +500,7 @@ __global__ void __launch_bounds__(kGmThreads) k_couple_gemm(MfmaArgs a)
             // for primaries of a boundary block outside the split
             float4 w4 = *reinterpret_cast<const float4*>(stg + g * kEntBytes + 128);
             const int pb = (kb0 + st) * kBlkRows;
-            if (pb < p_lo || pb + kBlkRows > p_hi) {
+            if (EDGE && (pb < p_lo || pb + kBlkRows > p_hi)) {
                 const int p = pb + 4 * g;
                 w4.x = (p + 0 >= p_lo && p + 0 < p_hi) ? w4.x : 0.f;
                 w4.y = (p + 1 >= p_lo && p + 1 < p_hi) ? w4.y : 0.f;
@@ -529,7 +539,7 @@ __global__ void __launch_bounds__(kGmThreads) k_couple_gemm(MfmaArgs a)
             wait_copies(ST - 1);
             asm volatile("s_barrier" ::: "memory");
         }
-        if (forms) form(0);
+        if (forms) form(0, std::true_type{});
     }
     for (int st = 0; st < nstep; ++st) {
         // After the barrier: every wave's operands of K block st are in buffer st & 1,
@@ -540,25 +550,47 @@ __global__ void __launch_bounds__(kGmThreads) k_couple_gemm(MfmaArgs a)
         asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
         if constexpr (!GL) copy_block(st + ST);
         const unsigned char* ob = opnd + (size_t)(st & 1) * kGmOpnd;
+        // the block's row and column operands, each read once, and the MFMAs of its
+        // tiles inside the macro tile
+        auto products = [&]() {
+            if (nr == 0) return;                          // wave-uniform
+            u32x4 ah[2], al[2], bh[2], bl[2];
 #pragma unroll
-        for (int j = 0; j < kGmOutPerWave; ++j) {
-            if (j >= nt) break;                           // wave-uniform
-            const u32x4 ah = *reinterpret_cast<const u32x4*>(ob + aslot[j]);
-            const u32x4 al = *reinterpret_cast<const u32x4*>(ob + aslot[j] + kWave * 16);
-            const u32x4 bh = *reinterpret_cast<const u32x4*>(ob + bslot[j]);
-            const u32x4 bl = *reinterpret_cast<const u32x4*>(ob + bslot[j] + kWave * 16);
-            acc[j] = mfma(ah, bh, acc[j]);
-            acc[j] = mfma(ah, bl, acc[j]);
-            acc[j] = mfma(al, bh, acc[j]);
-        }
-        if (forms && st + 1 < nstep) form(st + 1);
+            for (int i = 0; i < 2; ++i) {
+                ah[i] = *reinterpret_cast<const u32x4*>(ob + aslot[i]);
+                al[i] = *reinterpret_cast<const u32x4*>(ob + aslot[i] + kWave * 16);
+                bh[i] = *reinterpret_cast<const u32x4*>(ob + bslot[i]);
+                bl[i] = *reinterpret_cast<const u32x4*>(ob + bslot[i] + kWave * 16);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    if (i >= nr || j >= nc) continue;
+                    acc[i][j] = mfma(ah[i], bh[j], acc[i][j]);
+                    acc[i][j] = mfma(ah[i], bl[j], acc[i][j]);
+                    acc[i][j] = mfma(al[i], bh[j], acc[i][j]);
+                }
+        };
+        auto next = [&]() {
+            if (!forms || st + 1 >= nstep) return;
+            if (st + 2 < nstep) form(st + 1, std::false_type{});   // inside the split
+            else form(st + 1, std::true_type{});                  // the split's last K block
+        };
+        // (half the waves taking the forming first, so that one SIMD's matrix core
+        // and VALU would overlap after the barrier, measured slower: 100 ms against
+        // 86 ms for the 6PCF at lmax 3 over 200k primaries)
+        products();
+        next();
         if ((st + 1) % kFlushSteps == 0 || st + 1 == nstep) {
 #pragma unroll
-            for (int j = 0; j < kGmOutPerWave; ++j) {
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc64[j][r] += (double)acc[j][r];
-                acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-            }
+                for (int j = 0; j < 2; ++j) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
+                    acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+                }
         }
     }
     // no copy may still be writing LDS when the block ends
@@ -566,12 +598,14 @@ __global__ void __launch_bounds__(kGmThreads) k_couple_gemm(MfmaArgs a)
     // output tile layout of the 16x16 MFMA: lane holds column c16, rows 4g .. 4g+3
     double* D = a.D + (size_t)split * a.dense + (size_t)tile_base * 256;
 #pragma unroll
-    for (int j = 0; j < kGmOutPerWave; ++j) {
-        if (j >= nt) break;
-        double* t = D + (size_t)(wid + kGmWaves * j) * 256;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) t[(4 * g + r) * 16 + c16] = acc64[j][r];
-    }
+        for (int j = 0; j < 2; ++j) {
+            if (i >= nr || j >= nc) continue;              // never written: outside the macro tile
+            double* t = D + (size_t)((tr0 + i) * MC + tc0 + j) * 256;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) t[(4 * g + r) * 16 + c16] = acc64[i][j][r];
+        }
 }
 
 template <int KL, int KR, bool ODD>

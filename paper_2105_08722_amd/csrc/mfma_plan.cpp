@@ -215,14 +215,23 @@ int build_mfma_plan(int N, int lmax, bool allparity, int nbins, MfmaPlan& P)
 int gemm_split(int N) { return N == 3 ? 1 : (N == 6 ? 3 : 2); }
 
 // Cost of one K block of an MR x MC macro tile in CU cycles, a model of the
-// kernel: each operand tile takes ~320 SIMD cycles of VALU to form (products,
-// weights, bf16 hi + lo split), each output tile three 16-cycle MFMAs; both are
-// spread over the 4 SIMDs and mostly overlap; ~400 more for the K block's copy
-// and the barrier.
+// kernel: each operand tile takes ~376 SIMD cycles of VALU to form (products,
+// weights, bf16 hi + lo split), spread over the 4 SIMDs; the CU's LDS moves 128
+// bytes per cycle: ~8 KiB per formed operand (factor reads, hi + lo writes), 2 KiB
+// per operand tile each wave reads for its 2 x 2 output tiles, and the K block's
+// copy; each output tile takes three 16-cycle MFMAs.  The LDS and the VALU bound
+// it, partly overlapped; ~300 more for the barrier.
 static double macro_cost(int MR, int MC)
 {
-    const double F = 320.0 * ((MR + MC + 3) / 4), M = 48.0 * ((MR * MC + 3) / 4);
-    return std::max(F, M) + 0.25 * std::min(F, M) + 400.0;
+    const int ops = MR + MC;
+    double reads = 0.0;                          // operand tiles read, summed over the waves
+    for (int bi = 0; bi < (MR + 1) / 2; ++bi)
+        for (int bj = 0; bj < (MC + 1) / 2; ++bj)
+            reads += std::min(2, MR - 2 * bi) + std::min(2, MC - 2 * bj);
+    const double valu = 376.0 * ((ops + 3) / 4);
+    const double lds = (8.0 * ops + 2.0 * reads + 16.0) * 1024.0 / 128.0;
+    const double mfma = 48.0 * ((MR * MC + 3) / 4);
+    return std::max({valu, lds, mfma}) + 0.25 * std::min(valu, lds) + 300.0;
 }
 
 void gemm_macro_shape(int nrt, int nct, int* mr, int* mc)
@@ -230,7 +239,10 @@ void gemm_macro_shape(int nrt, int nct, int* mr, int* mc)
     double best = 0.0;
     *mr = *mc = 1;
     for (int r = 1; r <= std::min(nrt, kGemmMaxOps - 1); ++r) {
-        const int c = std::min(kGemmMaxOps - r, kGemmMaxOut / r);
+        // the widest c with r + c operand tiles and ceil(r/2) ceil(c/2) 2 x 2 output
+        // blocks (one per wave) within the kernel's 16 waves
+        int c = kGemmMaxOps - r;
+        while (c > 1 && ((r + 1) / 2) * ((c + 1) / 2) > kGemmMaxOps) --c;
         const int nr = (nrt + r - 1) / r, nc = (nct + c - 1) / c;
         double cost = 0.0;
         for (int i = 0; i < nr; ++i)

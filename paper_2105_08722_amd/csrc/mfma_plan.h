@@ -36,13 +36,13 @@ int build_mfma_plan(int N, int lmax, bool allparity, int nbins, MfmaPlan& P);
 // the other KR = K - KL factors (their (l, m), bins b_KL < b_{KL+1} < .. < b_K).
 // Rows and columns are grouped in blocks of fixed (sum of the row factors' m, b_KL):
 // a tuple's row and column meet only inside its block.  Each block is cut into
-// macro tiles of MR x MC 16 x 16 output tiles, MR + MC <= kGemmMaxOps and MR * MC <=
-// kGemmMaxOut; one workgroup forms a macro tile's MR + MC operand tiles once per 16
-// primaries and computes all its output tiles from them.  The shape is chosen per
+// macro tiles of MR x MC 16 x 16 output tiles, MR + MC <= kGemmMaxOps and at most
+// kGemmMaxOps blocks of 2 x 2 output tiles (ceil(MR/2) ceil(MC/2)); one workgroup
+// forms a macro tile's MR + MC operand tiles once per 16 primaries and computes all
+// its output tiles from them, one 2 x 2 block per wave.  The shape is chosen per
 // block: thin blocks (few row tiles) take long macro tiles, so that their row
 // operands are formed fewer times.
 constexpr int kGemmMaxOps = 16;      // operand tiles of a macro tile (one per wave)
-constexpr int kGemmMaxOut = 64;      // output tiles of a macro tile (four per wave)
 constexpr int kGemmMacroWidth = 5;   // row_start, col_start, row tiles, column tiles, tile_base
 struct GemmPlan {
     int K = 0, KL = 0, KR = 0, nlm = 0, nbins = 0, nent = 0;

@@ -64,7 +64,7 @@ static void check_case(int N, int L, bool allp, int nbins, int KL, int nprim, un
     const size_t nmacro = P.macros.size() / kGemmMacroWidth;
     for (size_t mc = 0; mc < nmacro; ++mc) {
         const int32_t* M = &P.macros[mc * kGemmMacroWidth];
-        if (M[2] < 1 || M[3] < 1 || M[2] + M[3] > kGemmMaxOps || M[2] * M[3] > kGemmMaxOut) {
+        if (M[2] < 1 || M[3] < 1 || M[2] + M[3] > kGemmMaxOps || ((M[2] + 1) / 2) * ((M[3] + 1) / 2) > kGemmMaxOps) {
             std::printf("FAIL N=%d L=%d: macro shape %d x %d\n", N, L, M[2], M[3]);
             ++failures;
             return;
