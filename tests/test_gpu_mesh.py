@@ -38,6 +38,8 @@ CASES = [  # N, lmax, n, allparity
     (4, 3, 16, False),
     (4, 2, 12, True),
     (5, 1, 16, False),
+    (6, 1, 12, False),
+    (6, 1, 12, True),
 ]
 
 
@@ -49,7 +51,9 @@ def test_mesh_matches_oracle(ctx, N, lmax, n, allp, precision):
     import torch
     _say("mesh N=%d lmax=%d n=%d allparity=%s %s" % (N, lmax, n, allp, precision))
     L = float(n)                                   # cell side 1
-    edges = np.array([1.5, 2.7, 4.1, 5.3, 5.9])     # no mesh distance falls on an edge
+    # no mesh distance falls on an edge (squared edges are not integers); the 6PCF
+    # needs five bins for a bin tuple
+    edges = np.array([1.5, 2.3, 3.1, 3.9, 4.7, 5.5]) if N == 6 else np.array([1.5, 2.7, 4.1, 5.3, 5.9])
     assert encore.num_bin_tuples(N, len(edges) - 1) > 0
     pos, w = _catalog(600, n, L, 7 * N + lmax)
     delta = synth.mesh_counts(pos, w, n, L)
