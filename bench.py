@@ -454,6 +454,18 @@ def main():
         extra["speedup_vs_fp64_path"] = extra["fp64_path"]["ms_per_step"] / ms
         extra["accuracy_vs_fp64_path"] = {"max_e_lambda": float(np.max(num[keep] / den[keep])),
                                           "median_e_lambda": float(np.median(num[keep] / den[keep]))}
+        if args.precision != "fp32":
+            # the plain FP32 path (compensated FP32 coefficients, FP32 VALU coupling)
+            log("FP32 path, one step")
+            step("fp32")
+            t2 = time.perf_counter()
+            z32, tm32 = step("fp32")
+            t3 = time.perf_counter()
+            e32 = np.linalg.norm(z32 - z64, axis=1)[keep] / den[keep]
+            extra["fp32_path"] = {"value": n / (t3 - t2), "unit": "primaries/s", "ms_per_step": (t3 - t2) * 1e3,
+                                  "gather_ms": tm32["gather_ms"], "couple_ms": tm32["couple_ms"],
+                                  "max_e_lambda_vs_fp64_path": float(np.max(e32)),
+                                  "median_e_lambda_vs_fp64_path": float(np.median(e32))}
     if args.batched_jobs > 0:
         log("batched leg: %d catalogs" % args.batched_jobs)
         extra["batched"] = batched_leg(ctx, edges, args.precision, args.batched_jobs)
