@@ -455,7 +455,7 @@ def main():
         extra["accuracy_vs_fp64_path"] = {"max_e_lambda": float(np.max(num[keep] / den[keep])),
                                           "median_e_lambda": float(np.median(num[keep] / den[keep]))}
         if args.precision != "fp32":
-            # the plain FP32 path (compensated FP32 coefficients, FP32 VALU coupling)
+            # the plain FP32 path (FP32 terms summed in FP64, FP32 VALU coupling)
             log("FP32 path, one step")
             step("fp32")
             t2 = time.perf_counter()

@@ -161,10 +161,10 @@ int check_grid_edges(const DevGrid& g, const double* edges, int nbins)
 
 int gather_precision(int prec)
 {
-    // The FP32 path keeps each lane's sums compensated: on survey geometry the
+    // The FP32 path sums each lane's FP32 terms in FP64: on survey geometry the
     // data-minus-randoms terms cancel inside each coefficient, and plain FP32
     // sums then miss 1e-6 on the multiplets (measured 9e-6 on the 6PCF of the
-    // survey wedge, 8e-7 compensated).  The split-bf16 path's own products carry
+    // survey wedge, 6e-7 with FP64 sums).  The split-bf16 path's own products carry
     // ~1e-5, far above what plain FP32 sums add, so it keeps the faster gather.
     return prec == 0 ? 0 : (prec == 1 ? 2 : 1);
 }

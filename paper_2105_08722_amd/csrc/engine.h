@@ -118,7 +118,7 @@ struct NpcfPlan {
 };
 int plan_call(int npcf, int lmax, int nbins, const double* edges, uint32_t flags, NpcfPlan* pl);
 // Gather variant of a call precision (0 FP64, 1 FP32, 2 split-BF16): 0 FP64
-// accumulators, 1 FP32 (split-BF16), 2 compensated FP32 (FP32); see launch_gather.
+// accumulators, 1 FP32 (split-BF16), 2 FP32 terms in FP64 sums (FP32); see launch_gather.
 int gather_precision(int prec);
 
 // per-job accumulator length: ntuple * nB (VALU coupling) or the dense MFMA tiles

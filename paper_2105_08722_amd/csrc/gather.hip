@@ -70,7 +70,7 @@ template <> __device__ __forceinline__ float rsqrt_t<float>(float v) { return __
 template <> __device__ __forceinline__ double rsqrt_t<double>(double v) { return 1.0 / sqrt(v); }
 
 // LDS of one wave: the per-bin rings (reused as the reduction scratch, whose values
-// are FP64 for the FP64 and the compensated FP32 accumulators) and the piece
+// are FP64 for the FP64 accumulators of the FP64 and the FP32 paths) and the piece
 // descriptors of one row batch.
 template <typename T, int NBG, bool COMP>
 __host__ __device__ constexpr int ring_bytes()
@@ -143,42 +143,17 @@ struct KappaTable {
 };
 template <int L> struct Kappa { static constexpr KappaTable<L> t{}; };
 
-// s += v, or with COMP the compensated (Kahan) sum: c carries the rounding error of
-// s with the opposite sign (the sum is s - c), so a lane's sum of many pairs loses
-// only the final rounding instead of one per addition.
-template <bool COMP, typename T>
-__device__ __forceinline__ void acc_add(T& s, T& c, T v)
-{
-    if constexpr (COMP) {
-        const T y = v - c;
-        const T t = s + y;
-        c = (t - s) - y;
-        s = t;
-    } else {
-        s += v;
-    }
-}
-// s += a * b (one rounding of the product: fused into the compensated update)
-template <bool COMP, typename T>
-__device__ __forceinline__ void acc_fma(T& s, T& c, T a, T b)
-{
-    if constexpr (COMP) {
-        const T y = __builtin_fmaf(a, b, -c);
-        const T t = s + y;
-        c = (t - s) - y;
-        s = t;
-    } else {
-        s += a * b;
-    }
-}
+// Accumulator type: T, or with COMP (T = float) FP64: the terms w Y_lm are formed in
+// FP32 and each is added exactly into an FP64 sum, so a lane's sum of many pairs
+// keeps no rounding of its own beyond the terms' (the data-minus-randoms terms cancel
+// inside each coefficient, and FP32 sums would lose that difference).
+template <typename T, bool COMP>
+using AccT = typename std::conditional<COMP, double, T>::type;
 
-// Add w*Y_lm for m in [M0, M1] of one pair into acc (layout [lm][re, im]); with
-// COMP, cmp holds the compensation of each accumulator (unused otherwise).
+// Add w*Y_lm for m in [M0, M1] of one pair into acc (layout [lm][re, im]).
 template <typename T, int L, int M0, int M1, bool COMP>
-__device__ __forceinline__ void accum_pair(T dx, T dy, T dz, T w, T (&acc)[nlm_of(L)][2],
-                                           T (&cmp)[COMP ? nlm_of(L) : 1][2])
+__device__ __forceinline__ void accum_pair(T dx, T dy, T dz, T w, AccT<T, COMP> (&acc)[nlm_of(L)][2])
 {
-    auto C = [&](int q, int ri) -> T& { return cmp[COMP ? q : 0][ri]; };
     const T r2 = dx * dx + dy * dy + dz * dz;
     const T inv = rsqrt_t<T>(r2);
     const T x = dx * inv, y = dy * inv, z = dz * inv;
@@ -201,27 +176,49 @@ __device__ __forceinline__ void accum_pair(T dx, T dy, T dz, T w, T (&acc)[nlm_o
             }
         }
         T r0 = w, r1 = zw;
-        if (m == 0) {
-            acc_add<COMP>(acc[lm_index(0, 0)][0], C(lm_index(0, 0), 0), r0);
-            if (L >= 1) acc_add<COMP>(acc[lm_index(1, 0)][0], C(lm_index(1, 0), 0), r1);
-        } else {
-            acc_fma<COMP>(acc[lm_index(m, m)][0], C(lm_index(m, m), 0), r0, ur);
-            acc_fma<COMP>(acc[lm_index(m, m)][1], C(lm_index(m, m), 1), r0, ui);
-            if (m + 1 <= L) {
-                acc_fma<COMP>(acc[lm_index(m + 1, m)][0], C(lm_index(m + 1, m), 0), r1, ur);
-                acc_fma<COMP>(acc[lm_index(m + 1, m)][1], C(lm_index(m + 1, m), 1), r1, ui);
-            }
-        }
+        if constexpr (COMP) {
+            // each recurrence value and (x + i y)^m widened once, one FP64 FMA per term
+            const double urd = ur, uid = ui;
+            auto put = [&](int l, T rn) {
+                const double rd = rn;
+                if (m == 0) {
+                    acc[lm_index(l, 0)][0] += rd;
+                } else {
+                    acc[lm_index(l, m)][0] = fma(rd, urd, acc[lm_index(l, m)][0]);
+                    acc[lm_index(l, m)][1] = fma(rd, uid, acc[lm_index(l, m)][1]);
+                }
+            };
+            put(m, r0);
+            if (m + 1 <= L) put(m + 1, r1);
 #pragma unroll
-        for (int l = m + 2; l <= L; ++l) {
-            const T rn = z * r1 - (T)Gamma<L>::t.v[lm_index(l, m)] * r0;
-            if (m == 0) {
-                acc_add<COMP>(acc[lm_index(l, 0)][0], C(lm_index(l, 0), 0), rn);
-            } else {
-                acc_fma<COMP>(acc[lm_index(l, m)][0], C(lm_index(l, m), 0), rn, ur);
-                acc_fma<COMP>(acc[lm_index(l, m)][1], C(lm_index(l, m), 1), rn, ui);
+            for (int l = m + 2; l <= L; ++l) {
+                const T rn = z * r1 - (T)Gamma<L>::t.v[lm_index(l, m)] * r0;
+                put(l, rn);
+                r0 = r1; r1 = rn;
             }
-            r0 = r1; r1 = rn;
+        } else {
+            if (m == 0) {
+                acc[lm_index(0, 0)][0] += r0;
+                if (L >= 1) acc[lm_index(1, 0)][0] += r1;
+            } else {
+                acc[lm_index(m, m)][0] += r0 * ur;
+                acc[lm_index(m, m)][1] += r0 * ui;
+                if (m + 1 <= L) {
+                    acc[lm_index(m + 1, m)][0] += r1 * ur;
+                    acc[lm_index(m + 1, m)][1] += r1 * ui;
+                }
+            }
+#pragma unroll
+            for (int l = m + 2; l <= L; ++l) {
+                const T rn = z * r1 - (T)Gamma<L>::t.v[lm_index(l, m)] * r0;
+                if (m == 0) {
+                    acc[lm_index(l, 0)][0] += rn;
+                } else {
+                    acc[lm_index(l, m)][0] += rn * ur;
+                    acc[lm_index(l, m)][1] += rn * ui;
+                }
+                r0 = r1; r1 = rn;
+            }
         }
     }
 }
@@ -466,11 +463,11 @@ __host__ __device__ constexpr int gather_wpe()
 }
 
 // PERS: persistent grid (work items pulled from queues); otherwise one item per wave.
-// COMP (T = float only): compensated accumulators, reduced across lanes in FP64.
+// COMP (T = float only): FP32 terms summed in FP64 accumulators, reduced in FP64.
 template <typename T, int L, int NBG, int M0, int M1, bool PERS, bool COMP>
 __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG, M0, M1, COMP>())) k_gather(GatherArgs a)
 {
-    static_assert(!COMP || std::is_same_v<T, float>, "compensated accumulation is for FP32");
+    static_assert(!COMP || std::is_same_v<T, float>, "FP64 accumulation of FP32 terms is for FP32");
     using E = typename Entry<T>::type;
     using RT = typename std::conditional<COMP, double, T>::type;   // lane reduction type
     constexpr int NLM = nlm_of(L);
@@ -545,16 +542,12 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
     int head[NBG], tail[NBG];
 #pragma unroll
     for (int k = 0; k < NBG; ++k) { head[k] = 0; tail[k] = 0; }
-    T acc[NBG][NLM][2];
-    T cmp[NBG][COMP ? NLM : 1][2];
+    using A = AccT<T, COMP>;
+    A acc[NBG][NLM][2];
 #pragma unroll
     for (int k = 0; k < NBG; ++k)
 #pragma unroll
-        for (int q = 0; q < NLM; ++q) { acc[k][q][0] = (T)0; acc[k][q][1] = (T)0; }
-#pragma unroll
-    for (int k = 0; k < NBG; ++k)
-#pragma unroll
-        for (int q = 0; q < (COMP ? NLM : 1); ++q) { cmp[k][q][0] = (T)0; cmp[k][q][1] = (T)0; }
+        for (int q = 0; q < NLM; ++q) { acc[k][q][0] = (A)0; acc[k][q][1] = (A)0; }
 
     // row range (unwrapped cell indices)
     // (reciprocal multiplies: the pad of Rc is far above their rounding)
@@ -735,7 +728,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
                         if (tail[K] - head[K] >= kWave) {
                             wave_sync();
                             const E e = ring[K * kCap + ((head[K] + lane) & (kCap - 1))];
-                            accum_pair<T, L, M0, M1, COMP>(e.x, e.y, e.z, e.w, acc[K], cmp[K]);
+                            accum_pair<T, L, M0, M1, COMP>(e.x, e.y, e.z, e.w, acc[K]);
                             head[K] += kWave;
                         }
                     }(), ...);
@@ -774,7 +767,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
             if (rem > 0) {
                 E e = ring[K * kCap + ((head[K] + lane) & (kCap - 1))];
                 if (lane >= rem) { e.x = (T)1; e.y = (T)0; e.z = (T)0; e.w = (T)0; }
-                accum_pair<T, L, M0, M1, COMP>(e.x, e.y, e.z, e.w, acc[K], cmp[K]);
+                accum_pair<T, L, M0, M1, COMP>(e.x, e.y, e.z, e.w, acc[K]);
             }
         }(), ...);
     }(std::make_integer_sequence<int, NBG>{});
@@ -782,8 +775,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
 
     // ---- 4. reduce the 64 lanes' accumulators and write
     constexpr int NV = NBG * NLM * 2;
-    T* accf = &acc[0][0][0];
-    T* cmpf = &cmp[0][0][0];
+    A* accf = &acc[0][0][0];
     const int nvalid = (b_hi - b_lo) * NLM * 2;
     T* out = reinterpret_cast<T*>(a.alm) + ((size_t)row * a.nbins + b_lo) * NLM * 2;
     if (grp == 0 && lane == 0) a.wprim[row] = Pi.w;
@@ -832,15 +824,14 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         }
         wave_sync();
     } else {
-        // FP64 (or compensated FP32, as s - c in FP64) accumulators: through LDS,
-        // 8 interleaved FP64 partial sums per value
+        // FP64 accumulators (the FP64 path, and the FP32 path's FP64 sums): through
+        // LDS, 8 interleaved FP64 partial sums per value
 #pragma unroll
         for (int v0 = 0; v0 < NV; v0 += CH) {
 #pragma unroll
             for (int c = 0; c < CH; ++c)
                 if (v0 + c < NV) {
-                    if constexpr (COMP) scratch[c * 65 + lane] = (double)accf[v0 + c] - (double)cmpf[v0 + c];
-                    else scratch[c * 65 + lane] = accf[v0 + c];
+                    scratch[c * 65 + lane] = accf[v0 + c];
                 }
             wave_sync();
             const int v = v0 + lane;
@@ -925,8 +916,8 @@ int nbg_env()
 }
 
 // The compiled variant with `nbg` bins per item, or the default (first) one.
-// precision: 0 FP64, 1 FP32, 2 FP32 with compensated accumulators (as many
-// registers per value as FP64, so the same bins per item and m split).
+// precision: 0 FP64, 1 FP32, 2 FP32 terms with FP64 accumulators (as many registers
+// per value as FP64, so the same bins per item and m split).
 KernelCfg config(int lmax, int precision, int nbg)
 {
     if (nbg_env() > 0) nbg = nbg_env();

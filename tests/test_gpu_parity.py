@@ -3,9 +3,10 @@
 Tolerances (tests/parity_bars.py)
   * FP64 path: the device uses the same FP64 bin decisions as the oracle and FP64
     arithmetic throughout; differences are rounding-order only: 1e-10 of max|Z|.
-  * FP32 path: FP32 unit vectors and Y_lm from FP64 separations, compensated FP32
-    accumulators reduced across lanes in FP64, FP32 coupling products, FP64 sums
-    over primaries.  Split-BF16 path: the FP32 gather without compensation, then
+  * FP32 path: FP32 unit vectors and Y_lm from FP64 separations, each FP32 term
+    added into FP64 per-lane accumulators reduced across lanes in FP64, FP32
+    coupling products, FP64 sums over primaries.  Split-BF16 path: the FP32 gather
+    with FP32 sums, then
     coupling products on the matrix cores with both operands split into bf16
     hi + lo and hi*hi + hi*lo + lo*hi summed in FP32 (flushed into FP64 every 256
     primaries); each product carries at most 3 * 2^-18 = 1.1e-5 of its magnitude.
@@ -273,7 +274,7 @@ def test_autotune_then_parity():
                                   n_sample=1000)
             _say("  %s: %s" % (prec, rep))
             assert (rep["cell_divisor"], rep["x_subdivision"]) in [(5, 8), (5, 6), (6, 8), (5, 4), (4, 6), (6, 4), (8, 4), (4, 8)]
-            # compiled bins-per-item values at lmax 5: compensated FP32 {2, 1}, FP32 {2, 3}
+            # compiled bins-per-item values at lmax 5: FP32 path (FP64 sums) {2, 1}, split-bf16 {2, 3}
             assert rep["bins_per_item"] in ((2, 1) if prec == "fp32" else (2, 3))
             assert 0 < rep["best_ms"] <= rep["default_ms"]
             prim = rng.choice(len(pos), 200, replace=False)
@@ -388,7 +389,7 @@ def test_config3_wedge_sampled_primaries(ctx, cfg3, N, lmax, nprim, precision):
          % (e.max(), np.median(e), np.median(kappa), np.max(e / (np.maximum(kappa, 1.0) + 1.0))))
     # The D-R field cancels inside each harmonic coefficient (sum_j |w_j Y_lm| /
     # |a~_lm| has median ~24 and reaches 1e3..1e5 on this geometry): the FP32
-    # gather's compensated accumulators keep that from reaching Z.
+    # gather's FP64 accumulators keep that from reaching Z.
     bars.check(zg, zo, za, precision, "wedge")
 
 
