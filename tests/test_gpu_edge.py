@@ -142,3 +142,31 @@ def test_edge_timings(ctx):
     assert t["total_ms"] > 0.0
     assert t["gather_ms"] == 0.0 and t["couple_ms"] == 0.0 and t["contract_ms"] == 0.0
     assert t["batches"] == 0 and t["pairs"] == 0
+
+
+@pytest.mark.parametrize("strong", [False, True])
+def test_edge_blocked_solve_many_panels(ctx, strong):
+    """The blocked LU on systems of 585 multiplets (5PCF, lmax 4: 19 panels of 32
+    columns, trailing updates over several 128 x 128 tiles), against numpy's LU solve
+    of the device's own coupling matrices (the Gaunt terms are pinned separately
+    against the oracle).  A mild window (R_0 dominant) and a strong one (every R_L of
+    order R_0, so that the matrices are far from diagonal and the pivoting exchanges
+    rows)."""
+    N, lmax, nbins = 5, 4, 6
+    _say("edge blocked solve N=%d lmax=%d strong=%s" % (N, lmax, strong))
+    nB = encore.num_bin_tuples(N, nbins)
+    n = encore.num_multiplets(N, lmax)
+    rng = np.random.default_rng(11 + strong)
+    R = rng.normal(0.0, 1.0 if strong else 0.03, (n, nB))
+    R[0] = rng.uniform(1.0, 3.0, nB)
+    Nm = rng.normal(0.0, 1.0, (n, nB))
+    z, M, bad = encore.edge_correct(ctx, N, lmax, nbins, Nm, R, return_coupling=True)
+    assert bad == 0
+    for b in range(nB):
+        A = M[b].T                                   # eq. edge-correction-matrix: sum_L zeta_L M[L][L'']
+        zr = np.linalg.solve(A, Nm[:, b] / R[0, b])
+        # two backward-stable solvers agree to ~cond(A) * eps
+        cond = np.linalg.cond(A)
+        if strong and b == 0:
+            _say("  cond of the first matrix: %.1e" % cond)
+        assert np.max(np.abs(z[:, b] - zr)) <= 1e-13 * cond * np.max(np.abs(zr))
