@@ -42,7 +42,7 @@ def test_closed_forms_match_definition(N, lmax, parity):
 
 def test_closed_form_n6_matches_definition():
     """The N = 6 closed form (three 9j symbols, two intermediates) against the
-    definition: every triple at lmax = 1 (both parities), and 1500 triples at lmax
+    definition: every triple at lmax = 1 (both parities), and 600 triples at lmax
     = 2 that pass the per-direction triangle rules (the others vanish on both
     sides)."""
     lams = multiplets(6, 1, "all")
@@ -62,7 +62,7 @@ def test_closed_form_n6_matches_definition():
     rng = np.random.default_rng(6)
     lams = multiplets(6, 2, "all")
     n, worst, nonzero = 0, 0.0, 0
-    while n < 1500:
+    while n < 600:
         a, b, c = (lams[i] for i in rng.integers(0, len(lams), 3))
         la, lb, lc = principal(6, a), principal(6, b), principal(6, c)
         if not all(abs(x - y) <= z <= x + y and (x + y + z) % 2 == 0 for x, y, z in zip(la, lb, lc)):
@@ -71,7 +71,7 @@ def test_closed_form_n6_matches_definition():
         d = edge.gaunt_definition(6, a, b, c)
         nonzero += abs(d) > 1e-12
         worst = max(worst, abs(edge.gaunt_closed(6, a, b, c) - d))
-    assert nonzero > 500 and worst < 1e-13
+    assert nonzero > 200 and worst < 1e-13
 
 
 @pytest.mark.parametrize("N,lmax,parity", [(3, 3, "even"), (4, 2, "all"), (5, 1, "even"), (6, 1, "all")])
