@@ -271,14 +271,16 @@ int encore_mfma_plan_stats(int npcf, int lmax, int nbins, uint32_t flags, int64_
  * Autotuner of the launch shapes: builds trial grids of the catalog (host arrays,
  * as encore_build_grid) with 8 cell shapes (cell side r_max/d on y and z,
  * r_max/(d*s) on x, where one cell row is a contiguous particle range; (d, s) =
- * (5, 8) -- the default without tuning --, (5, 6), (6, 8), (5, 4), (4, 6), (6, 4),
- * (8, 4), (4, 8)) and times,
+ * (5, 16) -- the default without tuning --, (5, 8), (6, 16), (5, 24), (6, 8),
+ * (4, 16), (5, 4), (4, 8)) and times,
  * for each, the gather + coupling of this job (as encore_npcf) over a sample of
  * n_sample primaries (16 runs of consecutive cell-sorted primaries spread over the
  * grid, so that neighbouring work items share cells as in a full pass), for every compiled
  * bins-per-work-item value of the gather.  The fastest (d, s) becomes the cell
  * shape of later grids built on ctx; the fastest bins-per-item value is used by
- * later calls with the same lmax, gather precision and nbins.  The choice changes
+ * later calls with the same lmax, gather precision and nbins.  The default shape
+ * and bins per item are kept unless the fastest is more than 1% faster on the
+ * sample (sample timings of nearby shapes differ by about that much).  The choice changes
  * only the order of floating-point operations, never what is computed.
  *  report  NULL or [5]: d, s, bins per item, best ms, ms of the default shape.
  * Errors: as encore_build_grid and encore_npcf; ESIZE if report_len < 5.

@@ -687,7 +687,8 @@ int encore_autotune(encore_ctx* ctx, const double* pos, const double* w, int64_t
     const int gprec = gather_precision(pl.prec);
     const std::vector<int> nbgs = gather_nbg_options(lmax, gprec);
     // cell shapes tried: (y/z divisor of r_max, extra x subdivision); the default first
-    static const double kCells[][2] = {{5, 8}, {5, 6}, {6, 8}, {5, 4}, {4, 6}, {6, 4}, {8, 4}, {4, 8}};
+    constexpr double kTuneMargin = 0.99;
+    static const double kCells[][2] = {{5, 16}, {5, 8}, {6, 16}, {5, 24}, {6, 8}, {4, 16}, {5, 4}, {4, 8}};
     // The sample: 16 runs of consecutive cell-sorted primaries spread over the grid,
     // so that neighbouring work items share cells as in a full pass (a scattered
     // sample would time cache misses that a full pass does not have).
@@ -760,6 +761,12 @@ int encore_autotune(encore_ctx* ctx, const double* pos, const double* w, int64_t
     (void)hipFree(d_pos);
     (void)hipFree(d_w);
     if (rc) return rc;
+    // a shape replaces the default only when it is clearly faster on the sample:
+    // the shapes near the best differ by about as much as repeated timings do, and
+    // a sample-noise pick can be slower on the full pass
+    if (!(best < kTuneMargin * dflt)) {
+        best = dflt; best_div = kCells[0][0]; best_xsub = kCells[0][1]; best_nbg = nbgs[0];
+    }
     {
         std::lock_guard<std::mutex> tl(ctx->tab_mu);
         ctx->cell_div = best_div;

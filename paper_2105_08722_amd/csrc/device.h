@@ -12,12 +12,18 @@ namespace encore {
 constexpr int kMaxBins = 16;     // radial bins per call
 constexpr int kMaxLmax = 10;     // largest principal ell built
 constexpr int kWave = 64;        // CDNA wavefront
+// NaN records after a grid's points: a chunk of kWave candidates that runs past
+// the last one maps its spare lanes onto distinct sentinels, which no bin accepts
+constexpr int kSentinels = kWave;
+// largest catalog of one grid: the gather packs a point index (sentinels
+// included) and a 6-bit image code into 32 bits
+constexpr int64_t kMaxGridPoints = (int64_t(1) << 26) - kSentinels;
 
 // Cell-sorted catalog on the device.  Particles are sorted by cell index
 // (cz * ncy + cy) * ncx + cx, so the cells of one (cy, cz) row are contiguous.
 struct DevGrid {
     int64_t n = 0;
-    double4* P = nullptr;        // sorted (x, y, z, w) in FP64; P[n] is a NaN sentinel
+    double4* P = nullptr;        // sorted (x, y, z, w) in FP64; P[n .. n+kSentinels) are NaN
     int32_t* perm = nullptr;     // sorted index -> input index
     int32_t* inv = nullptr;      // input index -> sorted index
     int32_t* cell_start = nullptr;  // [ncell + 1]
@@ -69,7 +75,7 @@ int launch_split_randoms(const DevGrid& S, double* pos, double* w, hipStream_t s
 // Work item = (slice row, bin group); rows are written as complex
 // alm[row][nbins][nlm] plus the primary's weight wprim[row].
 struct GatherSeg {
-    const double4* P;      // secondaries (cell-sorted, n points + the NaN sentinel)
+    const double4* P;      // secondaries (cell-sorted, n points + kSentinels NaN records)
     const int32_t* cell_start;
     const double4* Pq;     // primary records (P, or another grid's points)
     const int32_t* prim;   // indices into Pq of this segment's primaries
@@ -77,7 +83,7 @@ struct GatherSeg {
     double ox, oy, oz, csx, csy, csz;
     double Lx, Ly, Lz;
     int row0, nprim;
-    int nP, pad_;          // points of P (index of the sentinel)
+    int nP, pad_;          // points of P (index of the first sentinel)
     // derived by finish_seg: reciprocal cell sizes, the pad of the culling radius
     // and the FP32 row set-up margin (both in length units)
     double icsx, icsy, icsz, cull_pad, frame_eps;

@@ -644,10 +644,10 @@ double cell_x_subdiv(double tuned)
     const char* s = getenv("ENCORE_CELL_XSUB");
     if (s) {
         const int v = atoi(s);
-        if (v >= 1 && v <= 8) return v;
+        if (v >= 1 && v <= 32) return v;
     }
-    if (tuned >= 1.0 && tuned <= 8.0) return tuned;
-    return 8.0;
+    if (tuned >= 1.0 && tuned <= 32.0) return tuned;
+    return 16.0;
 }
 
 int ctx_nbg(encore_ctx* ctx, const NpcfPlan& pl)

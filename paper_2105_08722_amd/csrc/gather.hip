@@ -24,7 +24,7 @@
 //
 // Primaries are read from the segment's primary array (the catalog's own points,
 // or another grid's), candidates from its cell-sorted points; lanes past the last
-// candidate take the grid's NaN sentinel point, which no bin accepts.
+// candidate take the grid's NaN sentinel points, which no bin accepts.
 //
 // Y_lm = N_lm(z) (x + i y)^m for a unit vector (Condon-Shortley phase inside N_lm);
 // N_lm = kappa_lm R_lm with R_mm = 1, R_{m+1,m} = z, R_lm = z R_{l-1,m} - gamma_lm R_{l-2,m}.
@@ -595,22 +595,30 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         // ---- 2./3. candidates, 64 per chunk: lane l of the chunk at flat position p0
         //      takes candidate p0 + l, whose entry (particle index | image code) is
         //      p0 + l plus the delta of the last piece starting at or before it.
-        //      Positions past the batch take the grid's sentinel point (NaN position:
-        //      every bin compare is false).  Piece descriptors are held 64 at a time
-        //      in VGPRs (lane l: piece gbase + l) and read with readlane.
+        //      One more piece starts at the batch's end and maps the positions past
+        //      it onto the grid's NaN sentinels (every bin compare is false), so no
+        //      lane needs a select of its own; whole chunks past the end take the
+        //      first sentinel.  Piece descriptors are held 64 at a time in VGPRs
+        //      (lane l: piece gbase + l) and read with readlane.
         const unsigned fill_entry = (unsigned)g.nP | ((unsigned)kCenterCode << kCodeShift);
         int gbase = 0;
         unsigned dl_v = 0;
         int fs_v = 0;
         auto reload = [&](int base) {
             gbase = base;
-            const int sl = base + lane;
+            // the window start as an opaque scalar: the LDS address is formed here,
+            // on a reload, and not carried along the walk as a vector induction
+            int b = base;
+            asm("" : "+s"(b));
+            const int sl = b + lane;
             dl_v = sl < nseg ? seg_dl[sl] : 0u;
             fs_v = sl < nseg ? seg_flat[sl] : INT_MAX;
         };
-        // descriptor of piece t (uniform); past the last piece: start INT_MAX
+        // descriptor of piece t (uniform); piece nseg is the sentinel piece, past
+        // it the start is INT_MAX
+        const unsigned fill_delta = fill_entry - (unsigned)total;
         auto desc = [&](int t, unsigned& dl, int& fs) {
-            if (t >= nseg) { dl = 0u; fs = INT_MAX; return; }
+            if (t >= nseg) { dl = t == nseg ? fill_delta : 0u; fs = t == nseg ? total : INT_MAX; return; }
             if (t < gbase || t >= gbase + kWave) reload(t);
             dl = (unsigned)__builtin_amdgcn_readlane((int)dl_v, t - gbase);
             fs = __builtin_amdgcn_readlane(fs_v, t - gbase);
@@ -646,7 +654,6 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
                     desc(sg + 1, dnext, fnext);
                 } while (fnext < p0 + kWave);
             }
-            if (p0 + kWave > total && (int)pl >= total) me = fill_entry;
             return me;
         };
         {

@@ -194,9 +194,9 @@ __global__ void k_gather_sorted(const double* __restrict__ pos, const double* __
                                 double4* __restrict__ P, int32_t* __restrict__ inv)
 {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k > n) return;
-    if (k == n) {   // sentinel past the last point: NaN position, never binned
-        P[n] = make_double4(NAN, NAN, NAN, 0.0);
+    if (k >= n + kSentinels) return;
+    if (k >= n) {   // sentinels past the last point: NaN position, never binned
+        P[k] = make_double4(NAN, NAN, NAN, 0.0);
         return;
     }
     const int32_t i = perm[k];
@@ -373,10 +373,9 @@ int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, in
     g.r_max = r_max;
     g.dmr = dmr ? 1 : 0;
     g.n_data = dmr ? n_data : n;
-    // the gather packs a particle index and a 6-bit image code into one int
-    if (n >= (int64_t(1) << 26)) {
-        snprintf(errbuf, errlen, "catalog of %lld points exceeds the 2^26-point limit of one grid",
-                 (long long)n);
+    if (n > kMaxGridPoints) {
+        snprintf(errbuf, errlen, "catalog of %lld points exceeds the limit of one grid (%lld)",
+                 (long long)n, (long long)kMaxGridPoints);
         return -1;
     }
 
@@ -462,7 +461,7 @@ int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, in
     HIPCHK(dev_alloc((void**)&g.cell_start, sizeof(int32_t) * (ncell + 1), pool, stream));
     HIPCHK(dev_alloc((void**)&g.perm, sizeof(int32_t) * n, pool, stream));
     HIPCHK(dev_alloc((void**)&g.inv, sizeof(int32_t) * n, pool, stream));
-    HIPCHK(dev_alloc((void**)&g.P, sizeof(double4) * (n + 1), pool, stream));
+    HIPCHK(dev_alloc((void**)&g.P, sizeof(double4) * (n + kSentinels), pool, stream));
     HIPCHK(hipMemsetAsync(d_count, 0, sizeof(int32_t) * ncell, stream));
     k_cell_count<<<nblocks(n), kBlock, 0, stream>>>(d_pos, n, g.ncx, g.ncy, g.ncz, g.ox, g.oy, g.oz,
                                                     g.csx, g.csy, g.csz, d_cell, d_count);
@@ -470,7 +469,7 @@ int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, in
     HIPCHK(hipMemsetAsync(d_count, 0, sizeof(int32_t) * ncell, stream));
     k_scatter<<<nblocks(n), kBlock, 0, stream>>>(d_cell, n, g.cell_start, d_count, g.perm);
     k_cell_sort<<<nblocks(ncell), kBlock, 0, stream>>>(g.cell_start, (int)ncell, g.perm);
-    k_gather_sorted<<<nblocks(n + 1), kBlock, 0, stream>>>(d_pos, wsrc, g.perm, n, g.P, g.inv);
+    k_gather_sorted<<<nblocks(n + kSentinels), kBlock, 0, stream>>>(d_pos, wsrc, g.perm, n, g.P, g.inv);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream));
     rc = 0;

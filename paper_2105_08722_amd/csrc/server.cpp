@@ -297,8 +297,8 @@ void lane_main(encore_server* S, int li)
 // its primary list, T and the normalisation table.
 size_t footprint(int64_t n, int64_t ncell, int64_t outs, int64_t nB)
 {
-    return (size_t)n * (24 + 8 + 8 + 4 + 32 + 4 + 4 + 4) + (size_t)ncell * 8 + (size_t)outs * 8 +
-           (size_t)nB * 8 + ((size_t)1 << 16);
+    return (size_t)n * (24 + 8 + 8 + 4 + 32 + 4 + 4 + 4) + (size_t)kSentinels * 32 + (size_t)ncell * 8 +
+           (size_t)outs * 8 + (size_t)nB * 8 + ((size_t)1 << 16);
 }
 
 }  // namespace
@@ -372,7 +372,7 @@ int encore_server_submit(encore_server* S, const double* pos, const double* w, i
     if (!S || !job_id) return fail(ENCORE_EINVAL, "NULL server or job_id");
     if (!pos || !w) return fail(ENCORE_EINVAL, "NULL pos or w");
     if (n < 1) return fail(ENCORE_EINVAL, "n must be >= 1");
-    if (n >= ((int64_t)1 << 26)) return fail(ENCORE_EINVAL, "catalog exceeds the 2^26-point limit of one grid");
+    if (n > kMaxGridPoints) return fail(ENCORE_EINVAL, "catalog exceeds the point limit of one grid (2^26 - 64)");
     auto j = std::make_unique<SrvJob>();
     int rc;
     if ((rc = plan_call(npcf, lmax, nbins, edges, flags, &j->pl))) return rc;
