@@ -12,9 +12,10 @@ namespace encore {
 constexpr int kMaxBins = 16;     // radial bins per call
 constexpr int kMaxLmax = 10;     // largest principal ell built
 constexpr int kWave = 64;        // CDNA wavefront
-// NaN records after a grid's points: a chunk of kWave candidates that runs past
-// the last one maps its spare lanes onto distinct sentinels, which no bin accepts
-constexpr int kSentinels = kWave;
+// NaN records after a grid's points: the gather maps candidate positions up to
+// 2 * kWave - 1 past a batch's last candidate onto distinct sentinels, which no
+// bin accepts
+constexpr int kSentinels = 2 * kWave;
 // largest catalog of one grid: the gather packs a point index (sentinels
 // included) and a 6-bit image code into 32 bits
 constexpr int64_t kMaxGridPoints = (int64_t(1) << 26) - kSentinels;

@@ -69,16 +69,15 @@ template <typename T> __device__ __forceinline__ T rsqrt_t(T v);
 template <> __device__ __forceinline__ float rsqrt_t<float>(float v) { return __builtin_amdgcn_rsqf(v); }
 template <> __device__ __forceinline__ double rsqrt_t<double>(double v) { return 1.0 / sqrt(v); }
 
-// LDS of one wave: the per-bin rings (reused as the reduction scratch, whose values
-// are FP64 for the FP64 accumulators of the FP64 and the FP32 paths) and the piece
-// descriptors of one row batch.
+// LDS of one wave: the per-bin rings plus one dump entry per lane (reused as the
+// reduction scratch, whose values are FP64 for the FP64 accumulators of the FP64
+// and the FP32 paths) and the piece descriptors of one row batch.
 template <typename T, int NBG, bool COMP>
 __host__ __device__ constexpr int ring_bytes()
 {
     constexpr int red = kRedCh * 65 * ((COMP || sizeof(T) == 8) ? 8 : 4);
-    return (NBG * kCap * (int)sizeof(typename Entry<T>::type) > red)
-               ? NBG * kCap * (int)sizeof(typename Entry<T>::type)
-               : red;
+    constexpr int ring = (NBG * kCap + kWave) * (int)sizeof(typename Entry<T>::type);
+    return ring > red ? ring : red;
 }
 template <typename T, int NBG, bool COMP>
 __host__ __device__ constexpr int wave_lds_bytes()
@@ -597,10 +596,10 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         //      p0 + l plus the delta of the last piece starting at or before it.
         //      One more piece starts at the batch's end and maps the positions past
         //      it onto the grid's NaN sentinels (every bin compare is false), so no
-        //      lane needs a select of its own; whole chunks past the end take the
-        //      first sentinel.  Piece descriptors are held 64 at a time in VGPRs
+        //      lane needs a select of its own.  Piece descriptors are held 64 at a time in VGPRs
         //      (lane l: piece gbase + l) and read with readlane.
         const unsigned fill_entry = (unsigned)g.nP | ((unsigned)kCenterCode << kCodeShift);
+        const unsigned fill_delta = fill_entry - (unsigned)total;
         int gbase = 0;
         unsigned dl_v = 0;
         int fs_v = 0;
@@ -611,15 +610,14 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
             int b = base;
             asm("" : "+s"(b));
             const int sl = b + lane;
-            dl_v = sl < nseg ? seg_dl[sl] : 0u;
-            fs_v = sl < nseg ? seg_flat[sl] : INT_MAX;
+            dl_v = sl < nseg ? seg_dl[sl] : (sl == nseg ? fill_delta : 0u);
+            fs_v = sl < nseg ? seg_flat[sl] : (sl == nseg ? total : INT_MAX);
         };
         // descriptor of piece t (uniform); piece nseg is the sentinel piece, past
-        // it the start is INT_MAX
-        const unsigned fill_delta = fill_entry - (unsigned)total;
+        // it the start is INT_MAX.  The walk only moves forward, so a piece below
+        // the window is never asked for.
         auto desc = [&](int t, unsigned& dl, int& fs) {
-            if (t >= nseg) { dl = t == nseg ? fill_delta : 0u; fs = t == nseg ? total : INT_MAX; return; }
-            if (t < gbase || t >= gbase + kWave) reload(t);
+            if (t >= gbase + kWave) reload(t);
             dl = (unsigned)__builtin_amdgcn_readlane((int)dl_v, t - gbase);
             fs = __builtin_amdgcn_readlane(fs_v, t - gbase);
         };
@@ -629,31 +627,32 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         int sg = 0;
         unsigned dcur = 0u, dnext = 0u;
         int fnext = INT_MAX;
-        if (nseg > 0) {
+        {
             int f0;
-            desc(0, dcur, f0);
+            desc(0, dcur, f0);   // with no pieces: the sentinel piece at 0
             desc(1, dnext, fnext);
         }
-        // entries of the chunk at p0 (uniform, increasing from call to call)
+        // entries of the chunk at p0 (uniform, increasing from call to call).
+        // A chunk past the batch's end stays on the sentinel piece; the prefetch
+        // fetches a chunk only when the one before it starts inside the batch,
+        // so its lanes stay within 2 * kWave - 1 of the end (kSentinels records).
         auto fetch = [&](int p0) -> unsigned {
-            if (p0 >= total) return fill_entry;
             while (fnext <= p0) {
                 ++sg;
                 dcur = dnext;
                 desc(sg + 1, dnext, fnext);
             }
+            if (fnext >= p0 + kWave) return (unsigned)lane + ((unsigned)p0 + dcur);
+            // pieces starting inside the chunk; the walk ends on the last of them,
+            // which holds the next chunk's first position
             const unsigned pl = (unsigned)(p0 + lane);
             unsigned me = pl + dcur;
-            if (fnext < p0 + kWave) {
-                // pieces starting inside the chunk; the walk ends on the last of
-                // them, which holds the next chunk's first position
-                do {
-                    if (lane >= fnext - p0) me = pl + dnext;
-                    ++sg;
-                    dcur = dnext;
-                    desc(sg + 1, dnext, fnext);
-                } while (fnext < p0 + kWave);
-            }
+            do {
+                if (lane >= fnext - p0) me = pl + dnext;
+                ++sg;
+                dcur = dnext;
+                desc(sg + 1, dnext, fnext);
+            } while (fnext < p0 + kWave);
             return me;
         };
         {
@@ -693,7 +692,9 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
                     const unsigned s0 = r0 & (kCap - 1), s1 = (r1 & (kCap - 1)) | (unsigned)kCap;
                     unsigned sl;
                     asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(sl) : "v"(s0), "v"(s1), "s"(km));
-                    slot = (int)sl;
+                    // rejected lanes write their own dump entry: the ring push then
+                    // needs no exec-mask branch
+                    slot = ok ? (int)sl : NBG * kCap + lane;
                     tail[0] += __popcll(m0);
                     tail[1] += __popcll(m1);
                 } else {
@@ -725,10 +726,11 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
                     }
                     slot = k * kCap + ((tk + rank) & (kCap - 1));
                 }
-                if (ok) {
+                {
                     E ev;
                     ev.x = (T)dx; ev.y = (T)dy; ev.z = (T)dz; ev.w = (T)q.w;
-                    ring[slot] = ev;
+                    if constexpr (NBG == 2) ring[slot] = ev;
+                    else if (ok) ring[slot] = ev;
                 }
                 [&]<int... K>(std::integer_sequence<int, K...>) {
                     ([&] {
