@@ -413,27 +413,33 @@ __device__ __forceinline__ void image_range(const GatherSeg& g, int lo, int hi, 
     }
 }
 
-// pieces of a row: one per x range and periodic image (<= kSegPerRow), empty ones included
-__device__ __forceinline__ int row_pieces(const RowGeom& rg, const GatherSeg& g)
+// Pieces of a row: one per x range and periodic image (<= kSegPerRow), empty ones
+// included, split into centre pieces (no periodic image on any axis) and image
+// pieces.  Counted (nc, ni), then written to two slot ranges, so that a batch's
+// flat positions hold all centre pieces first: entry of the first candidate
+// (start | image code) and length.  Because particles are sorted by cell with x
+// fastest, each piece is one contiguous particle range.
+__device__ __forceinline__ void row_pieces_split(const RowGeom& rg, const GatherSeg& g, int& nc, int& ni)
 {
-    int n = 0;
+    nc = 0;
+    ni = 0;
+    const bool yz_centre = rg.code_yz == ((1 << 2) | (1 << 4));
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         if (rg.lo[q] > rg.hi[q]) continue;
         int sxa, sxb;
         image_range(g, rg.lo[q], rg.hi[q], sxa, sxb);
-        n += sxb - sxa + 1;
+        const int c = (yz_centre && sxa <= 0 && sxb >= 0) ? 1 : 0;
+        nc += c;
+        ni += sxb - sxa + 1 - c;
     }
-    return n;
 }
-
-// Write the row's pieces at slots [s0, ...): entry of the first candidate (start |
-// image code) and length.  Because particles are sorted by cell with x fastest,
-// each piece is one contiguous particle range.
-__device__ __forceinline__ int emit_pieces(const RowGeom& rg, const GatherSeg& g, gptr<int32_t> gcs, int s0,
-                                           unsigned* ent, int* len)
+__device__ __forceinline__ void emit_pieces_split(const RowGeom& rg, const GatherSeg& g, gptr<int32_t> gcs,
+                                                  int sc, int si, unsigned* ent, int* len, int& nlc, int& nli)
 {
-    int k = s0, nlen = 0;
+    nlc = 0;
+    nli = 0;
+    const bool yz_centre = rg.code_yz == ((1 << 2) | (1 << 4));
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         if (rg.lo[q] > rg.hi[q]) continue;
@@ -444,13 +450,13 @@ __device__ __forceinline__ int emit_pieces(const RowGeom& rg, const GatherSeg& g
             const int phi = min(rg.hi[q], sx * g.ncx + g.ncx - 1) - sx * g.ncx;
             const int st = gcs[rg.rowbase + plo];
             const int en = gcs[rg.rowbase + phi + 1];
+            const bool centre = yz_centre && sx == 0;
+            const int k = centre ? sc++ : si++;
             ent[k] = (unsigned)st | ((unsigned)((sx + 1) | rg.code_yz) << kCodeShift);
             len[k] = en - st;
-            nlen += en - st;
-            ++k;
+            if (centre) nlc += en - st; else nli += en - st;
         }
     }
-    return nlen;
 }
 
 // waves per SIMD the kernel is compiled for, from its accumulator registers
@@ -577,17 +583,33 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         rg.hi[0] = rg.hi[1] = 0;
         rg.rowbase = rg.code_yz = 0;
         if (r < nrows) rg = row_geom<float>(rf, g, r);
-        const int ns = row_pieces(rg, g);
-        int nseg = 0, total = 0;
-        const int sbase = wave_excl_scan(ns, lane, &nseg);
+        // centre pieces first, image pieces after them: a chunk wholly below
+        // total_c has no image (one scalar compare instead of a per-lane test)
+        int nc, ni;
+        row_pieces_split(rg, g, nc, ni);
+        int ntot = 0;   // both counts in one scan (at most 64 * kSegPerRow each)
+        const int sb = wave_excl_scan(nc | (ni << 16), lane, &ntot);
+        const int nseg_c = ntot & 0xffff;
+        const int nseg = nseg_c + (ntot >> 16);
+        const int sbase_c = sb & 0xffff, sbase_i = nseg_c + (sb >> 16);
         wave_sync();                        // the previous batch's descriptors are consumed
-        const int nlen = emit_pieces(rg, g, gcs, sbase, seg_dl, seg_flat);
-        int fbase = wave_excl_scan(nlen, lane, &total);
-        for (int q = 0; q < ns; ++q) {      // the lane's own slots only
-            const int ln = seg_flat[sbase + q];
-            seg_flat[sbase + q] = fbase;
-            seg_dl[sbase + q] -= (unsigned)fbase;
-            fbase += ln;
+        int nlc, nli;
+        emit_pieces_split(rg, g, gcs, sbase_c, sbase_i, seg_dl, seg_flat, nlc, nli);
+        int total_c = 0, total_i = 0;
+        int fc = wave_excl_scan(nlc, lane, &total_c);
+        int fi = wave_excl_scan(nli, lane, &total_i) + total_c;
+        const int total = total_c + total_i;
+        for (int q = 0; q < nc; ++q) {      // the lane's own slots only
+            const int sl = sbase_c + q, ln = seg_flat[sl];
+            seg_flat[sl] = fc;
+            seg_dl[sl] -= (unsigned)fc;
+            fc += ln;
+        }
+        for (int q = 0; q < ni; ++q) {
+            const int sl = sbase_i + q, ln = seg_flat[sl];
+            seg_flat[sl] = fi;
+            seg_dl[sl] -= (unsigned)fi;
+            fi += ln;
         }
         wave_sync();
 
@@ -657,12 +679,12 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         };
         {
             // one chunk of 64 candidates: exact FP64 bin, ring push, drains
-            auto chunk = [&](const unsigned me, const double4& q) {
-                // x_j - x_i, then the periodic image (+/- L; chunks without images
-                // skip the shift, which would add exactly 0)
+            auto chunk = [&](const unsigned me, const int p0, const double4& q) {
+                // x_j - x_i, then the periodic image (+/- L; chunks below the image
+                // pieces skip the shift, which would add exactly 0)
                 double dx = diff(q.x, xi), dy = diff(q.y, yi), dz = diff(q.z, zi);
-                const int code = (int)(me >> kCodeShift);
-                if (__builtin_amdgcn_ballot_w64(code != kCenterCode)) {
+                if (p0 + kWave > total_c) {
+                    const int code = (int)(me >> kCodeShift);
                     dx = sep(dx, 0.0, (double)((code & 3) - 1) * Lx);
                     dy = sep(dy, 0.0, (double)(((code >> 2) & 3) - 1) * Ly);
                     dz = sep(dz, 0.0, (double)(((code >> 4) & 3) - 1) * Lz);
@@ -751,11 +773,11 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
             for (int c0 = 0; c0 < total; c0 += 2 * kWave) {
                 const unsigned me_b = fetch(c0 + kWave);
                 const double4 q_b = load_point(gP, (int)(me_b & kStartMask));
-                chunk(me_a, q_a);
+                chunk(me_a, c0, q_a);
                 if (c0 + kWave >= total) break;
                 me_a = fetch(c0 + 2 * kWave);
                 q_a = load_point(gP, (int)(me_a & kStartMask));
-                chunk(me_b, q_b);
+                chunk(me_b, c0 + kWave, q_b);
             }
         }
         wave_sync();
@@ -817,7 +839,32 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         }
         const int rrow = lane >> 4;
         const int sub = (rrow == 1) ? 2 : (rrow == 2 ? 1 : rrow);
-        if ((lane & 15) == 0) {
+        if constexpr (M0 == 0 && M1 == L) {
+            // Every coefficient is written: stage the sums in LDS (the rings are
+            // free after the flush) in value order, then lane l scales values
+            // 4l .. 4l+3 (coefficients 2l and 2l+1 mod NLM) and stores them with
+            // two 8-byte stores (an item's row is 8 NLM bytes long, so out is
+            // 8-byte aligned; nvalid is even).
+            static_assert(NV4 / 4 <= kWave && NV4 * 4 <= ring_bytes<T, NBG, COMP>(), "staged values fit");
+            float* st = reinterpret_cast<float*>(base);
+            if ((lane & 15) == 0) {
+#pragma unroll
+                for (int q = 0; q < NV4 / 4; ++q) st[4 * q + sub] = c[q];
+            }
+            wave_sync();
+            if (lane < NV4 / 4) {
+                const int v0 = 4 * lane;
+                const float4 x = *reinterpret_cast<const float4*>(st + v0);
+                const double kA = Kappa<L>::t.v[(2 * lane) % NLM], kB = Kappa<L>::t.v[(2 * lane + 1) % NLM];
+                if (v0 + 1 < nvalid)
+                    *reinterpret_cast<float2*>(out + v0) =
+                        make_float2((T)((double)x.x * kA), (T)((double)x.y * kA));
+                if (v0 + 3 < nvalid)
+                    *reinterpret_cast<float2*>(out + v0 + 2) =
+                        make_float2((T)((double)x.z * kB), (T)((double)x.w * kB));
+            }
+            wave_sync();
+        } else if ((lane & 15) == 0) {
             // value 4q + sub is coefficient 2q + (sub >> 1) (mod NLM), part sub & 1;
             // both candidates and their m are compile-time constants
             const bool hi = (sub >> 1) != 0;
