@@ -138,7 +138,8 @@ __global__ void k_cell_count(const double* __restrict__ pos, int64_t n, int ncx,
 }
 
 // Exclusive scan of count[0..nc) into start[0..nc] with a single block of 1024
-// threads: each thread scans a contiguous chunk, then the chunk totals.
+// threads: each thread scans a contiguous chunk, then the chunk totals.  Used for
+// the tile totals of the cell scan below (at most 2^26 / kScanTile of them).
 __global__ void __launch_bounds__(1024) k_scan(const int32_t* __restrict__ count, int nc,
                                                int32_t* __restrict__ start)
 {
@@ -163,6 +164,64 @@ __global__ void __launch_bounds__(1024) k_scan(const int32_t* __restrict__ count
         run += count[i];
     }
     if (t == 1023) start[nc] = tot[1023];
+}
+
+// The cell scan in three passes over tiles of kScanTile cells: tile totals (reads
+// coalesced across the block), the single-block scan of the totals, then each
+// tile's own scan offset by its total's prefix.
+constexpr int kScanTile = 4096;
+constexpr int kScanPer = kScanTile / 256;
+
+__global__ void __launch_bounds__(256) k_scan_tiles(const int32_t* __restrict__ count, int nc,
+                                                    int32_t* __restrict__ tsum)
+{
+    __shared__ int32_t red[256];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int32_t s = 0;
+    for (int k = 0; k < kScanPer; ++k) {
+        const int64_t i = base + k * 256 + t;
+        if (i < nc) s += count[i];
+    }
+    red[t] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) red[t] += red[t + off];
+        __syncthreads();
+    }
+    if (t == 0) tsum[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_scan_apply(const int32_t* __restrict__ count, int nc,
+                                                    const int32_t* __restrict__ toff, int32_t* __restrict__ start)
+{
+    __shared__ int32_t ws[256];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)t * kScanPer;
+    int32_t v[kScanPer];
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        v[k] = (base + k < nc) ? count[base + k] : 0;
+        s += v[k];
+    }
+    // Hillis-Steele inclusive scan of the 256 thread totals
+    ws[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int32_t u = (t >= off) ? ws[t - off] : 0;
+        __syncthreads();
+        ws[t] += u;
+        __syncthreads();
+    }
+    int32_t run = toff[blockIdx.x] + ws[t] - s;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (base + k < nc) start[base + k] = run;
+        run += v[k];
+    }
+    // the thread holding the last cell also writes the grand total
+    if (base < nc && nc <= base + kScanPer) start[nc] = run;
 }
 
 __global__ void k_scatter(const int32_t* __restrict__ cell, int64_t n, const int32_t* __restrict__ start,
@@ -361,6 +420,8 @@ int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, in
     double* d_mm = nullptr;
     int32_t* d_cell = nullptr;
     int32_t* d_count = nullptr;
+    int32_t* d_tsum = nullptr;
+    int32_t* d_toff = nullptr;
     int flags = 0;
     double mm[6];
     const int npart = 512;
@@ -465,7 +526,14 @@ int grid_build(DevGrid& g, const double* d_pos, const double* d_w, int64_t n, in
     HIPCHK(hipMemsetAsync(d_count, 0, sizeof(int32_t) * ncell, stream));
     k_cell_count<<<nblocks(n), kBlock, 0, stream>>>(d_pos, n, g.ncx, g.ncy, g.ncz, g.ox, g.oy, g.oz,
                                                     g.csx, g.csy, g.csz, d_cell, d_count);
-    k_scan<<<1, 1024, 0, stream>>>(d_count, (int)ncell, g.cell_start);
+    {
+        const int ntile = (int)((ncell + kScanTile - 1) / kScanTile);
+        HIPCHK(dev_alloc((void**)&d_tsum, sizeof(int32_t) * ntile, pool, stream));
+        HIPCHK(dev_alloc((void**)&d_toff, sizeof(int32_t) * (ntile + 1), pool, stream));
+        k_scan_tiles<<<ntile, 256, 0, stream>>>(d_count, (int)ncell, d_tsum);
+        k_scan<<<1, 1024, 0, stream>>>(d_tsum, ntile, d_toff);
+        k_scan_apply<<<ntile, 256, 0, stream>>>(d_count, (int)ncell, d_toff, g.cell_start);
+    }
     HIPCHK(hipMemsetAsync(d_count, 0, sizeof(int32_t) * ncell, stream));
     k_scatter<<<nblocks(n), kBlock, 0, stream>>>(d_cell, n, g.cell_start, d_count, g.perm);
     k_cell_sort<<<nblocks(ncell), kBlock, 0, stream>>>(g.cell_start, (int)ncell, g.perm);
@@ -482,6 +550,8 @@ fail:
     dev_free(d_mm, pool, stream);
     dev_free(d_cell, pool, stream);
     dev_free(d_count, pool, stream);
+    dev_free(d_tsum, pool, stream);
+    dev_free(d_toff, pool, stream);
     if (rc != 0) grid_free(g, stream);
     return rc;
 }
