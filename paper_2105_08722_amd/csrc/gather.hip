@@ -298,15 +298,20 @@ __device__ __forceinline__ GatherSeg load_seg(const GatherSeg* segs, int s)
     return g;
 }
 
+// Exclusive wave scan by DPP: shifts by 1, 2, 4, 8 inside each row of 16 lanes
+// (lanes without a source add 0), then row 0's total into rows 1 and 3 and the
+// total of rows 0-1 into rows 2 and 3 (row broadcasts of lanes 15 and 31).
 __device__ __forceinline__ int wave_excl_scan(int v, int lane, int* total)
 {
+    (void)lane;
     int incl = v;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int t = __shfl_up(incl, off, kWave);
-        if (lane >= off) incl += t;
-    }
-    *total = uni(__shfl(incl, kWave - 1, kWave));
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x111, 0xf, 0xf, false);   // row_shr:1
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x112, 0xf, 0xf, false);   // row_shr:2
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x114, 0xf, 0xf, false);   // row_shr:4
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x118, 0xf, 0xf, false);   // row_shr:8
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    *total = __builtin_amdgcn_readlane(incl, kWave - 1);
     return incl - v;
 }
 
