@@ -279,7 +279,7 @@ int encore_mfma_plan_stats(int npcf, int lmax, int nbins, uint32_t flags, int64_
  * bins-per-work-item value of the gather.  The fastest (d, s) becomes the cell
  * shape of later grids built on ctx; the fastest bins-per-item value is used by
  * later calls with the same lmax, gather precision and nbins.  The default shape
- * and bins per item are kept unless the fastest is more than 1% faster on the
+ * and bins per item are kept unless the fastest is more than 2% faster on the
  * sample (sample timings of nearby shapes differ by about that much).  The choice changes
  * only the order of floating-point operations, never what is computed.
  *  report  NULL or [5]: d, s, bins per item, best ms, ms of the default shape.
