@@ -98,6 +98,32 @@ def test_alm_clustered_nonperiodic_offset_box(ctx):
     assert np.max(np.abs(ag - ao)) <= 1e-12 * np.max(np.abs(ao))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_alm_chunk_boundaries(ctx, precision):
+    """Catalogs on one cell row, every point within r_max of every other: each
+    primary's candidates are exactly the n points, so n = 63, 64, 65, 127, 128, 129
+    and 192 put the end of the candidate walk one short of, on, and one past a
+    64-candidate chunk (and the prefetched chunk past the end)."""
+    _say("alm chunk boundaries %s" % precision)
+    rng = np.random.default_rng(11)
+    edges = np.array([0.1, 35.0, 70.0])
+    for n in [1, 2, 63, 64, 65, 127, 128, 129, 192]:
+        pos = np.zeros((n, 3))
+        pos[:, 0] = 0.5 + 0.3 * np.arange(n)
+        pos[:, 1:] = 0.3 + rng.uniform(-0.2, 0.2, (n, 2))
+        w = rng.uniform(0.5, 1.5, n)
+        prim = np.arange(n)
+        with encore.build_grid(ctx, pos, w, r_max=edges[-1]) as g:
+            ag = encore.debug_alm(ctx, g, 3, edges, prim, precision)
+        ao = oracle.alm(pos, w, 3, edges, primaries=prim)
+        if n == 1:
+            assert np.all(ag == 0) and np.all(ao == 0)
+            continue
+        bar = 1e-12 if precision == "fp64" else 1e-6
+        for i in range(n):
+            assert np.max(np.abs(ag[i] - ao[i])) <= bar * np.max(np.abs(ao[i])), (n, i)
+
+
 # ------------------------------------------------------------------ multiplets
 
 CASES = [
