@@ -330,9 +330,13 @@ int encore_npcf_noalloc(encore_ctx* ctx, const encore_grid* grid, int npcf, int 
  *         and one ENCORE_PREC_* (the precision of the coupling; the transforms are
  *         FP64).  ENCORE_NORMALIZE is EUNSUPPORTED.
  *  stream hipStream_t (NULL: the context's stream); synchronous.
- * Device memory: nbins * (lmax+1)(lmax+2)/2 + 1 complex FP64 fields of nmesh^3
- * cells (kept by the context for later calls) plus the transform's work area.
- * Timings: [1] the fields, transforms and products, [2] the coupling, [5] 0.
+ * Device memory: 2 nbins * (lmax+1)(lmax+2)/2 + 1 complex FP64 fields of nmesh^3
+ * cells (kept by the context for later calls) plus the transform's work area.  The
+ * transforms of the kernel fields Y_lm Theta^b depend on (nmesh, box, lmax, edges)
+ * alone: a call with the shape of the context's previous mesh call reuses them and
+ * transforms only delta and the products.
+ * Timings: [1] the fields, transforms and products, [2] the coupling, [5] 1 when
+ * the kernel-field transforms were reused, else 0.
  * Errors: EINVAL, ESIZE, ENOMEM, EDEVICE, EUNSUPPORTED.
  */
 int encore_npcf_mesh(encore_ctx* ctx, const double* delta, int nmesh, double box, int npcf, int lmax,

@@ -81,6 +81,7 @@ struct Exec {
     Buf alm, wprim, T, segs, splits, redp, queues, misc, zeta, bscale, prim, Tjob, almb;
     Buf cache, cmap;   // random splits: the data part of a~ and the row maps
     Buf mesh, meshd;   // gridded data: the coefficient fields and the transform of delta
+    Buf meshk;         // gridded data: transforms of the kernel fields (kept between calls)
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 // pool: null for plain hipMalloc workspaces, else a stream-ordered pool the
@@ -205,6 +206,9 @@ struct encore_ctx {
     std::mutex tab_mu;   // tables
     std::mutex mu;       // main exec, timings
     double timings[6] = {0, 0, 0, 0, 0, 0};
+    // gridded data: (nmesh, box, lmax, nbins, edges) whose kernel-field transforms
+    // main.meshk holds; empty when it holds none (guarded by mu)
+    std::vector<double> mesh_key;
     std::atomic<int> live_grids{0};
 };
 

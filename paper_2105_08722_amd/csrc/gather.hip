@@ -8,7 +8,8 @@
 //     hold a secondary of the group's shell [R_in, R_out) and clips the row's x
 //     extent to the shell's chord (minus the inner hole where the whole row is
 //     inside R_in), splitting at periodic images.  Because particles are sorted by
-//     cell with x fastest, each clipped piece is one contiguous particle range.
+//     cell with x fastest, each clipped piece is one contiguous particle range;
+//     pieces without a periodic image come first.
 //  2. Candidate test, 64 candidates per step: separation in FP64 exactly as the
 //     definition orders it (x_j - x_i, then the periodic image), r^2 =
 //     (dx*dx + dy*dy) + dz*dz without contraction, bin by comparing r^2 with the
@@ -19,8 +20,8 @@
 //     per-lane register accumulators of that bin (the bin is wave-uniform, so the
 //     register index is static).
 //  4. Reduce the 64 lanes' accumulators (FP32: cross-lane swaps and row
-//     rotations; FP64: through LDS), scale by the recurrence normalisation
-//     kappa_lm and write the complex coefficients.
+//     rotations, then staged in LDS; FP64: through LDS), scale by the recurrence
+//     normalisation kappa_lm and write the complex coefficients.
 //
 // Primaries are read from the segment's primary array (the catalog's own points,
 // or another grid's), candidates from its cell-sorted points; lanes past the last
@@ -301,9 +302,8 @@ __device__ __forceinline__ GatherSeg load_seg(const GatherSeg* segs, int s)
 // Exclusive wave scan by DPP: shifts by 1, 2, 4, 8 inside each row of 16 lanes
 // (lanes without a source add 0), then row 0's total into rows 1 and 3 and the
 // total of rows 0-1 into rows 2 and 3 (row broadcasts of lanes 15 and 31).
-__device__ __forceinline__ int wave_excl_scan(int v, int lane, int* total)
+__device__ __forceinline__ int wave_excl_scan(int v, int* total)
 {
-    (void)lane;
     int incl = v;
     incl += __builtin_amdgcn_update_dpp(0, incl, 0x111, 0xf, 0xf, false);   // row_shr:1
     incl += __builtin_amdgcn_update_dpp(0, incl, 0x112, 0xf, 0xf, false);   // row_shr:2
@@ -593,7 +593,7 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         int nc, ni;
         row_pieces_split(rg, g, nc, ni);
         int ntot = 0;   // both counts in one scan (at most 64 * kSegPerRow each)
-        const int sb = wave_excl_scan(nc | (ni << 16), lane, &ntot);
+        const int sb = wave_excl_scan(nc | (ni << 16), &ntot);
         const int nseg_c = ntot & 0xffff;
         const int nseg = nseg_c + (ntot >> 16);
         const int sbase_c = sb & 0xffff, sbase_i = nseg_c + (sb >> 16);
@@ -601,8 +601,8 @@ __global__ void __launch_bounds__(kWave * kWavesPerBlock, (gather_wpe<T, L, NBG,
         int nlc, nli;
         emit_pieces_split(rg, g, gcs, sbase_c, sbase_i, seg_dl, seg_flat, nlc, nli);
         int total_c = 0, total_i = 0;
-        int fc = wave_excl_scan(nlc, lane, &total_c);
-        int fi = wave_excl_scan(nli, lane, &total_i) + total_c;
+        int fc = wave_excl_scan(nlc, &total_c);
+        int fi = wave_excl_scan(nli, &total_i) + total_c;
         const int total = total_c + total_i;
         for (int q = 0; q < nc; ++q) {      // the lane's own slots only
             const int sl = sbase_c + q, ln = seg_flat[sl];

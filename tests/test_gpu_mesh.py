@@ -94,6 +94,35 @@ def test_mesh_dense_overdensity_field(ctx):
         _say("  dense %s: max e_L = %.2e" % (prec, e))
 
 
+def test_mesh_kernel_transforms_reused(ctx):
+    """A call with the previous call's shape reuses the transformed kernel fields:
+    the same field gives the same Z bit for bit, another field on that shape still
+    matches the oracle, and a change of edges rebuilds the transforms."""
+    import torch
+    n, L = 16, 16.0
+    edges = np.array([1.5, 2.6, 3.7, 5.1])
+    edges2 = np.array([1.5, 2.9, 4.3, 5.6])
+    d1 = synth.mesh_counts(*_catalog(700, n, L, 21), n, L)
+    d2 = synth.mesh_counts(*_catalog(500, n, L, 22), n, L)
+    t1, t2 = torch.from_numpy(d1).cuda(), torch.from_numpy(d2).cuda()
+    za = encore.npcf_mesh(ctx, t1, L, 4, 2, edges, precision="fp64")
+    assert ctx.last_timings()["pairs"] == 0        # first call of this shape
+    zb = encore.npcf_mesh(ctx, t1, L, 4, 2, edges, precision="fp64")
+    assert ctx.last_timings()["pairs"] == 1        # transforms reused
+    assert np.array_equal(za, zb)
+    zc = encore.npcf_mesh(ctx, t2, L, 4, 2, edges, precision="splitbf16")
+    assert ctx.last_timings()["pairs"] == 1        # the precision is not part of the shape
+    zo, zabs = omesh.mesh_zeta(d2, L, 4, 2, edges, return_abs=True)
+    bars.check(zc, zo, zabs, "splitbf16", "mesh, reused transforms")
+    zd = encore.npcf_mesh(ctx, t2, L, 4, 2, edges2, precision="fp64")
+    assert ctx.last_timings()["pairs"] == 0
+    zo, zabs = omesh.mesh_zeta(d2, L, 4, 2, edges2, return_abs=True)
+    bars.check(zd, zo, zabs, "fp64", "mesh, rebuilt transforms")
+    ze = encore.npcf_mesh(ctx, t1, L, 4, 2, edges, precision="fp64")
+    assert ctx.last_timings()["pairs"] == 0
+    assert np.array_equal(ze, za)
+
+
 def test_mesh_rejects_bad_arguments(ctx):
     import torch
     delta = torch.zeros((8, 8, 8), dtype=torch.float64, device="cuda")
