@@ -271,8 +271,8 @@ int encore_mfma_plan_stats(int npcf, int lmax, int nbins, uint32_t flags, int64_
  * Autotuner of the launch shapes: builds trial grids of the catalog (host arrays,
  * as encore_build_grid) with 8 cell shapes (cell side r_max/d on y and z,
  * r_max/(d*s) on x, where one cell row is a contiguous particle range; (d, s) =
- * (5, 16) -- the default without tuning --, (5, 8), (6, 16), (5, 24), (6, 8),
- * (4, 16), (5, 4), (4, 8)) and times,
+ * (5, 16) -- the default without tuning --, (5, 8), (6, 16), (6, 8), (8, 8),
+ * (8, 4), (5, 24), (4, 16)) and times,
  * for each, the gather + coupling of this job (as encore_npcf) over a sample of
  * n_sample primaries (16 runs of consecutive cell-sorted primaries spread over the
  * grid, so that neighbouring work items share cells as in a full pass), for every compiled

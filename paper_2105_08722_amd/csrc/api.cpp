@@ -688,7 +688,7 @@ int encore_autotune(encore_ctx* ctx, const double* pos, const double* w, int64_t
     const std::vector<int> nbgs = gather_nbg_options(lmax, gprec);
     // cell shapes tried: (y/z divisor of r_max, extra x subdivision); the default first
     constexpr double kTuneMargin = 0.98;
-    static const double kCells[][2] = {{5, 16}, {5, 8}, {6, 16}, {5, 24}, {6, 8}, {4, 16}, {5, 4}, {4, 8}};
+    static const double kCells[][2] = {{5, 16}, {5, 8}, {6, 16}, {6, 8}, {8, 8}, {8, 4}, {5, 24}, {4, 16}};
     // The sample: 16 runs of consecutive cell-sorted primaries spread over the grid,
     // so that neighbouring work items share cells as in a full pass (a scattered
     // sample would time cache misses that a full pass does not have).

@@ -299,7 +299,7 @@ def test_autotune_then_parity():
             rep = encore.autotune(c, pos, w_in, 4, 5, edges, box=L, n_data=2500, precision=prec,
                                   n_sample=1000)
             _say("  %s: %s" % (prec, rep))
-            assert (rep["cell_divisor"], rep["x_subdivision"]) in [(5, 16), (5, 8), (6, 16), (5, 24), (6, 8), (4, 16), (5, 4), (4, 8)]
+            assert (rep["cell_divisor"], rep["x_subdivision"]) in [(5, 16), (5, 8), (6, 16), (6, 8), (8, 8), (8, 4), (5, 24), (4, 16)]
             # compiled bins-per-item values at lmax 5: FP32 path (FP64 sums) {2, 1}, split-bf16 {2, 3}
             assert rep["bins_per_item"] in ((2, 1) if prec == "fp32" else (2, 3))
             assert 0 < rep["best_ms"] <= rep["default_ms"]
