@@ -371,7 +371,10 @@ size_t alm_row_bytes(const NpcfPlan& pl)
 
 int64_t cap_rows(const NpcfPlan& pl)
 {
-    int64_t cap = std::max<int64_t>(1, (int64_t)((size_t)2 << 30) / alm_row_bytes(pl));
+    // 8 GiB of coefficients (about 3% of the HBM) and at most 2^27 rows (row indices
+    // are 32-bit in the kernels): the benchmark-size jobs run in one slice
+    int64_t cap = std::max<int64_t>(1, (int64_t)((size_t)8 << 30) / alm_row_bytes(pl));
+    cap = std::min<int64_t>(cap, (int64_t)1 << 27);
     if (const char* e = getenv("ENCORE_MAX_SLICE_ROWS")) {   // smaller slices (tests of slicing)
         const long long v = atoll(e);
         if (v > 0) cap = std::min<int64_t>(cap, v);

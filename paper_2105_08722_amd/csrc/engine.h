@@ -129,7 +129,8 @@ int acc_len_host(const NpcfPlan& pl, int64_t* out);
 
 // bytes of a~ per primary row
 size_t alm_row_bytes(const NpcfPlan& pl);
-// rows of a~ held at once (2 GiB of coefficients; ENCORE_MAX_SLICE_ROWS may lower it)
+// rows of a~ held at once (8 GiB of coefficients, at most 2^27 rows;
+// ENCORE_MAX_SLICE_ROWS may lower it)
 int64_t cap_rows(const NpcfPlan& pl);
 // Coupling split length of a job: a function of the job alone, so that a job's
 // zeta does not depend on what shares a launch with it.
