@@ -331,7 +331,8 @@ int encore_npcf_noalloc(encore_ctx* ctx, const encore_grid* grid, int npcf, int 
  *         FP64).  ENCORE_NORMALIZE is EUNSUPPORTED.
  *  stream hipStream_t (NULL: the context's stream); synchronous.
  * Device memory: 2 nbins * (lmax+1)(lmax+2)/2 + 1 complex FP64 fields of nmesh^3
- * cells (kept by the context for later calls) plus the transform's work area.  The
+ * cells and the transform plans with their work areas, kept by the context for
+ * later calls (the plans per (nmesh, number of fields)).  The
  * transforms of the kernel fields Y_lm Theta^b depend on (nmesh, box, lmax, edges)
  * alone: a call with the shape of the context's previous mesh call reuses them and
  * transforms only delta and the products.

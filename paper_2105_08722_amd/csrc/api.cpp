@@ -280,6 +280,7 @@ int encore_destroy(encore_ctx* ctx)
     if (!ctx) return ENCORE_OK;
     if (ctx->live_grids > 0) return fail(ENCORE_EINVAL, "free every grid before destroying the context");
     (void)hipSetDevice(ctx->device);
+    mesh_release(ctx);
     exec_release(ctx->main);
     for (auto& kv : ctx->tables) {
         DevTables& d = kv.second;

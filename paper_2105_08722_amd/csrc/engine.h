@@ -210,6 +210,12 @@ struct encore_ctx {
     // gridded data: (nmesh, box, lmax, nbins, edges) whose kernel-field transforms
     // main.meshk holds; empty when it holds none (guarded by mu)
     std::vector<double> mesh_key;
+    // gridded data: the transform plans (hipfftHandle) of the last (nmesh, number of
+    // fields), with their work areas, kept for later calls (guarded by mu; freed by
+    // mesh_release): a batch of mesh_plan_nf fields and a single field
+    void* mesh_plan = nullptr;
+    void* mesh_plan1 = nullptr;
+    int mesh_plan_n = 0, mesh_plan_nf = 0;
     std::atomic<int> live_grids{0};
 };
 
@@ -252,6 +258,8 @@ int run_jobs(encore_ctx* ctx, Exec& x, const DevTables* tb, int64_t cap, const s
 
 // tuned bins per work item for a call (0: default); thread-safe
 int ctx_nbg(encore_ctx* ctx, const NpcfPlan& pl);
+// destroy the context's gridded-data transform plans
+void mesh_release(encore_ctx* ctx);
 void ctx_cells(encore_ctx* ctx, double* div, double* xsub);
 // thread-safe; the returned tables live as long as the context
 int get_tables(encore_ctx* ctx, int N, int lmax, bool allparity, int nbins, DevTables** out);

@@ -220,8 +220,7 @@ extern "C" int encore_npcf_mesh(encore_ctx* ctx, const double* delta, int nmesh,
     HIPTRY(hipSetDevice(ctx->device));
     Exec& x = ctx->main;
     const hipStream_t s = stream ? (hipStream_t)stream : x.s;
-    hipfftHandle plan = 0;
-    bool have_plan = false;
+    hipfftHandle plan = 0, plan1 = 0;
     DevTables* tb = nullptr;
     double2* F = nullptr;
     double2* D = nullptr;
@@ -268,13 +267,24 @@ extern "C" int encore_npcf_mesh(encore_ctx* ctx, const double* delta, int nmesh,
                 if (l & 1) (lm < 64 ? odd_lo : odd_hi) |= (uint64_t)1 << (lm & 63);
             }
         // batched transforms over the nf interleaved fields (element stride nf)
-        int dims[3] = {nmesh, nmesh, nmesh};
-        FFTTRY(hipfftCreate(&plan));
-        have_plan = true;
+        // the plans (and their work areas) of the last (nmesh, nf) are kept
+        if (!(ctx->mesh_plan && ctx->mesh_plan1 && ctx->mesh_plan_n == nmesh && ctx->mesh_plan_nf == nf)) {
+            mesh_release(ctx);
+            int dims[3] = {nmesh, nmesh, nmesh};
+            hipfftHandle p = 0, p1 = 0;
+            FFTTRY(hipfftCreate(&p));
+            ctx->mesh_plan = p;
+            size_t work = 0;
+            FFTTRY(hipfftMakePlanMany(p, 3, dims, dims, 1, (int)ncell, dims, 1, (int)ncell, HIPFFT_Z2Z, nf, &work));
+            FFTTRY(hipfftPlan3d(&p1, nmesh, nmesh, nmesh, HIPFFT_Z2Z));
+            ctx->mesh_plan1 = p1;
+            ctx->mesh_plan_n = nmesh;
+            ctx->mesh_plan_nf = nf;
+        }
+        plan = (hipfftHandle)ctx->mesh_plan;
+        plan1 = (hipfftHandle)ctx->mesh_plan1;
         FFTTRY(hipfftSetStream(plan, s));
-        size_t work = 0;
-        FFTTRY(hipfftMakePlanMany(plan, 3, dims, dims, 1, (int)ncell, dims, 1, (int)ncell, HIPFFT_Z2Z, nf, &work));
-        hipfftHandle plan1 = 0;
+        FFTTRY(hipfftSetStream(plan1, s));
         HIPTRY_DONE(hipEventRecord(x.ev[0], s));
         if (!warm) {
             hipLaunchKernelGGL(k_mesh_kernels, dim3(nblk(total)), dim3(kMeshBlock), 0, s, ka, K, total, ncell);
@@ -282,13 +292,7 @@ extern "C" int encore_npcf_mesh(encore_ctx* ctx, const double* delta, int nmesh,
         }
         hipLaunchKernelGGL(k_mesh_complex, dim3(nblk(ncell)), dim3(kMeshBlock), 0, s, delta, D, ncell);
         HIPTRY_DONE(hipGetLastError());
-        {
-            hipfftResult fr = hipfftPlan3d(&plan1, nmesh, nmesh, nmesh, HIPFFT_Z2Z);
-            if (fr == HIPFFT_SUCCESS) fr = hipfftSetStream(plan1, s);
-            if (fr == HIPFFT_SUCCESS) fr = hipfftExecZ2Z(plan1, (hipfftDoubleComplex*)D, (hipfftDoubleComplex*)D, HIPFFT_FORWARD);
-            if (plan1) (void)hipfftDestroy(plan1);
-            FFTTRY(fr);
-        }
+        FFTTRY(hipfftExecZ2Z(plan1, (hipfftDoubleComplex*)D, (hipfftDoubleComplex*)D, HIPFFT_FORWARD));
         if (!warm) FFTTRY(hipfftExecZ2Z(plan, (hipfftDoubleComplex*)K, (hipfftDoubleComplex*)K, HIPFFT_FORWARD));
         hipLaunchKernelGGL(k_mesh_product, dim3(nblk(total)), dim3(kMeshBlock), 0, s, D, K, F, total, ncell, nlm,
                            odd_lo, odd_hi, 1.0 / (double)ncell);
@@ -367,6 +371,15 @@ extern "C" int encore_npcf_mesh(encore_ctx* ctx, const double* delta, int nmesh,
         ctx->mesh_key = key;                   // meshk holds this shape's transforms
     }
 done:
-    if (have_plan) (void)hipfftDestroy(plan);
     return rc;
+}
+
+void encore::mesh_release(encore_ctx* ctx)
+{
+    if (ctx->mesh_plan) (void)hipfftDestroy((hipfftHandle)ctx->mesh_plan);
+    if (ctx->mesh_plan1) (void)hipfftDestroy((hipfftHandle)ctx->mesh_plan1);
+    ctx->mesh_plan = nullptr;
+    ctx->mesh_plan1 = nullptr;
+    ctx->mesh_plan_n = 0;
+    ctx->mesh_plan_nf = 0;
 }
