@@ -413,6 +413,9 @@ int encore_debug_alm(encore_ctx* ctx, const encore_grid* grid, int lmax, int nbi
  *  zeta          host FP64 [nout][nB]; B with R_0 = 0 or a singular matrix get NaN.
  *  coupling      NULL or host FP64 [nB][nlam][nlam]: M[B][L][L''].
  *  n_singular    NULL or the number of B without a solution.
+ * Device memory: the nB matrices of nlam^2 FP64 values (twice when coupling is
+ * requested), the Gaunt table and the multiplets, in grow-only workspaces kept by
+ * the context for later calls; the table is uploaded once per (npcf, lmax, parity).
  * Errors: EINVAL, ESIZE (a buffer too small; the message gives the size),
  * EUNSUPPORTED (more than 4096 multiplets, e.g. npcf = 6 at lmax 4), ENOMEM, EDEVICE.
  */

@@ -23,24 +23,13 @@ using namespace encore;
 
 namespace {
 
-struct DevBufs {
-    std::vector<void*> p;
-    ~DevBufs()
-    {
-        for (void* q : p)
-            if (q) (void)hipFree(q);
-    }
-    template <typename T>
-    int get(T** out, size_t n)
-    {
-        void* q = nullptr;
-        const hipError_t e = hipMalloc(&q, sizeof(T) * std::max<size_t>(n, 1));
-        if (e != hipSuccess) return fail(ENCORE_ENOMEM, "hipMalloc (edge correction workspace)");
-        p.push_back(q);
-        *out = (T*)q;
-        return ENCORE_OK;
-    }
-};
+// byte offset of the next 256-byte-aligned part of a packed workspace
+size_t carve(size_t& off, size_t bytes)
+{
+    const size_t at = off;
+    off += (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+    return at;
+}
 
 }  // namespace
 
@@ -83,29 +72,50 @@ extern "C" int encore_edge_correct(encore_ctx* ctx, int npcf, int lmax, int nbin
     std::lock_guard<std::mutex> lock(ctx->mu);
     HIPTRY(hipSetDevice(ctx->device));
     const hipStream_t s = ctx->main.s;
-    DevBufs d;
+    Exec& x = ctx->main;
     EdgeArgs a{};
     a.nlam = n;
     a.nB = (int)nB;
     a.nout = nout;
-    double *dn, *dr, *dv, *dA, *dx, *dz, *dM = nullptr;
-    int64_t* drs;
-    int32_t *dlp, *dk;
-    unsigned* dbad;
     int rc;
-    const size_t nt = gt.term_lp.size();
-    if ((rc = d.get(&dn, (size_t)n * nB)) || (rc = d.get(&dr, (size_t)n * nB)) ||
-        (rc = d.get(&drs, gt.row_start.size())) || (rc = d.get(&dlp, nt)) || (rc = d.get(&dv, nt)) ||
-        (rc = d.get(&dA, (size_t)nB * n * n)) || (rc = d.get(&dx, (size_t)nB * n)) ||
-        (rc = d.get(&dk, (size_t)nout)) || (rc = d.get(&dz, (size_t)nout * nB)) || (rc = d.get(&dbad, 1)))
-        return rc;
-    if (coupling && (rc = d.get(&dM, (size_t)nB * n * n))) return rc;
+    // Workspaces: the context's grow-only buffers, kept for later calls; the Gaunt
+    // table is uploaded once per (npcf, lmax, parity) while its buffer stays put.
+    const size_t nt = gt.term_lp.size(), nrs = gt.row_start.size();
+    size_t go = 0;
+    const size_t o_rs = carve(go, sizeof(int64_t) * nrs), o_lp = carve(go, sizeof(int32_t) * nt),
+                 o_v = carve(go, sizeof(double) * nt);
+    const size_t gt_n0 = x.egt.n;
+    if ((rc = ensure(x.egt, go))) return rc;
+    const auto gt_key = std::make_tuple(npcf, lmax, allp);
+    const bool gt_fresh = ctx->edge_gt_key != gt_key || x.egt.n != gt_n0;
+    size_t io = 0;
+    const size_t o_n = carve(io, sizeof(double) * n * nB), o_r = carve(io, sizeof(double) * n * nB),
+                 o_x = carve(io, sizeof(double) * nB * n), o_k = carve(io, sizeof(int32_t) * nout),
+                 o_z = carve(io, sizeof(double) * nout * nB), o_bad = carve(io, sizeof(unsigned));
+    if ((rc = ensure(x.eio, io)) || (rc = ensure(x.eA, sizeof(double) * nB * n * n))) return rc;
+    if (coupling && (rc = ensure(x.eM, sizeof(double) * nB * n * n))) return rc;
+    char* gb = (char*)x.egt.p;
+    char* ib = (char*)x.eio.p;
+    int64_t* drs = (int64_t*)(gb + o_rs);
+    int32_t* dlp = (int32_t*)(gb + o_lp);
+    double* dv = (double*)(gb + o_v);
+    double* dn = (double*)(ib + o_n);
+    double* dr = (double*)(ib + o_r);
+    double* dx = (double*)(ib + o_x);
+    int32_t* dk = (int32_t*)(ib + o_k);
+    double* dz = (double*)(ib + o_z);
+    unsigned* dbad = (unsigned*)(ib + o_bad);
+    double* dA = (double*)x.eA.p;
+    double* dM = coupling ? (double*)x.eM.p : nullptr;
     HIPTRY(hipMemcpyAsync(dn, nmult, sizeof(double) * n * nB, hipMemcpyHostToDevice, s));
     HIPTRY(hipMemcpyAsync(dr, rmult, sizeof(double) * n * nB, hipMemcpyHostToDevice, s));
-    HIPTRY(hipMemcpyAsync(drs, gt.row_start.data(), sizeof(int64_t) * gt.row_start.size(), hipMemcpyHostToDevice, s));
-    if (nt) {
-        HIPTRY(hipMemcpyAsync(dlp, gt.term_lp.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice, s));
-        HIPTRY(hipMemcpyAsync(dv, gt.term_val.data(), sizeof(double) * nt, hipMemcpyHostToDevice, s));
+    if (gt_fresh) {
+        ctx->edge_gt_key = std::make_tuple(-1, -1, false);
+        HIPTRY(hipMemcpyAsync(drs, gt.row_start.data(), sizeof(int64_t) * nrs, hipMemcpyHostToDevice, s));
+        if (nt) {
+            HIPTRY(hipMemcpyAsync(dlp, gt.term_lp.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice, s));
+            HIPTRY(hipMemcpyAsync(dv, gt.term_val.data(), sizeof(double) * nt, hipMemcpyHostToDevice, s));
+        }
     }
     if (nout) HIPTRY(hipMemcpyAsync(dk, keep.data(), sizeof(int32_t) * nout, hipMemcpyHostToDevice, s));
     HIPTRY((hipError_t)launch_fill_u32(dbad, 1, 0u, s));
@@ -128,6 +138,7 @@ extern "C" int encore_edge_correct(encore_ctx* ctx, int npcf, int lmax, int nbin
     if (coupling) HIPTRY(hipMemcpyAsync(coupling, dM, sizeof(double) * nB * n * n, hipMemcpyDeviceToHost, s));
     HIPTRY(hipMemcpyAsync(&nbad, dbad, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     HIPTRY(hipStreamSynchronize(s));
+    ctx->edge_gt_key = gt_key;   // the upload (if any) has completed
     float ms = 0.f;
     for (double& t : ctx->timings) t = 0.0;
     if (hipEventElapsedTime(&ms, ctx->main.ev[0], ctx->main.ev[1]) == hipSuccess) ctx->timings[0] = ms;

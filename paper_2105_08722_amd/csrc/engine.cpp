@@ -69,7 +69,7 @@ static Buf* exec_bufs(Exec& x, int i)
 {
     Buf* all[] = {&x.alm, &x.wprim, &x.T, &x.segs, &x.splits, &x.redp, &x.queues,
                   &x.misc, &x.zeta, &x.bscale, &x.prim, &x.Tjob, &x.almb, &x.cache, &x.cmap,
-                  &x.mesh, &x.meshd, &x.meshk};
+                  &x.mesh, &x.meshd, &x.meshk, &x.egt, &x.eA, &x.eM, &x.eio};
     return i < (int)(sizeof(all) / sizeof(all[0])) ? all[i] : nullptr;
 }
 

@@ -82,6 +82,7 @@ struct Exec {
     Buf cache, cmap;   // random splits: the data part of a~ and the row maps
     Buf mesh, meshd;   // gridded data: the coefficient fields and the transform of delta
     Buf meshk;         // gridded data: transforms of the kernel fields (kept between calls)
+    Buf egt, eA, eM, eio;   // edge correction: Gaunt table, matrices, matrix copies, small arrays
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 // pool: null for plain hipMalloc workspaces, else a stream-ordered pool the
@@ -216,6 +217,9 @@ struct encore_ctx {
     void* mesh_plan = nullptr;
     void* mesh_plan1 = nullptr;
     int mesh_plan_n = 0, mesh_plan_nf = 0;
+    // edge correction: (npcf, lmax, all parities) of the Gaunt table held in
+    // main.egt; (-1, ...) when it holds none (guarded by mu)
+    std::tuple<int, int, bool> edge_gt_key{-1, -1, false};
     std::atomic<int> live_grids{0};
 };
 
