@@ -239,7 +239,8 @@ bool use_gemm_coupling(int N)
 {
     // Measured on the survey wedge (200k primaries, 10 bins): 5PCF lmax 4 31 ms
     // against 80 ms for the per-wave jobs, 6PCF lmax 3 132 ms against 458 ms; the
-    // 4PCF lmax 5 (800k primaries) 44 ms against 14.5 ms: its blocks are too thin.
+    // 4PCF lmax 5 (800k primaries, 2 + 1 factors) 22 ms against 14.4 ms: its blocks
+    // are too thin.
     return N >= 5;
 }
 
