@@ -19,6 +19,7 @@
 // transposed through LDS into the coupling's rows [cell][b][lm].
 #include <hip/hip_runtime.h>
 #include <hipfft/hipfft.h>
+#include <type_traits>
 
 #include <algorithm>
 #include <cmath>
@@ -139,9 +140,13 @@ __global__ void __launch_bounds__(kMeshBlock) k_mesh_rows(const double2* __restr
         const int64_t r = r0 + ri;
         const int f = f0 + fi;
         if (r < rows && f < nf) {
+            // one 8- or 16-byte store per complex value
+            using V2 = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
             const double2 v = tile[fi][ri];
-            alm[2 * (r * nf + f)] = (T)v.x;
-            alm[2 * (r * nf + f) + 1] = (T)v.y;
+            V2 o;
+            o.x = (T)v.x;
+            o.y = (T)v.y;
+            reinterpret_cast<V2*>(alm)[r * nf + f] = o;
         }
     }
     if (blockIdx.y == 0)
